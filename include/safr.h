@@ -1,0 +1,187 @@
+/*
+ * safr.h - C ABI of the MI355X (gfx950) SAFR reconstruction library.
+ *
+ * SAFR (Weissinger, Hubmer, Stadler, Ramlau; arXiv 2510.19542) solves the
+ * atmospheric tomography problem of multi-conjugate adaptive optics with one
+ * precomputed per-frequency regularised inverse:
+ *
+ *   soft real time (Alg. 2): for every spatial frequency n of the M x M grid,
+ *     A_n[g, l] = s_l(n) exp(i pi h_l (n_x ax_g + n_y ay_g) / (c_l T))     (Sec. 3.1)
+ *     s_l(n)    = gamma_l^(1/2) / c_l (1 + pi^2 |n|^2 / (c_l T)^2)^(-beta/2)
+ *     A_n = U S V^H,  B_n[l, g] = s_l(n) sum_r V[l, r] g(S_rr) conj(U[g, r]),
+ *     Tikhonov filter g(s) = s / (s^2 + alpha)                              (Sec. 3.1)
+ *   hard real time (Alg. 1): d_g = fft2(Psi_g) for the J guide-star wavefronts,
+ *     b_l(n) = sum_g B_n[l, g] d_g(n), Phi_l = ifft2(b_l) for the L layers.
+ *
+ * Conventions (identical to the CPU reference used by the tests):
+ *   - T = M * pitch / 2; layer l's output grid has spacing c_l * pitch and its
+ *     index M/2 sits at x = 0 (Sec. 3.2 grids); c_l = 1 (natural stars) or
+ *     1 - h_l / h_lgs (laser stars, Sec. 2);
+ *   - the n x n pupil data is placed at rows/columns p0 .. p0+n-1 of the M x M
+ *     zero grid, p0 = (M - n + 1) / 2 (extension by zero, Sec. 2);
+ *   - first array index <-> x <-> ax; arrays are row-major;
+ *   - even M: the Nyquist row and column carry B = 0 (symmetric truncation with
+ *     m = M/2 - 1 of the frequency index n(j), Sec. 3.2);
+ *   - mixed asterisms (both kinds present) use split tomography (Sec. 3.3):
+ *     laser-star data has its least-squares tip/tilt plane over the pupil
+ *     removed and is reconstructed with alpha; natural-star data is reduced to
+ *     that plane and reconstructed with alpha_tt; the natural-star layers are
+ *     resampled bilinearly (periodic) onto the laser layer grids and added.
+ *
+ * Memory: every data pointer passed to a reconstruct call is device memory
+ * owned by the caller.  A plan owns B and a single-frame workspace.  Calls on a
+ * plan are stream ordered on the stream given; reconstruct calls neither
+ * allocate nor synchronise.  A plan may be used from one thread at a time.
+ * No C++ exception crosses this interface; errors are returned as negative
+ * safr_status values and described by safr_last_error() (thread local).
+ */
+#ifndef SAFR_H
+#define SAFR_H
+
+#include <stddef.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SAFR_OK = 0,
+    SAFR_ERR_ARG = -1,          /* null pointer, bad size, bad enum, alpha/beta < 0 */
+    SAFR_ERR_GEOMETRY = -2,     /* heights not ascending, h >= h_lgs for laser stars, weights <= 0 */
+    SAFR_ERR_DOMAIN = -3,       /* a shifted, scaled aperture leaves c_l Omega_T (Sec. 2) */
+    SAFR_ERR_UNSUPPORTED = -4,  /* M not in {32, 64, 128, 256}, n > M, J or L beyond limits */
+    SAFR_ERR_NUMERIC = -5,      /* non-finite value in the precomputed operator */
+    SAFR_ERR_DEVICE = -6,       /* a HIP runtime call failed */
+    SAFR_ERR_STATE = -7         /* workspace too small for the requested frame count */
+} safr_status;
+
+enum { SAFR_NGS = 0, SAFR_LGS = 1 };
+enum { SAFR_FILTER_TIKHONOV = 0, SAFR_FILTER_MLP = 1 };
+enum { SAFR_FP32 = 0, SAFR_BF16X3 = 1 };
+
+#define SAFR_MAX_STARS_PER_GROUP 16
+#define SAFR_MAX_LAYERS 16
+#define SAFR_MLP_PARAMS 8705
+
+/* One guide star: direction (ax, ay) in radians (Sec. 2) and its kind. */
+typedef struct {
+    double ax, ay;
+    int kind;                       /* SAFR_NGS or SAFR_LGS */
+} safr_star;
+
+/* Problem geometry (Sec. 2, Sec. 3.2).  All pointers are host memory, read
+ * during safr_precompute only. */
+typedef struct {
+    int n;                          /* pupil grid n x n, 1 <= n <= M */
+    int M;                          /* periodic FFT grid M x M */
+    double pitch;                   /* grid spacing [m]; T = M * pitch / 2 */
+    int J;                          /* number of guide stars */
+    const safr_star* stars;         /* J stars */
+    double h_lgs;                   /* sodium layer height [m] (laser stars) */
+    const unsigned char* pupil;     /* n*n mask, row-major, nonzero = inside; NULL = all inside */
+    double beta;                    /* Sobolev smoothness, >= 0 */
+    double alpha_tt;                /* Tikhonov parameter of the natural-star group when mixed */
+    int filter;                     /* SAFR_FILTER_TIKHONOV or SAFR_FILTER_MLP */
+    const float* mlp;               /* SAFR_MLP_PARAMS network parameters (learned filter only) */
+    double noise;                   /* relative noise level, a network input (learned filter only) */
+} safr_geometry;
+
+typedef struct safr_plan safr_plan;
+
+/* Read-only description of a plan (filled by safr_plan_info). */
+typedef struct {
+    int n, M, J, L;
+    int groups;                     /* 1, or 2 for a mixed asterism (group 0 = laser, 1 = natural) */
+    int group_size[2];              /* stars per group */
+    int group_kind[2];
+    double c[SAFR_MAX_LAYERS];      /* output-grid cone coefficients c_l */
+    double layer_pitch[SAFR_MAX_LAYERS];   /* c_l * pitch [m] */
+    size_t B_complex_per_group[2];  /* stored half-spectrum entries: (M/2+1) * M * L * G */
+} safr_plan_desc;
+
+/*
+ * Soft-real-time precomputation (Alg. 2, Sec. 3.1): validates the geometry,
+ * builds A_n for the half spectrum on the GPU in FP64, takes its SVD (one-sided
+ * Jacobi), applies the filter (Tikhonov with alpha, or the learned network of
+ * geo->mlp evaluated in BF16 on the features (|n|/(2T), log10 s_r, log10 noise,
+ * sum_l gamma_l |V_lr|^2)), and stores B in FP64 (for export), FP32 and BF16
+ * hi/lo.  heights[L] [m] ascending, weights[L] > 0 (normalised internally),
+ * alpha >= 0 (0 = pseudo-inverse with rank tolerance max(G,L) eps s_1).
+ * Allocates device memory and synchronises `stream`.  On success *out owns
+ * the plan; release it with safr_destroy.
+ */
+safr_status safr_precompute(const safr_geometry* geo, int L, const double* heights,
+                            const double* weights, double alpha, safr_plan** out,
+                            hipStream_t stream);
+
+/*
+ * Hard-real-time reconstruction of one frame (Alg. 1): wavefronts [J][n][n]
+ * FP32 device (values outside the pupil are ignored) -> layers [L][M][M] FP32
+ * device, layer l on its own grid.  Uses the plan's internal workspace.
+ */
+safr_status safr_reconstruct(safr_plan* p, const float* wavefronts, float* layers,
+                             hipStream_t stream);
+
+/*
+ * Batched reconstruction of `frames` independent frames: wavefronts
+ * [frames][J][n][n] -> layers [frames][L][M][M].  precision SAFR_FP32 applies B
+ * in FP32; SAFR_BF16X3 applies it on BF16 matrix cores with FP32 accumulation
+ * and the split correction B_hi D_hi + B_hi D_lo + B_lo D_hi.  Needs a
+ * workspace of safr_workspace_size(p, frames, precision) bytes (internal for
+ * frames == 1, else bound with safr_set_workspace) or returns SAFR_ERR_STATE.
+ * The launch sequence is captured once per (frames, pointers, precision,
+ * stream) into a HIP graph and replayed on later identical calls.
+ */
+safr_status safr_reconstruct_batched(safr_plan* p, int frames, const float* wavefronts,
+                                     float* layers, int precision, hipStream_t stream);
+
+/* Device workspace bytes needed for `frames` frames. */
+safr_status safr_workspace_size(const safr_plan* p, int frames, int precision, size_t* bytes);
+
+/* Binds caller-owned device memory (>= 256-byte aligned) as the workspace
+ * (NULL restores the internal single-frame workspace).  Not owned by the plan. */
+safr_status safr_set_workspace(safr_plan* p, void* device_ptr, size_t bytes);
+
+safr_status safr_plan_info(const safr_plan* p, safr_plan_desc* out);
+
+/*
+ * Copies the FP64 B of one group to host memory as interleaved (re, im) doubles
+ * in the layout [k = 0..M/2][j = 0..M-1][l][g] (k: second frequency index,
+ * half spectrum; j: first frequency index).  `count` = number of doubles the
+ * buffer holds; must be >= 2 * B_complex_per_group[group].  Synchronises.
+ */
+safr_status safr_export_B(const safr_plan* p, int group, double* host, size_t count);
+
+/* Tuning and execution options of a plan (not needed for correct results):
+ *   SAFR_OPT_GRAPH       1 = capture the launch sequence in a HIP graph and replay it
+ *                        (non-default streams only), 0 = launch directly (default);
+ *   SAFR_OPT_ROW_TEAMS   transform teams per block of the row pass (2 rows per team);
+ *   SAFR_OPT_OUT_ROWS    output rows per block of the output pass (>= 2);
+ *   SAFR_OPT_MFMA_FRAMES frames per block of the BF16 apply (16);
+ *   SAFR_OPT_COL_FRAMES  frames per block of the FP32 column pass (B stays in registers
+ *                        across them; 1 = one frame per block);
+ *   SAFR_OPT_COL_PREFETCH 1 = the column pass keeps each block's B in registers when
+ *                        L * G <= 64 (default), 0 = it reads B inside the apply loop. */
+enum { SAFR_OPT_GRAPH = 0, SAFR_OPT_ROW_TEAMS = 1, SAFR_OPT_OUT_ROWS = 2, SAFR_OPT_MFMA_FRAMES = 3,
+       SAFR_OPT_COL_FRAMES = 4, SAFR_OPT_COL_PREFETCH = 5 };
+safr_status safr_set_option(safr_plan* p, int option, int value);
+
+/* Measures the three kernels of the hard-real-time step (row pass, column pass
+ * with the apply, output pass) with HIP events recorded on `stream` around each
+ * launch, over `iters` synchronised repetitions of a batched call; writes the
+ * average milliseconds of each to ms[0..2].  Same buffers and workspace rules as
+ * safr_reconstruct_batched. */
+safr_status safr_time_stages(safr_plan* p, int frames, const float* wavefronts, float* layers,
+                             int precision, int iters, hipStream_t stream, double* ms);
+
+/* Releases the plan and its device memory (NULL is a no-op). */
+void safr_destroy(safr_plan* p);
+
+/* Description of the last error on the calling thread (never NULL). */
+const char* safr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SAFR_H */

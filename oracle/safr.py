@@ -132,9 +132,15 @@ def tomography_matrix(nx, ny, angles, heights, c, gamma, T: float, beta: float) 
 # --------------------------------------------------------------------------------------
 
 def _jacobi_columns(X: np.ndarray, tol: float = 1e-15, max_sweeps: int = 100):
-    """Orthogonalise the columns of X (..., m, n) by plane rotations; returns (X V, V)."""
+    """Orthogonalise the columns of X (..., m, n) by plane rotations; returns (X V, V).
+
+    A pair is rotated while its inner product exceeds tol * |x_p| |x_q| and is not
+    negligible against the whole matrix (1e-30 |X|_F^2), so that columns of a
+    rank-deficient X that are zero up to rounding are left alone.
+    """
     X = np.array(X, dtype=np.complex128, copy=True)
     n = X.shape[-1]
+    floor = 1e-30 * np.sum(np.abs(X) ** 2, axis=(-2, -1))
     V = np.broadcast_to(np.eye(n, dtype=np.complex128), X.shape[:-2] + (n, n)).copy()
     for _ in range(max_sweeps):
         rotated = False
@@ -146,7 +152,7 @@ def _jacobi_columns(X: np.ndarray, tol: float = 1e-15, max_sweeps: int = 100):
                 b = np.sum(np.abs(xq) ** 2, axis=-1)
                 cpq = np.sum(np.conj(xp) * xq, axis=-1)
                 mag = np.abs(cpq)
-                act = mag > tol * np.sqrt(a * b)
+                act = (mag > tol * np.sqrt(a * b)) & (mag > floor)
                 if not np.any(act):
                     continue
                 rotated = True

@@ -1,0 +1,705 @@
+// Host side of the SAFR C ABI: validation of the geometry (Sec. 2), the
+// soft-real-time precomputation (Alg. 2) driven on the GPU, and the dispatch of
+// the hard-real-time kernels (Alg. 1).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "safr_internal.h"
+
+using namespace safr;
+
+namespace {
+
+thread_local std::string g_last_error = "no error";
+
+safr_status fail(safr_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                       \
+    do {                                                                                    \
+        hipError_t _e = (expr);                                                             \
+        if (_e != hipSuccess)                                                               \
+            return fail(SAFR_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(_e));  \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool supported_M(int M) { return M == 32 || M == 64 || M == 128 || M == 256; }
+
+int team_size(int M) { return M == 256 ? 16 : (M == 32 ? 4 : 8); }
+
+// LDS bytes of one output-pass block (must match the launcher in k_out.hip).
+size_t out_lds_bytes(int M, int rows, bool mixed) {
+    const int T = team_size(M);
+    const int N1 = M == 32 ? 8 : (M == 64 ? 8 : 16), N2 = M / N1;
+    const int trows = mixed ? 2 * rows + 2 : rows;
+    return (size_t)(256 / T) * N1 * (N2 + 1) * 8 + (size_t)trows * (M / 2 + 1) * 8 + (size_t)trows * M * 4;
+}
+constexpr size_t kMaxLds = 160 * 1024;
+
+}  // namespace
+
+struct safr_plan {
+    int n = 0, M = 0, J = 0, L = 0, Kh = 0;
+    int ngroups = 0, mixed = 0;
+    double pitch = 0.0, T = 0.0;
+    int gsize[2] = {0, 0}, gkind[2] = {0, 0};
+    int gstar[2][kMaxG] = {};
+    double galpha[2] = {0.0, 0.0};
+    double c_out[kMaxL] = {};
+    size_t bcount[2] = {0, 0};      // complex entries per group (FP64 export layout)
+    size_t boff[2] = {0, 0};        // group offsets in B64
+    size_t boff32[2] = {0, 0};      // group offsets in B32 (column-block layout, zero padded)
+    float tt_b[3] = {0, 0, 0}, tt_c[3] = {0, 0, 0};
+    int p0 = 0;
+    // device memory owned by the plan
+    double2* B64 = nullptr;
+    float2* B32 = nullptr;
+    uint16_t* Apack = nullptr;
+    size_t apack_off[2] = {0, 0};
+    int mf_lt[2] = {0, 0}, mf_ntile[2] = {0, 0}, mf_ppm[2] = {0, 0};
+    float2* tw = nullptr;
+    float2* Xh = nullptr;           // DFT2 of x * pupil (tip/tilt plane transforms), [Kh][M]
+    float2* Yh = nullptr;
+    unsigned char* pupil = nullptr;
+    int* tt_mode = nullptr;
+    void* ws_own = nullptr;
+    size_t ws_own_bytes = 0;
+    void* ws_user = nullptr;
+    size_t ws_user_bytes = 0;
+    // tuning
+    int row_teams = 0, out_rows = 0, mfma_frames = 16, col_frames = 1, col_prefetch = 1;
+    int use_graph = 0;
+    // graph cache
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    int g_frames = 0, g_prec = 0;
+    const float* g_wf = nullptr;
+    float* g_out = nullptr;
+    hipStream_t g_stream = nullptr;
+};
+
+namespace {
+
+// workspace: row spectra R, layer column spectra C, partial moments (sized for the smallest row blocks)
+size_t ws_r(const safr_plan* p, int frames) { return align256((size_t)frames * p->J * p->Kh * p->n * sizeof(float2)); }
+size_t ws_c(const safr_plan* p, int frames) {
+    return align256((size_t)frames * p->ngroups * p->L * p->Kh * p->M * sizeof(float2));
+}
+size_t ws_m(const safr_plan* p, int frames) {
+    return align256((size_t)frames * p->J * ((p->n + 1) / 2) * 4 * sizeof(float));
+}
+size_t ws_bytes(const safr_plan* p, int frames) { return ws_r(p, frames) + ws_c(p, frames) + ws_m(p, frames); }
+
+void free_plan(safr_plan* p) {
+    if (!p) return;
+    if (p->gexec) hipGraphExecDestroy(p->gexec);
+    if (p->graph) hipGraphDestroy(p->graph);
+    hipFree(p->B64);
+    hipFree(p->B32);
+    hipFree(p->Apack);
+    hipFree(p->tw);
+    hipFree(p->Xh);
+    hipFree(p->Yh);
+    hipFree(p->pupil);
+    hipFree(p->tt_mode);
+    hipFree(p->ws_own);
+    delete p;
+}
+
+// Inverse of the 3 x 3 normal matrix of the least-squares fit of [1, x, y] over the pupil.
+bool tt_inverse(const std::vector<unsigned char>& pup, int n, double inv[9]) {
+    double N[9] = {0};
+    const double half = 0.5 * (n - 1);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            if (!pup[(size_t)i * n + j]) continue;
+            const double v[3] = {1.0, i - half, j - half};
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) N[3 * a + b] += v[a] * v[b];
+        }
+    const double det = N[0] * (N[4] * N[8] - N[5] * N[7]) - N[1] * (N[3] * N[8] - N[5] * N[6]) +
+                       N[2] * (N[3] * N[7] - N[4] * N[6]);
+    if (!(std::fabs(det) > 1e-12)) return false;
+    inv[0] = (N[4] * N[8] - N[5] * N[7]) / det;
+    inv[1] = (N[2] * N[7] - N[1] * N[8]) / det;
+    inv[2] = (N[1] * N[5] - N[2] * N[4]) / det;
+    inv[3] = (N[5] * N[6] - N[3] * N[8]) / det;
+    inv[4] = (N[0] * N[8] - N[2] * N[6]) / det;
+    inv[5] = (N[2] * N[3] - N[0] * N[5]) / det;
+    inv[6] = (N[3] * N[7] - N[4] * N[6]) / det;
+    inv[7] = (N[1] * N[6] - N[0] * N[7]) / det;
+    inv[8] = (N[0] * N[4] - N[1] * N[3]) / det;
+    return true;
+}
+
+// DFT2 (FP64, direct) of x * pupil and y * pupil zero-extended at offset p0, half spectrum [k][j].
+void tt_transforms(const std::vector<unsigned char>& pup, int n, int M, int p0, std::vector<float2>& X,
+                   std::vector<float2>& Y) {
+    const int Kh = M / 2 + 1;
+    const double half = 0.5 * (n - 1);
+    auto w = [M](long e) {
+        const double ang = -2.0 * M_PI * (double)(e % M) / M;
+        return std::make_pair(std::cos(ang), std::sin(ang));
+    };
+    // row sums at each k: rx = sum_q mask e^{-2 pi i k (p0+q)/M}, ry = sum_q (q - half) mask e^{...}
+    std::vector<double> rxr((size_t)n * Kh), rxi((size_t)n * Kh), ryr((size_t)n * Kh), ryi((size_t)n * Kh);
+    for (int p = 0; p < n; ++p)
+        for (int k = 0; k < Kh; ++k) {
+            double ar = 0, ai = 0, br = 0, bi = 0;
+            for (int q = 0; q < n; ++q) {
+                if (!pup[(size_t)p * n + q]) continue;
+                const auto e = w((long)k * (p0 + q));
+                ar += e.first;
+                ai += e.second;
+                br += (q - half) * e.first;
+                bi += (q - half) * e.second;
+            }
+            rxr[(size_t)p * Kh + k] = ar;
+            rxi[(size_t)p * Kh + k] = ai;
+            ryr[(size_t)p * Kh + k] = br;
+            ryi[(size_t)p * Kh + k] = bi;
+        }
+    X.assign((size_t)Kh * M, make_float2(0.f, 0.f));
+    Y.assign((size_t)Kh * M, make_float2(0.f, 0.f));
+    for (int k = 0; k < Kh; ++k)
+        for (int j = 0; j < M; ++j) {
+            double xr = 0, xi = 0, yr = 0, yi = 0;
+            for (int p = 0; p < n; ++p) {
+                const auto e = w((long)j * (p0 + p));
+                const double cr = rxr[(size_t)p * Kh + k], ci = rxi[(size_t)p * Kh + k];
+                const double dr = ryr[(size_t)p * Kh + k], di = ryi[(size_t)p * Kh + k];
+                const double x = p - half;
+                xr += x * (e.first * cr - e.second * ci);
+                xi += x * (e.first * ci + e.second * cr);
+                yr += e.first * dr - e.second * di;
+                yi += e.first * di + e.second * dr;
+            }
+            X[(size_t)k * M + j] = make_float2((float)xr, (float)xi);
+            Y[(size_t)k * M + j] = make_float2((float)yr, (float)yi);
+        }
+}
+
+safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, int precision,
+                       void* ws, hipStream_t s, hipEvent_t* ev = nullptr);
+
+}  // namespace
+
+extern "C" {
+
+const char* safr_last_error(void) { return g_last_error.c_str(); }
+
+safr_status safr_precompute(const safr_geometry* geo, int L, const double* heights, const double* weights,
+                            double alpha, safr_plan** out, hipStream_t stream) {
+    if (!out) return fail(SAFR_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!geo || !heights || !weights) return fail(SAFR_ERR_ARG, "geometry, heights or weights is NULL");
+    if (!geo->stars || geo->J < 1) return fail(SAFR_ERR_ARG, "need J >= 1 stars");
+    if (L < 1) return fail(SAFR_ERR_ARG, "need L >= 1 layers");
+    if (L > kMaxL) return fail(SAFR_ERR_UNSUPPORTED, "L = %d exceeds %d", L, kMaxL);
+    const int M = geo->M, n = geo->n, J = geo->J;
+    if (!supported_M(M)) return fail(SAFR_ERR_UNSUPPORTED, "M = %d not in {32, 64, 128, 256}", M);
+    if (n < 1) return fail(SAFR_ERR_ARG, "n = %d < 1", n);
+    if (n > M) return fail(SAFR_ERR_UNSUPPORTED, "n = %d exceeds M = %d", n, M);
+    if (!(geo->pitch > 0.0) || !std::isfinite(geo->pitch)) return fail(SAFR_ERR_ARG, "pitch must be > 0");
+    if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(SAFR_ERR_ARG, "alpha must be >= 0");
+    if (!(geo->beta >= 0.0) || !std::isfinite(geo->beta)) return fail(SAFR_ERR_ARG, "beta must be >= 0");
+    if (!(geo->alpha_tt >= 0.0) || !std::isfinite(geo->alpha_tt))
+        return fail(SAFR_ERR_ARG, "alpha_tt must be >= 0");
+    if (geo->filter != SAFR_FILTER_TIKHONOV && geo->filter != SAFR_FILTER_MLP)
+        return fail(SAFR_ERR_ARG, "unknown filter %d", geo->filter);
+    if (geo->filter == SAFR_FILTER_MLP && (!geo->mlp || !(geo->noise > 0.0)))
+        return fail(SAFR_ERR_ARG, "learned filter needs parameters and noise > 0");
+    int nl = 0, nn = 0;
+    for (int g = 0; g < J; ++g) {
+        const safr_star& st = geo->stars[g];
+        if (st.kind != SAFR_NGS && st.kind != SAFR_LGS) return fail(SAFR_ERR_ARG, "star %d: bad kind", g);
+        if (!std::isfinite(st.ax) || !std::isfinite(st.ay)) return fail(SAFR_ERR_ARG, "star %d: bad angle", g);
+        (st.kind == SAFR_LGS ? nl : nn)++;
+    }
+    double wsum = 0.0;
+    for (int l = 0; l < L; ++l) {
+        if (!std::isfinite(heights[l]) || heights[l] < 0.0)
+            return fail(SAFR_ERR_GEOMETRY, "height %d must be finite and >= 0", l);
+        if (l > 0 && !(heights[l] > heights[l - 1]))
+            return fail(SAFR_ERR_GEOMETRY, "heights must be strictly ascending");
+        if (!(weights[l] > 0.0) || !std::isfinite(weights[l]))
+            return fail(SAFR_ERR_GEOMETRY, "weight %d must be > 0", l);
+        wsum += weights[l];
+    }
+    if (nl > 0) {
+        if (!(geo->h_lgs > 0.0)) return fail(SAFR_ERR_GEOMETRY, "h_lgs must be > 0 with laser stars");
+        if (!(heights[L - 1] < geo->h_lgs)) return fail(SAFR_ERR_GEOMETRY, "layers must lie below h_lgs");
+    }
+    if (nl > kMaxG || nn > kMaxG) return fail(SAFR_ERR_UNSUPPORTED, "more than %d stars of one kind", kMaxG);
+
+    safr_plan* p = new safr_plan();
+    p->n = n;
+    p->M = M;
+    p->J = J;
+    p->L = L;
+    p->Kh = M / 2 + 1;
+    p->pitch = geo->pitch;
+    p->T = M * geo->pitch / 2.0;
+    p->p0 = (M - n + 1) / 2;
+    p->mixed = (nl > 0 && nn > 0);
+    // groups: mixed -> 0 = laser stars (alpha), 1 = natural stars (alpha_tt)
+    if (p->mixed) {
+        p->ngroups = 2;
+        p->gkind[0] = SAFR_LGS;
+        p->gkind[1] = SAFR_NGS;
+        p->galpha[0] = alpha;
+        p->galpha[1] = geo->alpha_tt;
+    } else {
+        p->ngroups = 1;
+        p->gkind[0] = nl > 0 ? SAFR_LGS : SAFR_NGS;
+        p->galpha[0] = alpha;
+    }
+    for (int g = 0; g < J; ++g) {
+        const int gi = p->mixed ? (geo->stars[g].kind == SAFR_LGS ? 0 : 1) : 0;
+        p->gstar[gi][p->gsize[gi]++] = g;
+    }
+    double cgrp[2][kMaxL];
+    for (int gi = 0; gi < p->ngroups; ++gi)
+        for (int l = 0; l < L; ++l)
+            cgrp[gi][l] = p->gkind[gi] == SAFR_LGS ? 1.0 - heights[l] / geo->h_lgs : 1.0;
+    for (int l = 0; l < L; ++l) p->c_out[l] = cgrp[0][l];
+
+    // domain condition c_l Omega_A + alpha_g h_l in c_l Omega_T (Sec. 2); skipped when the
+    // data covers the whole periodic grid (n == M)
+    if (n < M) {
+        const double half = 0.5 * (n - 1) * geo->pitch;
+        for (int gi = 0; gi < p->ngroups; ++gi)
+            for (int l = 0; l < L; ++l)
+                for (int m = 0; m < p->gsize[gi]; ++m) {
+                    const safr_star& st = geo->stars[p->gstar[gi][m]];
+                    const double c = cgrp[gi][l];
+                    const double ext = c * half + std::max(std::fabs(st.ax), std::fabs(st.ay)) * heights[l];
+                    if (ext > c * p->T * (1.0 + 1e-12)) {
+                        free_plan(p);
+                        return fail(SAFR_ERR_DOMAIN, "star %d at layer %d leaves the periodic domain",
+                                    p->gstar[gi][m], l);
+                    }
+                }
+    }
+
+    std::vector<unsigned char> pup((size_t)n * n, 1);
+    if (geo->pupil)
+        for (size_t i = 0; i < pup.size(); ++i) pup[i] = geo->pupil[i] ? 1 : 0;
+    std::vector<int> mode(J, 0);
+    if (p->mixed) {
+        double inv[9];
+        if (!tt_inverse(pup, n, inv)) {
+            free_plan(p);
+            return fail(SAFR_ERR_GEOMETRY, "pupil too small for a tip/tilt fit");
+        }
+        for (int a = 0; a < 3; ++a) {
+            p->tt_b[a] = (float)inv[3 + a];
+            p->tt_c[a] = (float)inv[6 + a];
+        }
+        for (int g = 0; g < J; ++g) mode[g] = geo->stars[g].kind == SAFR_LGS ? 1 : 2;
+    }
+
+    // tuning defaults
+    const int T = team_size(M);
+    p->row_teams = std::min(256 / T, std::max(1, (n + 1) / 2));
+    if (M == 256) p->row_teams = std::min(p->row_teams, 8);
+    p->out_rows = p->mixed ? (M == 256 ? 8 : 16) : 16;
+
+    safr_status st = SAFR_OK;
+    double2* W = nullptr;
+    double2* Qd = nullptr;
+    double* sig = nullptr;
+    float* feats = nullptr;
+    float* phi = nullptr;
+    int* dbad = nullptr;
+    do {
+        size_t total = 0, total32 = 0;
+        const int cpw = 256 / M, kblocks = (p->Kh + cpw - 1) / cpw;
+        for (int gi = 0; gi < p->ngroups; ++gi) {
+            p->boff[gi] = total;
+            p->bcount[gi] = (size_t)p->Kh * M * L * p->gsize[gi];
+            total += p->bcount[gi];
+            p->boff32[gi] = total32;
+            total32 += (size_t)kblocks * L * p->gsize[gi] * 256;
+        }
+#define PC_TRY(expr)                                                                                \
+    {                                                                                               \
+        hipError_t _e = (expr);                                                                     \
+        if (_e != hipSuccess) {                                                                     \
+            st = fail(SAFR_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(_e));            \
+            break;                                                                                  \
+        }                                                                                           \
+    }
+        PC_TRY(hipMalloc(&p->B64, total * sizeof(double2)));
+        PC_TRY(hipMalloc(&p->B32, total32 * sizeof(float2)));
+        PC_TRY(hipMemsetAsync(p->B32, 0, total32 * sizeof(float2), stream));
+        if (p->mixed) {
+            std::vector<float2> X, Y;
+            tt_transforms(pup, n, M, p->p0, X, Y);
+            PC_TRY(hipMalloc(&p->Xh, X.size() * sizeof(float2)));
+            PC_TRY(hipMalloc(&p->Yh, Y.size() * sizeof(float2)));
+            PC_TRY(hipMemcpy(p->Xh, X.data(), X.size() * sizeof(float2), hipMemcpyHostToDevice));
+            PC_TRY(hipMemcpy(p->Yh, Y.data(), Y.size() * sizeof(float2), hipMemcpyHostToDevice));
+        }
+        std::vector<float2> tw(M);
+        for (int e = 0; e < M; ++e)
+            tw[e] = make_float2((float)std::cos(2.0 * M_PI * e / M), (float)std::sin(2.0 * M_PI * e / M));
+        PC_TRY(hipMalloc(&p->tw, M * sizeof(float2)));
+        PC_TRY(hipMemcpy(p->tw, tw.data(), M * sizeof(float2), hipMemcpyHostToDevice));
+        PC_TRY(hipMalloc(&p->pupil, pup.size()));
+        PC_TRY(hipMemcpy(p->pupil, pup.data(), pup.size(), hipMemcpyHostToDevice));
+        PC_TRY(hipMalloc(&p->tt_mode, J * sizeof(int)));
+        PC_TRY(hipMemcpy(p->tt_mode, mode.data(), J * sizeof(int), hipMemcpyHostToDevice));
+        PC_TRY(hipMalloc(&dbad, sizeof(int)));
+        PC_TRY(hipMemsetAsync(dbad, 0, sizeof(int), stream));
+        const int H = p->Kh * M;
+        int gmax = std::max(p->gsize[0], p->gsize[1]);
+        const int Rm = std::max(gmax, L), Cm = std::min(gmax, L);
+        PC_TRY(hipMalloc(&W, (size_t)H * Rm * Cm * sizeof(double2)));
+        PC_TRY(hipMalloc(&Qd, (size_t)H * Cm * Cm * sizeof(double2)));
+        PC_TRY(hipMalloc(&sig, (size_t)H * Cm * sizeof(double)));
+        if (geo->filter == SAFR_FILTER_MLP) {
+            PC_TRY(hipMalloc(&feats, (size_t)H * Cm * 4 * sizeof(float)));
+            PC_TRY(hipMalloc(&phi, (size_t)H * Cm * sizeof(float)));
+        }
+        for (int gi = 0; gi < p->ngroups && st == SAFR_OK; ++gi) {
+            PrecompArgs a{};
+            a.M = M;
+            a.G = p->gsize[gi];
+            a.L = L;
+            a.T = p->T;
+            a.beta = geo->beta;
+            a.alpha = p->galpha[gi];
+            for (int m = 0; m < a.G; ++m) {
+                a.ax[m] = geo->stars[p->gstar[gi][m]].ax;
+                a.ay[m] = geo->stars[p->gstar[gi][m]].ay;
+            }
+            for (int l = 0; l < L; ++l) {
+                a.h[l] = heights[l];
+                a.c[l] = cgrp[gi][l];
+                a.gamma[l] = weights[l] / wsum;
+                a.sqrt_gamma[l] = std::sqrt(weights[l] / wsum);
+            }
+            a.W = W;
+            a.Q = Qd;
+            a.sigma = sig;
+            a.feats = feats;
+            a.phi = phi;
+            a.B64 = p->B64 + p->boff[gi];
+            a.B32 = p->B32 + p->boff32[gi];
+            a.log10_noise = geo->filter == SAFR_FILTER_MLP ? std::log10(geo->noise) : 0.0;
+            a.bad = dbad;
+            PC_TRY(launch_svd(a, stream));
+            if (geo->filter == SAFR_FILTER_MLP) {
+                st = fail(SAFR_ERR_UNSUPPORTED, "learned filter not available in this build");
+                break;
+            }
+            PC_TRY(launch_assemble(a, stream));
+        }
+        if (st != SAFR_OK) break;
+        int hbad = 0;
+        PC_TRY(hipMemcpyAsync(&hbad, dbad, sizeof(int), hipMemcpyDeviceToHost, stream));
+        PC_TRY(hipStreamSynchronize(stream));
+        if (hbad) {
+            st = fail(SAFR_ERR_NUMERIC, "non-finite value in the precomputed operator");
+            break;
+        }
+        p->ws_own_bytes = ws_bytes(p, 1);
+        PC_TRY(hipMalloc(&p->ws_own, p->ws_own_bytes));
+#undef PC_TRY
+    } while (0);
+    hipFree(W);
+    hipFree(Qd);
+    hipFree(sig);
+    hipFree(feats);
+    hipFree(phi);
+    hipFree(dbad);
+    if (st != SAFR_OK) {
+        free_plan(p);
+        return st;
+    }
+    *out = p;
+    return SAFR_OK;
+}
+
+safr_status safr_workspace_size(const safr_plan* p, int frames, int precision, size_t* bytes) {
+    if (!p || !bytes) return fail(SAFR_ERR_ARG, "NULL argument");
+    if (frames < 1) return fail(SAFR_ERR_ARG, "frames must be >= 1");
+    if (precision != SAFR_FP32 && precision != SAFR_BF16X3) return fail(SAFR_ERR_ARG, "bad precision");
+    *bytes = ws_bytes(p, frames);
+    return SAFR_OK;
+}
+
+safr_status safr_set_workspace(safr_plan* p, void* dev, size_t bytes) {
+    if (!p) return fail(SAFR_ERR_ARG, "plan is NULL");
+    if (dev && (reinterpret_cast<uintptr_t>(dev) & 255)) return fail(SAFR_ERR_ARG, "workspace not 256-byte aligned");
+    p->ws_user = dev;
+    p->ws_user_bytes = dev ? bytes : 0;
+    return SAFR_OK;
+}
+
+safr_status safr_plan_info(const safr_plan* p, safr_plan_desc* d) {
+    if (!p || !d) return fail(SAFR_ERR_ARG, "NULL argument");
+    std::memset(d, 0, sizeof(*d));
+    d->n = p->n;
+    d->M = p->M;
+    d->J = p->J;
+    d->L = p->L;
+    d->groups = p->ngroups;
+    for (int gi = 0; gi < p->ngroups; ++gi) {
+        d->group_size[gi] = p->gsize[gi];
+        d->group_kind[gi] = p->gkind[gi];
+        d->B_complex_per_group[gi] = p->bcount[gi];
+    }
+    for (int l = 0; l < p->L; ++l) {
+        d->c[l] = p->c_out[l];
+        d->layer_pitch[l] = p->c_out[l] * p->pitch;
+    }
+    return SAFR_OK;
+}
+
+safr_status safr_export_B(const safr_plan* p, int group, double* host, size_t count) {
+    if (!p || !host) return fail(SAFR_ERR_ARG, "NULL argument");
+    if (group < 0 || group >= p->ngroups) return fail(SAFR_ERR_ARG, "bad group %d", group);
+    const size_t need = 2 * p->bcount[group];
+    if (count < need) return fail(SAFR_ERR_ARG, "buffer holds %zu doubles, need %zu", count, need);
+    // device layout [k][l][g][j] -> export layout [k][j][l][g]
+    std::vector<double2> tmp(p->bcount[group]);
+    HIP_TRY(hipMemcpy(tmp.data(), p->B64 + p->boff[group], tmp.size() * sizeof(double2),
+                      hipMemcpyDeviceToHost));
+    const int M = p->M, L = p->L, G = p->gsize[group];
+    for (int k = 0; k < p->Kh; ++k)
+        for (int l = 0; l < L; ++l)
+            for (int g = 0; g < G; ++g)
+                for (int j = 0; j < M; ++j) {
+                    const double2 v = tmp[(((size_t)k * L + l) * G + g) * M + j];
+                    const size_t o = (((size_t)k * M + j) * L + l) * G + g;
+                    host[2 * o] = v.x;
+                    host[2 * o + 1] = v.y;
+                }
+    return SAFR_OK;
+}
+
+safr_status safr_reconstruct_batched(safr_plan* p, int frames, const float* wf, float* out, int precision,
+                                     hipStream_t s) {
+    if (!p || !wf || !out) return fail(SAFR_ERR_ARG, "NULL argument");
+    if (frames < 1) return fail(SAFR_ERR_ARG, "frames must be >= 1");
+    if (precision != SAFR_FP32 && precision != SAFR_BF16X3) return fail(SAFR_ERR_ARG, "bad precision");
+    if (precision == SAFR_BF16X3 && !p->Apack)
+        return fail(SAFR_ERR_UNSUPPORTED, "BF16 path not available in this build");
+    const size_t need = ws_bytes(p, frames);
+    void* ws = nullptr;
+    if (p->ws_user && p->ws_user_bytes >= need) ws = p->ws_user;
+    else if (p->ws_own_bytes >= need) ws = p->ws_own;
+    else return fail(SAFR_ERR_STATE, "workspace of %zu bytes needed for %d frames", need, frames);
+
+    if (p->use_graph && s != nullptr) {
+        const bool hit = p->gexec && p->g_frames == frames && p->g_prec == precision && p->g_wf == wf &&
+                         p->g_out == out && p->g_stream == s;
+        if (!hit) {
+            if (p->gexec) hipGraphExecDestroy(p->gexec);
+            if (p->graph) hipGraphDestroy(p->graph);
+            p->gexec = nullptr;
+            p->graph = nullptr;
+            HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            safr_status st = launch_all(p, frames, wf, out, precision, ws, s);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(s, &g);
+            if (st != SAFR_OK) {
+                if (g) hipGraphDestroy(g);
+                return st;
+            }
+            if (e != hipSuccess) return fail(SAFR_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+            p->graph = g;
+            HIP_TRY(hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0));
+            p->g_frames = frames;
+            p->g_prec = precision;
+            p->g_wf = wf;
+            p->g_out = out;
+            p->g_stream = s;
+        }
+        HIP_TRY(hipGraphLaunch(p->gexec, s));
+        return SAFR_OK;
+    }
+    return launch_all(p, frames, wf, out, precision, ws, s);
+}
+
+safr_status safr_reconstruct(safr_plan* p, const float* wf, float* out, hipStream_t s) {
+    return safr_reconstruct_batched(p, 1, wf, out, SAFR_FP32, s);
+}
+
+safr_status safr_time_stages(safr_plan* p, int frames, const float* wf, float* out, int precision, int iters,
+                             hipStream_t s, double* ms) {
+    if (!p || !wf || !out || !ms || iters < 1) return fail(SAFR_ERR_ARG, "bad argument");
+    if (precision != SAFR_FP32 && precision != SAFR_BF16X3) return fail(SAFR_ERR_ARG, "bad precision");
+    if (precision == SAFR_BF16X3 && !p->Apack) return fail(SAFR_ERR_UNSUPPORTED, "BF16 path not available");
+    const size_t need = ws_bytes(p, frames);
+    void* ws = nullptr;
+    if (p->ws_user && p->ws_user_bytes >= need) ws = p->ws_user;
+    else if (p->ws_own_bytes >= need) ws = p->ws_own;
+    else return fail(SAFR_ERR_STATE, "workspace of %zu bytes needed for %d frames", need, frames);
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+    double acc[3] = {0, 0, 0};
+    safr_status st = SAFR_OK;
+    for (int it = 0; it < iters && st == SAFR_OK; ++it) {
+        st = launch_all(p, frames, wf, out, precision, ws, s, ev);
+        if (st != SAFR_OK) break;
+        if (hipEventSynchronize(ev[3]) != hipSuccess) {
+            st = fail(SAFR_ERR_DEVICE, "event synchronisation failed");
+            break;
+        }
+        for (int k = 0; k < 3; ++k) {
+            float t = 0.f;
+            hipEventElapsedTime(&t, ev[k], ev[k + 1]);
+            acc[k] += t;
+        }
+    }
+    for (auto& e : ev) hipEventDestroy(e);
+    if (st != SAFR_OK) return st;
+    for (int k = 0; k < 3; ++k) ms[k] = acc[k] / iters;
+    return SAFR_OK;
+}
+
+void safr_destroy(safr_plan* p) { free_plan(p); }
+
+safr_status safr_set_option(safr_plan* p, int option, int value) {
+    if (!p) return fail(SAFR_ERR_ARG, "plan is NULL");
+    switch (option) {
+        case 0: p->use_graph = value != 0; return SAFR_OK;
+        case 1:
+            if (value < 1 || value * team_size(p->M) > 256) return fail(SAFR_ERR_ARG, "bad row team count");
+            p->row_teams = value;
+            return SAFR_OK;
+        case 2:
+            if (value < 2 || value > p->M) return fail(SAFR_ERR_ARG, "bad output rows per block");
+            if (out_lds_bytes(p->M, value, p->mixed) > kMaxLds)
+                return fail(SAFR_ERR_ARG, "%d output rows per block need more than 160 KiB of LDS", value);
+            p->out_rows = value;
+            return SAFR_OK;
+        case 3:
+            if (value != 16) return fail(SAFR_ERR_ARG, "frames per MFMA block must be 16");
+            p->mfma_frames = value;
+            return SAFR_OK;
+        case 4:
+            if (value < 1 || value > 4096) return fail(SAFR_ERR_ARG, "bad frames per column block");
+            p->col_frames = value;
+            return SAFR_OK;
+        case 5: p->col_prefetch = value != 0; return SAFR_OK;
+        default: return fail(SAFR_ERR_ARG, "unknown option %d", option);
+    }
+}
+
+}  // extern "C"
+
+namespace {
+
+safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, int precision, void* ws,
+                       hipStream_t s, hipEvent_t* ev) {
+    if (ev) HIP_TRY(hipEventRecord(ev[0], s));
+    char* base = reinterpret_cast<char*>(ws);
+    float2* R = reinterpret_cast<float2*>(base);
+    float2* C = reinterpret_cast<float2*>(base + ws_r(p, frames));
+    float* mom = reinterpret_cast<float*>(base + ws_r(p, frames) + ws_c(p, frames));
+    RowArgs ra{};
+    ra.wf = wf;
+    ra.R = R;
+    ra.mom = mom;
+    ra.pupil = p->pupil;
+    ra.tt_mode = p->tt_mode;
+    ra.tw = p->tw;
+    ra.n = p->n;
+    ra.J = p->J;
+    ra.p0 = p->p0;
+    ra.rows_per_block = 2 * p->row_teams;
+    const int nchunk = (p->n + ra.rows_per_block - 1) / ra.rows_per_block;
+    HIP_TRY(launch_rows(p->M, ra, frames, nchunk, p->row_teams, s));
+    if (ev) HIP_TRY(hipEventRecord(ev[1], s));
+
+    GroupSet gs{};
+    gs.count = p->ngroups;
+    int gmax = 0;
+    for (int gi = 0; gi < p->ngroups; ++gi) {
+        gs.g[gi].G = p->gsize[gi];
+        gs.g[gi].mode = p->mixed ? (p->gkind[gi] == SAFR_LGS ? 1 : 2) : 0;
+        for (int m = 0; m < p->gsize[gi]; ++m) gs.g[gi].star[m] = p->gstar[gi][m];
+        gs.g[gi].b_off = p->boff32[gi];
+        gmax = std::max(gmax, p->gsize[gi]);
+    }
+    if (precision == SAFR_FP32) {
+        ColArgs ca{};
+        ca.R = R;
+        ca.B = p->B32;
+        ca.C = C;
+        ca.tw = p->tw;
+        ca.mom = mom;
+        ca.Xh = p->Xh;
+        ca.Yh = p->Yh;
+        for (int i = 0; i < 3; ++i) {
+            ca.tt_b[i] = p->tt_b[i];
+            ca.tt_c[i] = p->tt_c[i];
+        }
+        ca.groups = gs;
+        ca.n = p->n;
+        ca.J = p->J;
+        ca.L = p->L;
+        ca.p0 = p->p0;
+        ca.frames = frames;
+        ca.frames_per_block = std::max(1, std::min(p->col_frames, frames));
+        ca.nchunk = nchunk;
+        ca.gmax = gmax;
+        ca.prefetch = p->col_prefetch;
+        HIP_TRY(launch_cols(p->M, ca, frames, s));
+    } else {
+        MfmaArgs ma{};
+        ma.R = R;
+        ma.Apack = p->Apack;
+        ma.C = C;
+        ma.tw = p->tw;
+        ma.groups = gs;
+        for (int gi = 0; gi < 2; ++gi) {
+            ma.a_off[gi] = p->apack_off[gi];
+            ma.lt[gi] = p->mf_lt[gi];
+            ma.ntile[gi] = p->mf_ntile[gi];
+            ma.ppm[gi] = p->mf_ppm[gi];
+        }
+        ma.n = p->n;
+        ma.J = p->J;
+        ma.L = p->L;
+        ma.p0 = p->p0;
+        ma.frames = frames;
+        HIP_TRY(launch_cols_mfma(p->M, ma, frames, p->mfma_frames, s));
+    }
+    if (ev) HIP_TRY(hipEventRecord(ev[2], s));
+
+    OutArgs oa{};
+    oa.C = C;
+    oa.out = out;
+    oa.tw = p->tw;
+    for (int l = 0; l < p->L; ++l) oa.c[l] = (float)p->c_out[l];
+    oa.L = p->L;
+    oa.groups = p->ngroups;
+    oa.mixed = p->mixed;
+    oa.rows_per_block = p->out_rows;
+    oa.ngs_group = p->mixed ? 1 : 0;
+    HIP_TRY(launch_out(p->M, oa, frames, s));
+    if (ev) HIP_TRY(hipEventRecord(ev[3], s));
+    return SAFR_OK;
+}
+
+}  // namespace

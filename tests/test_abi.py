@@ -1,0 +1,70 @@
+"""The C ABI library loads and exports every symbol the header declares; argument
+validation that fails before any device work returns the documented codes (CPU only)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "safr.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(safr_[a-z_A-Z0-9]+)\s*\(", text)))
+
+
+def _lib():
+    from paper_2510_19542_amd import safr as S
+    if not os.path.exists(S.LIB_PATH):
+        pytest.fail("libsafr.so is not built (run __graft_entry__.build())")
+    return S
+
+
+def test_header_declares_the_entry_points():
+    names = _declared()
+    for must in ("safr_precompute", "safr_reconstruct", "safr_reconstruct_batched", "safr_destroy"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    S = _lib()
+    L = ctypes.CDLL(S.LIB_PATH)
+    for name in _declared():
+        assert hasattr(L, name), name
+    assert sorted(S.EXPORTED) == sorted(_declared())
+
+
+def _pre(S, **kw):
+    args = dict(n=9, M=32, pitch=0.5, stars=[(1e-5, 0.0, 0), (0.0, 1e-5, 0)], h_lgs=90e3,
+                heights=[0.0, 5000.0], weights=[0.5, 0.5], alpha=1e-3, alpha_tt=1e-3, beta=1.5, stream=0)
+    args.update(kw)
+    return S.safr_precompute(**args)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(M=48), -4),                                   # M not a supported power of two
+    (dict(M=100), -4),
+    (dict(n=40), -4),                                   # n > M
+    (dict(n=0), -1),
+    (dict(alpha=-1.0), -1),
+    (dict(beta=-0.5), -1),
+    (dict(pitch=0.0), -1),
+    (dict(heights=[5000.0, 0.0]), -2),                  # not ascending
+    (dict(heights=[0.0, 0.0]), -2),
+    (dict(weights=[0.5, 0.0]), -2),
+    (dict(stars=[(1e-5, 0.0, 1)], heights=[0.0, 95e3]), -2),   # laser star, layer above the sodium layer
+    (dict(stars=[(3e-3, 0.0, 0)], heights=[0.0, 5000.0]), -3),  # line of sight leaves the domain
+    (dict(stars=[(0.0, 0.0, 7)]), -1),
+    (dict(stars=[(0.0, 0.0, 0)] * 17), -4),             # more than 16 stars of one kind
+    (dict(heights=list(np.arange(17) * 100.0), weights=[1.0] * 17), -4),
+])
+def test_validation_errors(kw, code):
+    S = _lib()
+    with pytest.raises(S.SafrError) as e:
+        _pre(S, **kw)
+    assert e.value.status == code
+    assert len(S.safr_last_error()) > 0

@@ -1,0 +1,254 @@
+"""Parity of the HIP library (through its C ABI) with the FP64 oracle.
+
+Tolerances (relative L2 over the whole result, per frame):
+* B from the GPU's FP64 precomputation vs the oracle's: 1e-12 (both FP64; the
+  SVDs differ only in rounding order);
+* FP32 reconstruction vs the oracle: 1e-5.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import safr as O
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _lib():
+    from paper_2510_19542_amd import safr as S
+    S.lib()                      # fails loudly if the library is missing
+    return S
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def _geo(name, **kw):
+    g = synth.preset(name)
+    return g.replace(**kw) if kw else g
+
+
+def _small(M=32, n=17, kinds=(0, 0, 0), L=2, seed=0, pitch=0.5, alpha=1e-3, alpha_tt=1e-3, beta=1.5,
+           obstruction=0.0):
+    """Small geometry with random star angles that satisfies the domain condition."""
+    rng = np.random.default_rng(100 + seed)
+    T = M * pitch / 2
+    half = (n - 1) * pitch / 2
+    h = np.sort(rng.uniform(0, 12000, L))
+    h[0] = 0.0
+    h = np.maximum.accumulate(h + np.arange(L) * 10.0)
+    hmax = max(h.max(), 1.0)
+    amax = abs(0.8 * (0.7 * T - half) / hmax)
+    stars = [(float(rng.uniform(-amax, amax)), float(rng.uniform(-amax, amax)), int(k)) for k in kinds]
+    return synth.Geometry(name=f"small{seed}", n=n, M=M, pitch=pitch, diameter=(n - 1) * pitch,
+                          obstruction=obstruction, stars=stars, h_lgs=90e3, heights=h,
+                          weights=rng.uniform(0.2, 1.0, L), alpha=alpha, alpha_tt=alpha_tt, beta=beta,
+                          truth_heights=h, truth_fracs=np.ones(L) / L, r0=0.15, L0=25.0, eta=0.01,
+                          config_id=90 + seed)
+
+
+def _gpu_reconstruct(geo, wf, **kw):
+    torch = _torch()
+    S = _lib()
+    plan = S.precompute_geometry(geo, **kw)
+    x = torch.from_numpy(np.ascontiguousarray(wf, dtype=np.float32)).cuda()
+    out = S.reconstruct(plan, x)
+    torch.cuda.synchronize()
+    return plan, out.cpu().numpy()
+
+
+_ORACLE_CACHE = {}
+
+
+def _oracle(geo, **kw):
+    key = (geo.name, geo.n, geo.M, tuple(map(tuple, geo.stars)), tuple(geo.heights), tuple(sorted(kw)))
+    if key not in _ORACLE_CACHE:
+        _ORACLE_CACHE[key] = O.precompute_geometry(geo, **kw)
+    return _ORACLE_CACHE[key]
+
+
+def _wavefronts(geo, frame=0):
+    wf, _ = synth.frame(geo, frame)
+    return wf
+
+
+CASES = {
+    "C1": lambda: _geo("C1"),
+    "C5-Mid": lambda: _geo("C5-Mid"),
+    "C2": lambda: _geo("C2"),
+    "m32-ngs-odd-n": lambda: _small(32, 17, (0, 0, 0, 0), L=2, seed=1),
+    "m32-lgs-even-n": lambda: _small(32, 20, (1, 1, 1), L=3, seed=2),
+    "m32-mixed": lambda: _small(32, 19, (1, 1, 1, 0, 0), L=3, seed=3, obstruction=0.2),
+    "m64-one-star-one-layer": lambda: _small(64, 33, (0,), L=1, seed=4),
+    "m128-lgs-G1-L4": lambda: _small(128, 45, (1,), L=4, seed=5),
+    "m32-full-grid": lambda: _small(32, 32, (0, 0, 0), L=2, seed=6),
+    "m64-mixed-L5": lambda: _small(64, 31, (1, 1, 1, 1, 0, 0, 0), L=5, seed=7),
+    "m32-n1": lambda: _small(32, 1, (0, 0), L=1, seed=8),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_B_matches_oracle(case):
+    geo = CASES[case]()
+    S = _lib()
+    plan = S.precompute_geometry(geo)
+    ref = _oracle(geo)
+    M = geo.M
+    for gi, grp in enumerate(ref.groups):
+        got = S.safr_export_B(plan, gi)                          # [k][j][l][g]
+        want = np.transpose(grp.B[:, : M // 2 + 1], (1, 0, 2, 3))
+        err = np.max(np.abs(got - want)) / np.max(np.abs(want))
+        assert err <= 1e-12, (case, gi, err)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_reconstruct_matches_oracle(case):
+    geo = CASES[case]()
+    wf = _wavefronts(geo)
+    _, got = _gpu_reconstruct(geo, wf)
+    want = O.reconstruct(_oracle(geo), wf.astype(np.float64))
+    err = rel_l2(got, want)
+    print(f"{case}: rel-L2 {err:.3e}")
+    assert err <= 1e-5, (case, err)
+
+
+def test_exact_recovery_on_gpu():
+    """Periodic data from the exact forward operator, alpha = 0, J > L: the layers come back.
+
+    The worst frequency has sigma_min / sigma_max ~ 2e-4, so FP32 rounding of the data alone
+    costs ~3e-6 (measured with the oracle); the bound is 1e-4.
+    """
+    M = 32
+    st = [(1.3e-4, 0.2e-4, 0), (-0.5e-4, 1.1e-4, 0), (0.3e-4, -1.2e-4, 0), (-1.0e-4, -0.6e-4, 0)]
+    h = np.array([0.0, 4000.0, 8000.0])
+    geo = synth.Geometry(name="exact", n=M, M=M, pitch=1.0, diameter=float(M), obstruction=0.0, stars=st,
+                         h_lgs=90e3, heights=h, weights=np.array([0.5, 0.3, 0.2]), alpha=0.0, alpha_tt=0.0,
+                         beta=1.5, truth_heights=h, truth_fracs=np.ones(3) / 3, r0=0.15, L0=25.0, eta=0.0,
+                         config_id=99)
+    rng = np.random.default_rng(3)
+    F = O.dft2(rng.standard_normal((3, M, M)))
+    _, keep = O.shifted_index(M)
+    K = keep[:, None] & keep[None, :]
+    K[0, 0] = False
+    truth = O.idft2(F * K).real
+    c = O.cone_coefficients(h, 0, geo.h_lgs)
+    wf = O.forward_fourier(truth, O.layer_shifts(st, h, c, 1.0))
+    _, got = _gpu_reconstruct(geo, wf, pupil=None)
+    assert rel_l2(got, truth) <= 1e-4
+
+
+def test_batched_equals_single_frames():
+    torch = _torch()
+    S = _lib()
+    geo = _geo("C1")
+    plan = S.precompute_geometry(geo)
+    wf = torch.from_numpy(synth.frames(geo, 5)).cuda()
+    batched = S.reconstruct(plan, wf)
+    single = torch.stack([S.reconstruct(plan, wf[i]) for i in range(5)])
+    torch.cuda.synchronize()
+    assert torch.equal(batched, single)
+    ref = O.precompute_geometry(geo)
+    for i in range(5):
+        assert rel_l2(batched[i].cpu().numpy(), O.reconstruct(ref, wf[i].cpu().numpy().astype(np.float64))) <= 1e-5
+
+
+def test_nan_frame_stays_in_its_frame():
+    torch = _torch()
+    S = _lib()
+    geo = _small(32, 17, (1, 1, 0, 0), L=2, seed=12)
+    plan = S.precompute_geometry(geo)
+    wf = torch.from_numpy(synth.random_wavefronts(geo, 4)).cuda()
+    clean = S.reconstruct(plan, wf)
+    wf[2, 1, 8, 8] = float("nan")
+    dirty = S.reconstruct(plan, wf)
+    torch.cuda.synchronize()
+    assert torch.isnan(dirty[2]).any()
+    for i in (0, 1, 3):
+        assert torch.equal(dirty[i], clean[i])
+
+
+def test_deterministic():
+    torch = _torch()
+    S = _lib()
+    geo = _geo("C2")
+    plan = S.precompute_geometry(geo)
+    wf = torch.from_numpy(synth.random_wavefronts(geo, 1)[0]).cuda()
+    a = S.reconstruct(plan, wf)
+    b = S.reconstruct(plan, wf)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_graph_replay_matches_eager():
+    """The captured launch sequence, replayed several times with new data in the same buffers."""
+    torch = _torch()
+    S = _lib()
+    geo = _geo("C1")
+    plan = S.precompute_geometry(geo)
+    F = 3
+    need = S.safr_workspace_size(plan, F)
+    ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+    base = (ws.data_ptr() + 255) & ~255
+    S.safr_set_workspace(plan, base, need)
+    wf = torch.empty((F, geo.J, geo.n, geo.n), dtype=torch.float32, device="cuda")
+    out = torch.empty((F, geo.L, geo.M, geo.M), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.Stream()
+    for rep in range(4):
+        data = torch.from_numpy(synth.random_wavefronts(geo, F, seed=rep)).cuda()
+        wf.copy_(data)
+        torch.cuda.synchronize()
+        S.safr_set_option(plan, S.SAFR_OPT_GRAPH, 0)
+        S.safr_reconstruct_batched(plan, F, wf, out, S.SAFR_FP32, stream)
+        stream.synchronize()
+        eager = out.clone()
+        out.zero_()
+        torch.cuda.synchronize()
+        S.safr_set_option(plan, S.SAFR_OPT_GRAPH, 1)
+        S.safr_reconstruct_batched(plan, F, wf, out, S.SAFR_FP32, stream)
+        stream.synchronize()
+        assert torch.equal(out, eager), rep
+    S.safr_set_workspace(plan, 0, 0)
+
+
+def test_tuning_options_do_not_change_results():
+    torch = _torch()
+    S = _lib()
+    geo = _geo("C2")
+    plan = S.precompute_geometry(geo)
+    wf = torch.from_numpy(synth.random_wavefronts(geo, 1)[0]).cuda()
+    ref = S.reconstruct(plan, wf)
+    for teams in (1, 4, 16):
+        for rows in (2, 5, 16, 24):
+            S.safr_set_option(plan, S.SAFR_OPT_ROW_TEAMS, teams)
+            S.safr_set_option(plan, S.SAFR_OPT_OUT_ROWS, rows)
+            got = S.reconstruct(plan, wf)
+            torch.cuda.synchronize()
+            # a different row pairing in the packed transforms changes only the rounding
+            assert rel_l2(got.cpu().numpy(), ref.cpu().numpy().astype(np.float64)) <= 1e-6, (teams, rows)
+
+
+def test_oversized_output_tile_is_rejected():
+    S = _lib()
+    plan = S.precompute_geometry(_geo("C2"))
+    with pytest.raises(S.SafrError) as e:
+        S.safr_set_option(plan, S.SAFR_OPT_OUT_ROWS, 64)       # would need more than 160 KiB of LDS
+    assert e.value.status == S.SAFR_ERR_ARG
+
+
+def test_workspace_too_small_is_an_error():
+    torch = _torch()
+    S = _lib()
+    geo = _geo("C1")
+    plan = S.precompute_geometry(geo)
+    wf = torch.zeros((2, geo.J, geo.n, geo.n), device="cuda")
+    out = torch.zeros((2, geo.L, geo.M, geo.M), device="cuda")
+    with pytest.raises(S.SafrError) as e:
+        S.safr_reconstruct_batched(plan, 2, wf, out)
+    assert e.value.status == S.SAFR_ERR_STATE
