@@ -175,6 +175,14 @@ safr_status safr_set_option(safr_plan* p, int option, int value);
 safr_status safr_time_stages(safr_plan* p, int frames, const float* wavefronts, float* layers,
                              int precision, int iters, hipStream_t stream, double* ms);
 
+/* Autotuner: for the given frame count and precision, times every admissible
+ * row-pass block shape (SAFR_OPT_ROW_TEAMS), output-pass tile (SAFR_OPT_OUT_ROWS)
+ * and, for several FP32 frames, column-pass frames per block (SAFR_OPT_COL_FRAMES)
+ * with HIP events over `iters` synchronised launches each, and keeps the fastest.
+ * Overwrites `layers`.  choice (may be NULL) receives the three values chosen. */
+safr_status safr_autotune(safr_plan* p, int frames, const float* wavefronts, float* layers, int precision,
+                          int iters, hipStream_t stream, int* choice);
+
 /* Releases the plan and its device memory (NULL is a no-op). */
 void safr_destroy(safr_plan* p);
 

@@ -8,9 +8,7 @@
 // 256 / M columns of one group and loops over a chunk of frames.
 //
 // B is stored per block of columns as [l][g][column][j], so the block's whole
-// B slice is one contiguous run and thread t owns the entries t, t + 256, ...:
-// they are loaded into registers once, at entry (overlapping the first column
-// FFT), and reused for every frame of the chunk.
+// B slice is one contiguous run and thread t owns the entries t, t + 256, ...
 //
 // Split tomography (Sec. 3.3): the least-squares plane b x + c y of each
 // wavefront over the pupil is obtained from the moments written by the row
@@ -18,207 +16,315 @@
 // d_g -= b DFT2(x mask) + c DFT2(y mask) and keeping only the plane (natural
 // stars) is d_g = b DFT2(x mask) + c DFT2(y mask), with the two transforms
 // precomputed in FP64 per plan.
+//
+// Two kernels:
+//   cols_fixed<M, L, G0, G1>: shapes known at compile time (the configured
+//     geometries).  The block's B slice is loaded into registers once, right
+//     after the first column-FFT inputs (loads retire in order, so the first
+//     transform does not wait for B), and the apply is a branch-free unrolled
+//     L x G product whose LDS reads issue together.
+//   cols_generic<M>: any shape; B is read inside the apply loop.
 #include "fft_device.h"
 #include "safr_internal.h"
 
 namespace safr {
 
-template <int M, int GLMAX>
-__global__ __launch_bounds__(256) void cols_kernel(ColArgs a) {
+namespace {
+
+struct ColGeom {
+    int kb, k0, tid, team, t, c, j, k;
+    bool kvalid;
+    int f0, f1;
+};
+
+template <int M>
+__device__ __forceinline__ ColGeom col_geom(const ColArgs& a) {
     using S = FftShape<M>;
-    constexpr int T = S::T;
-    constexpr int CPW = 256 / M;
-    constexpr int Kh = M / 2 + 1;
-    constexpr int NTEAM = 256 / T;
-    constexpr int TL = team_lds<M>();
-    extern __shared__ float2 smem[];
+    ColGeom q;
+    q.kb = blockIdx.x;
+    q.k0 = q.kb * (256 / M);
+    q.tid = threadIdx.x;
+    q.team = q.tid / S::T;
+    q.t = q.tid % S::T;
+    q.c = q.tid / M;
+    q.j = q.tid % M;
+    q.k = q.k0 + q.c;
+    q.kvalid = q.k < M / 2 + 1;
+    q.f0 = blockIdx.z * a.frames_per_block;
+    q.f1 = min(a.frames, q.f0 + a.frames_per_block);
+    return q;
+}
 
-    const int gi = blockIdx.y;
-    const int kb = blockIdx.x;
-    const int k0 = kb * CPW;
+// plane coefficients (b, c) of every star of the group for frame f, from the row-pass moments
+__device__ __forceinline__ void plane_coefs(const ColArgs& a, const GroupArgs& gr, int G, int f, int tid,
+                                            float2* coef) {
+    if (tid < G) {
+        const float* mo = a.mom + ((size_t)f * a.J + gr.star[tid]) * a.nchunk * 4;
+        float m0 = 0.f, m1 = 0.f, m2 = 0.f;
+        for (int q = 0; q < a.nchunk; ++q) {
+            m0 += mo[4 * q + 0];
+            m1 += mo[4 * q + 1];
+            m2 += mo[4 * q + 2];
+        }
+        coef[tid] = make_float2(a.tt_b[0] * m0 + a.tt_b[1] * m1 + a.tt_b[2] * m2,
+                                a.tt_c[0] * m0 + a.tt_c[1] * m1 + a.tt_c[2] * m2);
+    }
+}
+
+__device__ __forceinline__ float2 plane_value(float2 cf, float2 xh, float2 yh) {
+    return make_float2(cf.x * xh.x + cf.y * yh.x, cf.x * xh.y + cf.y * yh.y);
+}
+
+// column-FFT inputs of task `task` (= column * G + member) for thread t: x[n1] = R[.][k][N2 n1 + t - p0]
+template <int M>
+__device__ __forceinline__ void load_column(const ColArgs& a, const GroupArgs& gr, int G, int ftasks, int k0,
+                                            int f, int task, int t, float2 (&x)[FftShape<M>::N1]) {
+    using S = FftShape<M>;
+    const int cc = task / G, g = task - cc * G;
+    const int kk = k0 + cc;
+    if (task < ftasks && kk < M / 2 + 1) {
+        const float2* col = a.R + (((size_t)f * a.J + gr.star[g]) * (M / 2 + 1) + kk) * a.n;
+#pragma unroll
+        for (int n1 = 0; n1 < S::N1; ++n1) {
+            const int pr = S::N2 * n1 + t - a.p0;
+            x[n1] = (pr >= 0 && pr < a.n) ? col[pr] : make_float2(0.f, 0.f);
+        }
+    }
+}
+
+// inverse column transforms of the L layer spectra in Bsp, written to C
+template <int M>
+__device__ __forceinline__ void inverse_columns(const ColArgs& a, const ColGeom& q, int gi, int L, int f,
+                                                const float2* tws, float2* xch, const float2* Bsp) {
+    constexpr int CPW = 256 / M, Kh = M / 2 + 1, NTEAM = 256 / FftShape<M>::T;
+    const int itasks = CPW * L;
+    for (int base = 0; base < itasks; base += NTEAM) {
+        const int task = base + q.team;
+        const int cc = task / L, l = task - cc * L;
+        const int kk = q.k0 + cc;
+        const bool active = task < itasks && kk < Kh;
+        if (active) {
+            const float2* src = Bsp + (cc * L + l) * M;
+            fft_pass1<M, +1>(q.t, xch, tws, [&](int jj) -> float2 { return src[jj]; });
+        }
+        __syncthreads();
+        if (active) {
+            float2* dst = a.C + ((((size_t)f * a.groups.count + gi) * L + l) * Kh + kk) * M;
+            fft_pass2<M, +1>(q.t, xch, [&](int p, float2 v) { dst[p] = v; });
+        }
+        __syncthreads();
+    }
+}
+
+// LDS: tws[M] | xch[NTEAM][TL] | D[CPW][gmax][M] | Bsp[CPW][L][M] | coef[16]
+template <int M>
+__device__ __forceinline__ void carve(float2* smem, int gmax, int L, float2*& tws, float2*& xall, float2*& D,
+                                      float2*& Bsp, float2*& coef) {
+    constexpr int CPW = 256 / M, NTEAM = 256 / FftShape<M>::T;
+    tws = smem;
+    xall = tws + M;
+    D = xall + NTEAM * team_lds<M>();
+    Bsp = D + CPW * gmax * M;
+    coef = Bsp + CPW * L * M;
+}
+
+template <int M, int L, int G, int MODE>
+__device__ __forceinline__ void cols_body(const ColArgs& a, int gi, float2* smem) {
+    using S = FftShape<M>;
+    constexpr int CPW = 256 / M, NTEAM = 256 / S::T;
+    constexpr int FT = MODE == 2 ? 0 : CPW * G;          // forward transforms per frame
     const GroupArgs& gr = a.groups.g[gi];
-    const int G = gr.G;
-    const int mode = gr.mode;
-    const int L = a.L;
-    const int LG = L * G;
-    const int n = a.n;
-    const int tid = threadIdx.x;
-    const int team = tid / T;
-    const int t = tid % T;
-    const int c = tid / M, j = tid % M;
-    const int k = k0 + c;
-    const bool kvalid = k < Kh;
-    const int f0 = blockIdx.z * a.frames_per_block;
-    const int f1 = min(a.frames, f0 + a.frames_per_block);
+    const ColGeom q = col_geom<M>(a);
+    float2 *tws, *xall, *D, *Bsp, *coef;
+    carve<M>(smem, a.gmax, L, tws, xall, D, Bsp, coef);
+    float2* xch = xall + q.team * team_lds<M>();
 
-    float2* xch = smem + team * TL;
-    float2* D = smem + NTEAM * TL;               // [CPW][G][M]
-    float2* Bsp = D + CPW * a.gmax * M;          // [CPW][L][M]
-    float2* coef = Bsp + CPW * L * M;            // [G] plane coefficients (b, c)
-
-    const float2* Bblk = a.B + gr.b_off + (size_t)kb * LG * 256;
-    const int ftasks = mode == 2 ? 0 : CPW * G;       // natural stars of a mixed asterism need no transform
-
-    // inputs of one pass-1 sub-transform of the column FFT: x[n1] = column[N2 n1 + t]
+    // loads, oldest first: twiddles, first column inputs, B
+    const float2 twv = q.tid < M ? a.tw[q.tid] : make_float2(0.f, 0.f);
     float2 x[S::N1];
-    auto load_column = [&](int f, int task) {
-        const int cc = task / G, g = task - cc * G;
-        const int kk = k0 + cc;
-        if (task < ftasks && kk < Kh) {
-            const float2* col = a.R + (((size_t)f * a.J + gr.star[g]) * Kh + kk) * n;
+    if constexpr (FT > 0) load_column<M>(a, gr, G, FT, q.k0, q.f0, q.team, q.t, x);
+    const float2* Bblk = a.B + gr.b_off + (size_t)q.kb * L * G * 256;
+    float2 breg[L * G];
 #pragma unroll
-            for (int n1 = 0; n1 < S::N1; ++n1) {
-                const int pr = S::N2 * n1 + t - a.p0;
-                x[n1] = (pr >= 0 && pr < n) ? col[pr] : make_float2(0.f, 0.f);
-            }
-        }
-    };
-    // the first transform's inputs are requested before B: loads retire in order, so the
-    // first column FFT does not wait for the B slice, which stays in registers for every frame
-    load_column(f0, team);
-    float2 breg[GLMAX > 0 ? GLMAX : 1];
-    if constexpr (GLMAX > 0) {
-#pragma unroll
-        for (int i = 0; i < GLMAX; ++i)
-            breg[i] = (i < LG) ? Bblk[(size_t)i * 256 + tid] : make_float2(0.f, 0.f);
-    }
+    for (int i = 0; i < L * G; ++i) breg[i] = Bblk[(size_t)i * 256 + q.tid];
     float2 xh = make_float2(0.f, 0.f), yh = make_float2(0.f, 0.f);
-    if (mode != 0 && kvalid) {
-        xh = a.Xh[(size_t)k * M + j];
-        yh = a.Yh[(size_t)k * M + j];
+    if (MODE != 0 && q.kvalid) {
+        xh = a.Xh[(size_t)q.k * M + q.j];
+        yh = a.Yh[(size_t)q.k * M + q.j];
     }
+    if (q.tid < M) tws[q.tid] = twv;
+    __syncthreads();
 
-    for (int f = f0; f < f1; ++f) {
-        if (mode != 0 && tid < G) {
-            const float* mo = a.mom + ((size_t)f * a.J + gr.star[tid]) * a.nchunk * 4;
-            float m0 = 0.f, m1 = 0.f, m2 = 0.f;
-            for (int q = 0; q < a.nchunk; ++q) {
-                m0 += mo[4 * q + 0];
-                m1 += mo[4 * q + 1];
-                m2 += mo[4 * q + 2];
-            }
-            coef[tid] = make_float2(a.tt_b[0] * m0 + a.tt_b[1] * m1 + a.tt_b[2] * m2,
-                                    a.tt_c[0] * m0 + a.tt_c[1] * m1 + a.tt_c[2] * m2);
-        }
-        // 1. forward column transforms
-        for (int base = 0; base < max(ftasks, 1); base += NTEAM) {
-            const int task = base + team;
-            const int cc = task / G, g = task - cc * G;
-            const bool active = task < ftasks && k0 + cc < Kh;
-            if (f != f0 || base != 0) load_column(f, task);
-            if (active) fft_pass1_regs<M, -1>(t, xch, a.tw, x);
-            __syncthreads();
-            if (active) {
-                float2* d = D + (cc * G + g) * M;
-                fft_pass2<M, -1>(t, xch, [&](int jj, float2 v) { d[jj] = v; });
-            }
-            __syncthreads();
-        }
-
-        // 2. per-frequency apply
-        if (kvalid) {
-            const float2* d = D + c * G * M + j;
-            float2* bo = Bsp + c * L * M + j;
-            auto dval = [&](int g) -> float2 {
-                if (mode == 0) return d[g * M];
-                const float2 cf = coef[g];
-                const float2 plane = make_float2(cf.x * xh.x + cf.y * yh.x, cf.x * xh.y + cf.y * yh.y);
-                return mode == 2 ? plane : csub(d[g * M], plane);
-            };
-            if constexpr (GLMAX > 0) {
-                float2 acc = make_float2(0.f, 0.f);
-                int g = 0, l = 0;
+    for (int f = q.f0; f < q.f1; ++f) {
+        if (MODE != 0) plane_coefs(a, gr, G, f, q.tid, coef);
+        if constexpr (FT > 0) {
 #pragma unroll
-                for (int i = 0; i < GLMAX; ++i) {
-                    if (i < LG) {
-                        const float2 bv = breg[i];
-                        const float2 dv = dval(g);
-                        acc.x += bv.x * dv.x - bv.y * dv.y;
-                        acc.y += bv.x * dv.y + bv.y * dv.x;
-                        if (++g == G) {
-                            bo[l * M] = acc;
-                            acc = make_float2(0.f, 0.f);
-                            g = 0;
-                            ++l;
-                        }
-                    }
+            for (int base = 0; base < FT; base += NTEAM) {
+                const int task = base + q.team;
+                const int cc = task / G, g = task - cc * G;
+                const bool active = task < FT && q.k0 + cc < M / 2 + 1;
+                if (f != q.f0 || base != 0) load_column<M>(a, gr, G, FT, q.k0, f, task, q.t, x);
+                if (active) fft_pass1_regs<M, -1>(q.t, xch, tws, x);
+                __syncthreads();
+                if (active) {
+                    float2* d = D + (cc * G + g) * M;
+                    fft_pass2<M, -1>(q.t, xch, [&](int jj, float2 v) { d[jj] = v; });
                 }
-            } else {
-                for (int l = 0; l < L; ++l) {
-                    float2 acc = make_float2(0.f, 0.f);
-                    for (int g = 0; g < G; ++g) {
-                        const float2 bv = Bblk[(size_t)(l * G + g) * 256 + tid];
-                        const float2 dv = dval(g);
-                        acc.x += bv.x * dv.x - bv.y * dv.y;
-                        acc.y += bv.x * dv.y + bv.y * dv.x;
-                    }
-                    bo[l * M] = acc;
+                __syncthreads();
+            }
+        } else {
+            __syncthreads();
+        }
+        if (q.kvalid) {
+            float2 dv[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                if constexpr (MODE == 0) dv[g] = D[(q.c * G + g) * M + q.j];
+                else if constexpr (MODE == 1) dv[g] = csub(D[(q.c * G + g) * M + q.j], plane_value(coef[g], xh, yh));
+                else dv[g] = plane_value(coef[g], xh, yh);
+            }
+#pragma unroll
+            for (int l = 0; l < L; ++l) {
+                float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const float2 bv = breg[l * G + g];
+                    acc.x += bv.x * dv[g].x - bv.y * dv[g].y;
+                    acc.y += bv.x * dv[g].y + bv.y * dv[g].x;
                 }
+                Bsp[(q.c * L + l) * M + q.j] = acc;
             }
         }
         __syncthreads();
-
-        // 3. inverse column transforms
-        const int itasks = CPW * L;
-        for (int base = 0; base < itasks; base += NTEAM) {
-            const int task = base + team;
-            const int cc = task / L, l = task - cc * L;
-            const int kk = k0 + cc;
-            const bool active = task < itasks && kk < Kh;
-            if (active) {
-                const float2* src = Bsp + (cc * L + l) * M;
-                fft_pass1<M, +1>(t, xch, a.tw, [&](int jj) -> float2 { return src[jj]; });
-            }
-            __syncthreads();
-            if (active) {
-                float2* dst = a.C + ((((size_t)f * a.groups.count + gi) * L + l) * Kh + kk) * M;
-                fft_pass2<M, +1>(t, xch, [&](int p, float2 v) { dst[p] = v; });
-            }
-            __syncthreads();
-        }
+        inverse_columns<M>(a, q, gi, L, f, tws, xch, Bsp);
     }
 }
 
-template <int M, int GLMAX>
-static hipError_t launch_cols_t2(const ColArgs& a, int frames, hipStream_t s) {
-    constexpr int CPW = 256 / M;
-    constexpr int Kh = M / 2 + 1;
-    const size_t lds = ((size_t)(256 / FftShape<M>::T) * team_lds<M>() + (size_t)CPW * (a.gmax + a.L) * M +
-                        kMaxG) * sizeof(float2);
-    const dim3 grid((Kh + CPW - 1) / CPW, a.groups.count, (frames + a.frames_per_block - 1) / a.frames_per_block);
-    allow_large_lds(reinterpret_cast<const void*>(&cols_kernel<M, GLMAX>));
-    hipLaunchKernelGGL((cols_kernel<M, GLMAX>), grid, dim3(256), lds, s, a);
-    return hipGetLastError();
+}  // namespace
+
+template <int M, int L, int G0, int G1>
+__global__ __launch_bounds__(256, 2) void cols_fixed(ColArgs a) {
+    extern __shared__ float2 smem[];
+    if constexpr (G1 == 0) {
+        cols_body<M, L, G0, 0>(a, 0, smem);
+    } else {
+        if (blockIdx.y == 0) cols_body<M, L, G0, 1>(a, 0, smem);
+        else cols_body<M, L, G1, 2>(a, 1, smem);
+    }
 }
 
 template <int M>
-static hipError_t launch_cols_t(const ColArgs& a, int frames, hipStream_t s) {
-    int lg = 0;
-    for (int i = 0; i < a.groups.count; ++i) lg = lg > a.L * a.groups.g[i].G ? lg : a.L * a.groups.g[i].G;
-    if (!a.prefetch) return launch_cols_t2<M, 0>(a, frames, s);
-    if (lg <= 8) return launch_cols_t2<M, 8>(a, frames, s);
-    if (lg <= 16) return launch_cols_t2<M, 16>(a, frames, s);
-    if (lg <= 32) return launch_cols_t2<M, 32>(a, frames, s);
-    if (lg <= 48) return launch_cols_t2<M, 48>(a, frames, s);
-    if (lg <= 56) return launch_cols_t2<M, 56>(a, frames, s);
-    if (lg <= 64) return launch_cols_t2<M, 64>(a, frames, s);
-    return launch_cols_t2<M, 0>(a, frames, s);
-}
-
-hipError_t launch_cols(int M, const ColArgs& a, int frames, hipStream_t s) {
-    switch (M) {
-        case 32: return launch_cols_t<32>(a, frames, s);
-        case 64: return launch_cols_t<64>(a, frames, s);
-        case 128: return launch_cols_t<128>(a, frames, s);
-        case 256: return launch_cols_t<256>(a, frames, s);
-        default: return hipErrorInvalidValue;
+__global__ __launch_bounds__(256) void cols_generic(ColArgs a) {
+    using S = FftShape<M>;
+    constexpr int CPW = 256 / M, NTEAM = 256 / S::T;
+    extern __shared__ float2 smem[];
+    const int gi = blockIdx.y;
+    const GroupArgs& gr = a.groups.g[gi];
+    const int G = gr.G, mode = gr.mode, L = a.L;
+    const ColGeom q = col_geom<M>(a);
+    float2 *tws, *xall, *D, *Bsp, *coef;
+    carve<M>(smem, a.gmax, L, tws, xall, D, Bsp, coef);
+    float2* xch = xall + q.team * team_lds<M>();
+    const int ftasks = mode == 2 ? 0 : CPW * G;
+    const float2* Bblk = a.B + gr.b_off + (size_t)q.kb * L * G * 256;
+    for (int i = q.tid; i < M; i += 256) tws[i] = a.tw[i];
+    float2 xh = make_float2(0.f, 0.f), yh = make_float2(0.f, 0.f);
+    if (mode != 0 && q.kvalid) {
+        xh = a.Xh[(size_t)q.k * M + q.j];
+        yh = a.Yh[(size_t)q.k * M + q.j];
+    }
+    __syncthreads();
+    for (int f = q.f0; f < q.f1; ++f) {
+        if (mode != 0) plane_coefs(a, gr, G, f, q.tid, coef);
+        for (int base = 0; base < max(ftasks, 1); base += NTEAM) {
+            const int task = base + q.team;
+            const int cc = task / G, g = task - cc * G;
+            const bool active = task < ftasks && q.k0 + cc < M / 2 + 1;
+            float2 x[S::N1];
+            load_column<M>(a, gr, G, ftasks, q.k0, f, task, q.t, x);
+            if (active) fft_pass1_regs<M, -1>(q.t, xch, tws, x);
+            __syncthreads();
+            if (active) {
+                float2* d = D + (cc * G + g) * M;
+                fft_pass2<M, -1>(q.t, xch, [&](int jj, float2 v) { d[jj] = v; });
+            }
+            __syncthreads();
+        }
+        if (q.kvalid) {
+            for (int l = 0; l < L; ++l) {
+                float2 acc = make_float2(0.f, 0.f);
+                for (int g = 0; g < G; ++g) {
+                    float2 dv;
+                    if (mode == 2) dv = plane_value(coef[g], xh, yh);
+                    else {
+                        dv = D[(q.c * G + g) * M + q.j];
+                        if (mode == 1) dv = csub(dv, plane_value(coef[g], xh, yh));
+                    }
+                    const float2 bv = Bblk[(size_t)(l * G + g) * 256 + q.tid];
+                    acc.x += bv.x * dv.x - bv.y * dv.y;
+                    acc.y += bv.x * dv.y + bv.y * dv.x;
+                }
+                Bsp[(q.c * L + l) * M + q.j] = acc;
+            }
+        }
+        __syncthreads();
+        inverse_columns<M>(a, q, gi, L, f, tws, xch, Bsp);
     }
 }
 
 size_t cols_lds_bytes(int M, int gmax, int L) {
     const int N1 = M == 32 ? 8 : (M == 64 ? 8 : 16), N2 = M / N1;
     const int T = M == 256 ? 16 : (M == 32 ? 4 : 8);
-    return ((size_t)(256 / T) * N1 * (N2 + 1) + (size_t)(256 / M) * (gmax + L) * M + kMaxG) * sizeof(float2);
+    return ((size_t)M + (size_t)(256 / T) * N1 * (N2 + 1) + (size_t)(256 / M) * (gmax + L) * M + kMaxG) *
+           sizeof(float2);
+}
+
+namespace {
+
+template <class K>
+hipError_t launch_cols_kernel(K kernel, int M, const ColArgs& a, int frames, hipStream_t s) {
+    const int CPW = 256 / M, Kh = M / 2 + 1;
+    const size_t lds = cols_lds_bytes(M, a.gmax, a.L);
+    const dim3 grid((Kh + CPW - 1) / CPW, a.groups.count, (frames + a.frames_per_block - 1) / a.frames_per_block);
+    allow_large_lds(reinterpret_cast<const void*>(kernel));
+    hipLaunchKernelGGL(kernel, grid, dim3(256), lds, s, a);
+    return hipGetLastError();
+}
+
+// shapes with a compile-time kernel: (M, L, laser-or-only group size, natural group size or 0)
+#define SAFR_FIXED_SHAPES(X) \
+    X(256, 9, 6, 3)          \
+    X(256, 9, 6, 0)          \
+    X(128, 5, 6, 0)          \
+    X(64, 2, 4, 0)           \
+    X(64, 3, 4, 0)
+
+bool fixed_shape_known(int M, int L, int G0, int G1) {
+#define SAFR_MATCH(m, l, g0, g1) \
+    if (M == m && L == l && G0 == g0 && G1 == g1) return true;
+    SAFR_FIXED_SHAPES(SAFR_MATCH)
+#undef SAFR_MATCH
+    return false;
+}
+
+}  // namespace
+
+hipError_t launch_cols(int M, const ColArgs& a, int frames, hipStream_t s) {
+    const int G0 = a.groups.g[0].G, G1 = a.groups.count > 1 ? a.groups.g[1].G : 0;
+    if (a.prefetch && fixed_shape_known(M, a.L, G0, G1)) {
+#define SAFR_LAUNCH(m, l, g0, g1)                           \
+    if (M == m && a.L == l && G0 == g0 && G1 == g1)         \
+        return launch_cols_kernel(&cols_fixed<m, l, g0, g1>, M, a, frames, s);
+        SAFR_FIXED_SHAPES(SAFR_LAUNCH)
+#undef SAFR_LAUNCH
+    }
+    switch (M) {
+        case 32: return launch_cols_kernel(&cols_generic<32>, M, a, frames, s);
+        case 64: return launch_cols_kernel(&cols_generic<64>, M, a, frames, s);
+        case 128: return launch_cols_kernel(&cols_generic<128>, M, a, frames, s);
+        case 256: return launch_cols_kernel(&cols_generic<256>, M, a, frames, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace safr

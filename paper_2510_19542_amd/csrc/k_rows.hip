@@ -40,25 +40,48 @@ __global__ void rows_kernel(RowArgs a) {
     const float* wf = a.wf + ((size_t)f * a.J + star) * (size_t)n * n + (size_t)r0 * n;
     const unsigned char* pup = a.pupil + (size_t)r0 * n;
 
-    // LDS: [teams][TL + M] exchange + packed spectra, then rows * n staged values, then 3 * waves floats
-    float2* xch = smem + team * (TL + M);
+    // LDS: twiddles [M], then per team (stride TS, odd so that teams fall on different banks)
+    // the pass-1 -> pass-2 exchange [TL] and the packed spectrum [M], then the staged rows, then
+    // 3 floats per wavefront for the moment reduction
+    constexpr int TS = TL + M + 1;
+    float2* tws = smem;
+    float2* xch = smem + M + team * TS;
     float2* zb = xch + TL;
-    float* vals = reinterpret_cast<float*>(smem + nteams * (TL + M));
+    float* vals = reinterpret_cast<float*>(smem + M + nteams * TS);
     float* red = vals + a.rows_per_block * n;
 
-    // stage the block's rows (pupil-masked), coalesced
+    // stage the block's rows (pupil-masked): all loads of a chunk are issued before any is used
     const float half = 0.5f * (float)(n - 1);
     float m0 = 0.f, m1 = 0.f, m2 = 0.f;
-    for (int i = tid; i < rows * n; i += nthr) {
-        const float v = pup[i] ? wf[i] : 0.f;
-        vals[i] = v;
-        if (mode != 0) {
-            const int pr = i / n;
-            const float x = (float)(r0 + pr) - half;
-            const float y = (float)(i - pr * n) - half;
-            m0 += v;
-            m1 += x * v;
-            m2 += y * v;
+    const int total = rows * n;
+    for (int i = tid; i < M; i += nthr) tws[i] = a.tw[i];
+    constexpr int CH = 8;
+    for (int base = 0; base < total; base += CH * nthr) {
+        float v[CH];
+        unsigned char m[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int i = base + tid + u * nthr;
+            if (i < total) {
+                m[u] = pup[i];
+                v[u] = wf[i];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int i = base + tid + u * nthr;
+            if (i < total) {
+                const float val = m[u] ? v[u] : 0.f;
+                vals[i] = val;
+                if (mode != 0) {
+                    const int pr = i / n;
+                    const float x = (float)(r0 + pr) - half;
+                    const float y = (float)(i - pr * n) - half;
+                    m0 += val;
+                    m1 += x * val;
+                    m2 += y * val;
+                }
+            }
         }
     }
     if (mode != 0) {
@@ -101,7 +124,7 @@ __global__ void rows_kernel(RowArgs a) {
         if (active) {
             const float* va = vals + ra * n;
             const float* vb = vals + (has_b ? ra + 1 : ra) * n;
-            fft_pass1<M, -1>(t, xch, a.tw, [&](int q) -> float2 {
+            fft_pass1<M, -1>(t, xch, tws, [&](int q) -> float2 {
                 const int qc = q - a.p0;
                 if (qc < 0 || qc >= n) return make_float2(0.f, 0.f);
                 return make_float2(va[qc], has_b ? vb[qc] : 0.f);
@@ -115,7 +138,7 @@ __global__ void rows_kernel(RowArgs a) {
         for (int idx = tid; idx < Kh * nrow; idx += nthr) {
             const int k = idx / nrow;
             const int r = idx - k * nrow;
-            const float2* z = smem + (r >> 1) * (TL + M) + TL;
+            const float2* z = smem + M + (r >> 1) * TS + TL;
             const float2 zk = z[k];
             const float2 zm = cconj(z[(M - k) & (M - 1)]);
             float2 v;
@@ -133,8 +156,7 @@ __global__ void rows_kernel(RowArgs a) {
 template <int M>
 static hipError_t launch_rows_t(const RowArgs& a, int frames, int nchunk, int teams, hipStream_t s) {
     constexpr int T = FftShape<M>::T;
-    const size_t lds = (size_t)teams * (team_lds<M>() + M) * sizeof(float2) +
-                       (size_t)(2 * teams) * a.n * sizeof(float) + 64 * sizeof(float);
+    const size_t lds = rows_lds_bytes(M, a.n, teams);
     allow_large_lds(reinterpret_cast<const void*>(&rows_kernel<M>));
     const int threads = ((teams * T + 63) / 64) * 64;       // whole wavefronts (the reduction uses all lanes)
     hipLaunchKernelGGL(rows_kernel<M>, dim3(nchunk, a.J, frames), dim3(threads), lds, s, a);
@@ -153,8 +175,8 @@ hipError_t launch_rows(int M, const RowArgs& a, int frames, int nchunk, int team
 
 size_t rows_lds_bytes(int M, int n, int teams) {
     const int N1 = M == 32 ? 8 : (M == 64 ? 8 : 16), N2 = M / N1;
-    return (size_t)teams * (N1 * (N2 + 1) + M) * sizeof(float2) + (size_t)(2 * teams) * n * sizeof(float) +
-           64 * sizeof(float);
+    return ((size_t)M + (size_t)teams * (N1 * (N2 + 1) + M + 1)) * sizeof(float2) +
+           (size_t)(2 * teams) * n * sizeof(float) + 64 * sizeof(float);
 }
 
 }  // namespace safr

@@ -42,13 +42,6 @@ bool supported_M(int M) { return M == 32 || M == 64 || M == 128 || M == 256; }
 
 int team_size(int M) { return M == 256 ? 16 : (M == 32 ? 4 : 8); }
 
-// LDS bytes of one output-pass block (must match the launcher in k_out.hip).
-size_t out_lds_bytes(int M, int rows, bool mixed) {
-    const int T = team_size(M);
-    const int N1 = M == 32 ? 8 : (M == 64 ? 8 : 16), N2 = M / N1;
-    const int trows = mixed ? 2 * rows + 2 : rows;
-    return (size_t)(256 / T) * N1 * (N2 + 1) * 8 + (size_t)trows * (M / 2 + 1) * 8 + (size_t)trows * M * 4;
-}
 constexpr size_t kMaxLds = 160 * 1024;
 
 }  // namespace
@@ -576,18 +569,115 @@ safr_status safr_time_stages(safr_plan* p, int frames, const float* wf, float* o
     return SAFR_OK;
 }
 
+namespace {
+
+// average milliseconds of one stage over `iters` synchronised launches of the whole sequence
+safr_status time_stage(safr_plan* p, int frames, const float* wf, float* out, int precision, void* ws, int iters,
+                       hipStream_t s, hipEvent_t* ev, int stage, double* ms) {
+    double acc = 0.0;
+    for (int it = 0; it < iters; ++it) {
+        safr_status st = launch_all(p, frames, wf, out, precision, ws, s, ev);
+        if (st != SAFR_OK) return st;
+        if (hipEventSynchronize(ev[3]) != hipSuccess) return fail(SAFR_ERR_DEVICE, "event synchronisation failed");
+        float t = 0.f;
+        hipEventElapsedTime(&t, ev[stage], ev[stage + 1]);
+        acc += t;
+    }
+    *ms = acc / iters;
+    return SAFR_OK;
+}
+
+}  // namespace
+
+safr_status safr_autotune(safr_plan* p, int frames, const float* wf, float* out, int precision, int iters,
+                          hipStream_t s, int* choice) {
+    if (!p || !wf || !out || iters < 1) return fail(SAFR_ERR_ARG, "bad argument");
+    if (precision != SAFR_FP32 && precision != SAFR_BF16X3) return fail(SAFR_ERR_ARG, "bad precision");
+    if (precision == SAFR_BF16X3 && !p->Apack) return fail(SAFR_ERR_UNSUPPORTED, "BF16 path not available");
+    const size_t need = ws_bytes(p, frames);
+    void* ws = nullptr;
+    if (p->ws_user && p->ws_user_bytes >= need) ws = p->ws_user;
+    else if (p->ws_own_bytes >= need) ws = p->ws_own;
+    else return fail(SAFR_ERR_STATE, "workspace of %zu bytes needed for %d frames", need, frames);
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+    safr_status st = SAFR_OK;
+    const int T = team_size(p->M);
+    // row pass: transform teams per block
+    {
+        int best = p->row_teams;
+        double bt = 1e30;
+        for (int teams : {1, 2, 4, 8, 16}) {
+            if (teams * T > 256 || rows_lds_bytes(p->M, p->n, teams) > kMaxLds || 2 * teams > 2 * p->n) continue;
+            p->row_teams = teams;
+            double ms = 0.0;
+            if ((st = time_stage(p, frames, wf, out, precision, ws, iters, s, ev, 0, &ms)) != SAFR_OK) break;
+            if (ms < bt) { bt = ms; best = teams; }
+        }
+        p->row_teams = best;
+    }
+    // output pass: rows per block
+    if (st == SAFR_OK) {
+        int best = p->out_rows;
+        double bt = 1e30;
+        for (int rows : {2, 4, 8, 16}) {
+            if (rows > p->M || out_lds_bytes(p->M, rows, p->mixed) > kMaxLds) continue;
+            p->out_rows = rows;
+            double ms = 0.0;
+            if ((st = time_stage(p, frames, wf, out, precision, ws, iters, s, ev, 2, &ms)) != SAFR_OK) break;
+            if (ms < bt) { bt = ms; best = rows; }
+        }
+        p->out_rows = best;
+    }
+    // column pass (FP32): frames per block (B reused from registers across them)
+    if (st == SAFR_OK && precision == SAFR_FP32 && frames > 1) {
+        int best = p->col_frames;
+        double bt = 1e30;
+        for (int cf : {1, 2, 4, 8, 16}) {
+            if (cf > frames) continue;
+            p->col_frames = cf;
+            double ms = 0.0;
+            if ((st = time_stage(p, frames, wf, out, precision, ws, iters, s, ev, 1, &ms)) != SAFR_OK) break;
+            if (ms < bt) { bt = ms; best = cf; }
+        }
+        p->col_frames = best;
+    }
+    for (auto& e : ev) hipEventDestroy(e);
+    if (p->gexec) {                      // a captured graph holds the old launch shapes
+        hipGraphExecDestroy(p->gexec);
+        hipGraphDestroy(p->graph);
+        p->gexec = nullptr;
+        p->graph = nullptr;
+    }
+    if (choice) {
+        choice[0] = p->row_teams;
+        choice[1] = p->out_rows;
+        choice[2] = p->col_frames;
+    }
+    return st;
+}
+
 void safr_destroy(safr_plan* p) { free_plan(p); }
 
 safr_status safr_set_option(safr_plan* p, int option, int value) {
     if (!p) return fail(SAFR_ERR_ARG, "plan is NULL");
+    if (p->gexec) {                      // a captured graph holds the old launch shapes
+        hipGraphExecDestroy(p->gexec);
+        hipGraphDestroy(p->graph);
+        p->gexec = nullptr;
+        p->graph = nullptr;
+    }
     switch (option) {
         case 0: p->use_graph = value != 0; return SAFR_OK;
         case 1:
             if (value < 1 || value * team_size(p->M) > 256) return fail(SAFR_ERR_ARG, "bad row team count");
+            if (rows_lds_bytes(p->M, p->n, value) > kMaxLds)
+                return fail(SAFR_ERR_ARG, "%d row teams need more than 160 KiB of LDS", value);
             p->row_teams = value;
             return SAFR_OK;
         case 2:
-            if (value < 2 || value > p->M) return fail(SAFR_ERR_ARG, "bad output rows per block");
+            if (value != 2 && value != 4 && value != 8 && value != 16)
+                return fail(SAFR_ERR_ARG, "output rows per block must be 2, 4, 8 or 16");
             if (out_lds_bytes(p->M, value, p->mixed) > kMaxLds)
                 return fail(SAFR_ERR_ARG, "%d output rows per block need more than 160 KiB of LDS", value);
             p->out_rows = value;

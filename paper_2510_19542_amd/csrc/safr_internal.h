@@ -95,6 +95,7 @@ hipError_t launch_cols(int M, const ColArgs& a, int frames, hipStream_t s);
 hipError_t launch_out(int M, const OutArgs& a, int frames, hipStream_t s);
 hipError_t launch_cols_mfma(int M, const MfmaArgs& a, int frames, int frames_per_block, hipStream_t s);
 size_t rows_lds_bytes(int M, int n, int teams);
+size_t out_lds_bytes(int M, int rows_per_block, bool mixed);
 size_t cols_lds_bytes(int M, int gmax, int L);
 
 // Precompute (FP64): SVD per half-spectrum frequency and the assembly of B.

@@ -30,7 +30,7 @@ SAFR_MLP_PARAMS = 8705
 EXPORTED = [
     "safr_precompute", "safr_reconstruct", "safr_reconstruct_batched", "safr_workspace_size",
     "safr_set_workspace", "safr_plan_info", "safr_export_B", "safr_set_option", "safr_time_stages",
-    "safr_destroy", "safr_last_error",
+    "safr_autotune", "safr_destroy", "safr_last_error",
 ]
 
 
@@ -91,6 +91,7 @@ def lib() -> ctypes.CDLL:
     L.safr_export_B.argtypes = [vp, i, ctypes.POINTER(d), sz]
     L.safr_set_option.argtypes = [vp, i, i]
     L.safr_time_stages.argtypes = [vp, i, vp, vp, i, i, vp, ctypes.POINTER(d)]
+    L.safr_autotune.argtypes = [vp, i, vp, vp, i, i, vp, ctypes.POINTER(i)]
     L.safr_destroy.argtypes = [vp]
     L.safr_destroy.restype = None
     L.safr_last_error.restype = ctypes.c_char_p
@@ -219,6 +220,16 @@ def safr_time_stages(plan: Plan, frames: int, wavefronts, layers, precision: int
     _check(lib().safr_time_stages(plan._as_parameter_, int(frames), _ptr(wavefronts), _ptr(layers), int(precision),
                                   int(iters), _stream(stream), ms))
     return [float(x) for x in ms]
+
+
+def safr_autotune(plan: Plan, frames: int, wavefronts, layers, precision: int = SAFR_FP32, iters: int = 10,
+                  stream=None):
+    """Times the admissible block shapes of each stage and keeps the fastest; returns
+    (row teams, output rows per block, column frames per block)."""
+    ch = (ctypes.c_int * 3)()
+    _check(lib().safr_autotune(plan._as_parameter_, int(frames), _ptr(wavefronts), _ptr(layers), int(precision),
+                               int(iters), _stream(stream), ch))
+    return tuple(int(x) for x in ch)
 
 
 def safr_plan_info(plan: Plan) -> safr_plan_desc:

@@ -225,7 +225,7 @@ def test_tuning_options_do_not_change_results():
     wf = torch.from_numpy(synth.random_wavefronts(geo, 1)[0]).cuda()
     ref = S.reconstruct(plan, wf)
     for teams in (1, 4, 16):
-        for rows in (2, 5, 16, 24):
+        for rows in (2, 4, 8, 16):
             S.safr_set_option(plan, S.SAFR_OPT_ROW_TEAMS, teams)
             S.safr_set_option(plan, S.SAFR_OPT_OUT_ROWS, rows)
             got = S.reconstruct(plan, wf)
@@ -252,3 +252,22 @@ def test_workspace_too_small_is_an_error():
     with pytest.raises(S.SafrError) as e:
         S.safr_reconstruct_batched(plan, 2, wf, out)
     assert e.value.status == S.SAFR_ERR_STATE
+
+
+def test_autotune_picks_valid_shapes_and_keeps_results():
+    torch = _torch()
+    S = _lib()
+    geo = _geo("C2")
+    plan = S.precompute_geometry(geo)
+    F = 4
+    wf = torch.from_numpy(synth.random_wavefronts(geo, F)).cuda()
+    ref = S.reconstruct(plan, wf).cpu().numpy().astype(np.float64)
+    need = S.safr_workspace_size(plan, F)
+    ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+    S.safr_set_workspace(plan, (ws.data_ptr() + 255) & ~255, need)
+    out = torch.empty((F, geo.L, geo.M, geo.M), device="cuda")
+    teams, rows, cf = S.safr_autotune(plan, F, wf, out, S.SAFR_FP32, 2)
+    assert teams in (1, 2, 4, 8, 16) and rows in (2, 4, 8, 16) and 1 <= cf <= F
+    S.safr_reconstruct_batched(plan, F, wf, out)
+    torch.cuda.synchronize()
+    assert rel_l2(out.cpu().numpy(), ref) <= 1e-6
