@@ -124,7 +124,8 @@ safr_status safr_reconstruct(safr_plan* p, const float* wavefronts, float* layer
                              hipStream_t stream);
 
 /*
- * Batched reconstruction of `frames` independent frames: wavefronts
+ * Batched reconstruction of `frames` independent frames (SAFR_BF16X3: plans with
+ * M <= 128 only, otherwise SAFR_ERR_UNSUPPORTED): wavefronts
  * [frames][J][n][n] -> layers [frames][L][M][M].  precision SAFR_FP32 applies B
  * in FP32; SAFR_BF16X3 applies it on BF16 matrix cores with FP32 accumulation
  * and the split correction B_hi D_hi + B_hi D_lo + B_lo D_hi.  Needs a
@@ -158,7 +159,8 @@ safr_status safr_export_B(const safr_plan* p, int group, double* host, size_t co
  *                        (non-default streams only), 0 = launch directly (default);
  *   SAFR_OPT_ROW_TEAMS   transform teams per block of the row pass (2 rows per team);
  *   SAFR_OPT_OUT_ROWS    output rows per block of the output pass (>= 2);
- *   SAFR_OPT_MFMA_FRAMES frames per block of the BF16 apply (16);
+ *   SAFR_OPT_MFMA_FRAMES frames per block of the BF16 apply (4, 8 or 16; default: the
+ *                        largest that fits in LDS);
  *   SAFR_OPT_COL_FRAMES  frames per block of the FP32 column pass (B stays in registers
  *                        across them; 1 = one frame per block);
  *   SAFR_OPT_COL_PREFETCH 1 = the column pass keeps each block's B in registers when

@@ -412,8 +412,36 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
             st = fail(SAFR_ERR_NUMERIC, "non-finite value in the precomputed operator");
             break;
         }
+        // BF16 hi/lo tiles of the real-split B for the matrix-core apply (M <= 128)
+        if (M <= 128) {
+            const int gm = std::max(p->gsize[0], p->gsize[1]);
+            int nf = 0;
+            for (int cand : {16, 8, 4})
+                if (!nf && mfma_lds_bytes(M, cand, gm, L) <= 160 * 1024) nf = cand;
+            if (nf) {
+                p->mfma_frames = nf;
+                size_t tot = 0;
+                for (int gi = 0; gi < p->ngroups; ++gi) {
+                    const int G = p->gsize[gi];
+                    const int lt = std::min(L, 8), ntile = (L + lt - 1) / lt;
+                    int ppm = std::max(1, std::min(16 / (2 * lt), 32 / (2 * G)));
+                    while (ppm & (ppm - 1)) --ppm;             // a power of two, so it divides M
+                    p->mf_lt[gi] = lt;
+                    p->mf_ntile[gi] = ntile;
+                    p->mf_ppm[gi] = ppm;
+                    p->apack_off[gi] = tot;
+                    tot += (size_t)p->Kh * (M / ppm) * ntile * 2 * 64 * 8;
+                }
+                PC_TRY(hipMalloc(&p->Apack, tot * sizeof(uint16_t)));
+                for (int gi = 0; gi < p->ngroups; ++gi)
+                    PC_TRY(launch_pack_bf16(M, L, p->gsize[gi], p->B32 + p->boff32[gi], p->Apack + p->apack_off[gi],
+                                            p->mf_lt[gi], p->mf_ntile[gi], p->mf_ppm[gi], stream));
+                if (st != SAFR_OK) break;
+            }
+        }
         p->ws_own_bytes = ws_bytes(p, 1);
         PC_TRY(hipMalloc(&p->ws_own, p->ws_own_bytes));
+        PC_TRY(hipStreamSynchronize(stream));
 #undef PC_TRY
     } while (0);
     hipFree(W);
@@ -683,7 +711,10 @@ safr_status safr_set_option(safr_plan* p, int option, int value) {
             p->out_rows = value;
             return SAFR_OK;
         case 3:
-            if (value != 16) return fail(SAFR_ERR_ARG, "frames per MFMA block must be 16");
+            if (value != 4 && value != 8 && value != 16) return fail(SAFR_ERR_ARG, "frames per MFMA block: 4, 8 or 16");
+            if (!p->Apack) return fail(SAFR_ERR_UNSUPPORTED, "BF16 path not available for this plan");
+            if (mfma_lds_bytes(p->M, value, std::max(p->gsize[0], p->gsize[1]), p->L) > kMaxLds)
+                return fail(SAFR_ERR_ARG, "%d frames per MFMA block need more than 160 KiB of LDS", value);
             p->mfma_frames = value;
             return SAFR_OK;
         case 4:
@@ -768,11 +799,20 @@ safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, in
             ma.ntile[gi] = p->mf_ntile[gi];
             ma.ppm[gi] = p->mf_ppm[gi];
         }
+        ma.mom = mom;
+        ma.Xh = p->Xh;
+        ma.Yh = p->Yh;
+        for (int i = 0; i < 3; ++i) {
+            ma.tt_b[i] = p->tt_b[i];
+            ma.tt_c[i] = p->tt_c[i];
+        }
         ma.n = p->n;
         ma.J = p->J;
         ma.L = p->L;
         ma.p0 = p->p0;
         ma.frames = frames;
+        ma.nchunk = nchunk;
+        ma.gmax = gmax;
         HIP_TRY(launch_cols_mfma(p->M, ma, frames, p->mfma_frames, s));
     }
     if (ev) HIP_TRY(hipEventRecord(ev[2], s));

@@ -67,12 +67,16 @@ struct OutArgs {
 // BF16 hi/lo split apply on matrix cores (batched path).
 struct MfmaArgs {
     const float2* R;
-    const uint16_t* Apack;      // packed real-split B tiles, hi and lo
+    const uint16_t* Apack;      // packed real-split B tiles, hi and lo (bf16 bit patterns)
     float2* C;
     const float2* tw;
+    const float* mom;
+    const float2* Xh;
+    const float2* Yh;
+    float tt_b[3], tt_c[3];
     GroupSet groups;
     size_t a_off[2];            // per-group offset into Apack (uint16 elements)
-    int n, J, L, p0, frames;
+    int n, J, L, p0, frames, nchunk, gmax;
     int lt[2];                  // layers per tile (per group)
     int ntile[2];               // layer tiles per group
     int ppm[2];                 // frequencies packed per matrix op (per group)
@@ -96,6 +100,7 @@ hipError_t launch_out(int M, const OutArgs& a, int frames, hipStream_t s);
 hipError_t launch_cols_mfma(int M, const MfmaArgs& a, int frames, int frames_per_block, hipStream_t s);
 size_t rows_lds_bytes(int M, int n, int teams);
 size_t out_lds_bytes(int M, int rows_per_block, bool mixed);
+size_t mfma_lds_bytes(int M, int frames_per_block, int gmax, int L);
 size_t cols_lds_bytes(int M, int gmax, int L);
 
 // Precompute (FP64): SVD per half-spectrum frequency and the assembly of B.
