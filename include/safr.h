@@ -185,6 +185,47 @@ safr_status safr_time_stages(safr_plan* p, int frames, const float* wavefronts, 
 safr_status safr_autotune(safr_plan* p, int frames, const float* wavefronts, float* layers, int precision,
                           int iters, hipStream_t stream, int* choice);
 
+/* ---- Learned spectral filter ------------------------------------------------------------
+ * The learned filter replaces Tikhonov's filter factors (Sec. 3.1 admits any regularising
+ * filter): g_r = phi_r / s_r, phi = MLP(|n|/(2T), log10 s_r, log10 noise, sum_l gamma_l |V_lr|^2),
+ * a 4 -> 64 -> 64 -> 64 -> 1 network (exact GELU, logistic output), SAFR_MLP_PARAMS floats
+ * packed W1 (64x4), b1, W2 (64x64), b2, W3, b3, w4 (64), b4 with W[out][in].
+ *
+ * The trainer is built for one geometry with one kind of guide star.  Frames are generated
+ * by the caller as random draws only; the trainer applies the tomography operator in its
+ * Fourier form (layer spectra F_l = amp_l z_l, wavefront spectra sum_l exp(2 pi i n . s_gl / M)
+ * F_l plus eta sigma_n M z_g, sigma_n the expected wavefront RMS) and stores, per frame and
+ * half-spectrum frequency, the statistics of the full-grid layer residual, which is quadratic
+ * in phi.  Training minimises the frame-averaged relative residual with Adam, in FP32.
+ */
+typedef struct safr_trainer safr_trainer;
+
+/* amp: host [L][M/2+1][M] layer amplitudes; room for max_frames frames.  Synchronises. */
+safr_status safr_trainer_create(const safr_geometry* geo, int L, const double* heights,
+                                const double* weights, const float* amp, int max_frames,
+                                safr_trainer** out, hipStream_t stream);
+/* zl: device complex64 [count][L][M/2+1][M], zn: device complex64 [count][J][M/2+1][M]
+ * (complex normal, E|z|^2 = 1); eta: host [count] noise levels (> 0).  Appends frames. */
+safr_status safr_trainer_add_frames(safr_trainer* t, int count, const void* zl, const void* zn,
+                                    const float* eta, hipStream_t stream);
+/* Copies parameters in (and resets the Adam state) or out (host arrays of SAFR_MLP_PARAMS). */
+safr_status safr_trainer_set_params(safr_trainer* t, const float* params);
+safr_status safr_trainer_get_params(const safr_trainer* t, float* params);
+/* One Adam step (lr; beta1 0.9, beta2 0.999, eps 1e-8) on the frames listed (host indices);
+ * loss (may be NULL) receives the batch loss before the step (synchronises when requested). */
+safr_status safr_trainer_step(safr_trainer* t, int nb, const int* frames, float lr, double* loss,
+                              hipStream_t stream);
+/* Gradient of the batch loss with respect to the parameters (host grad, may be NULL), no update. */
+safr_status safr_trainer_gradient(safr_trainer* t, int nb, const int* frames, float* grad, double* loss,
+                                  hipStream_t stream);
+int safr_trainer_frames(const safr_trainer* t);
+void safr_trainer_destroy(safr_trainer* t);
+
+/* BF16 inference of the network on device feature rows feats[rows][4] (the third feature is
+ * replaced by log10 noise) into device phi[rows]; params on the host.  Synchronises. */
+safr_status safr_mlp_infer(const float* params, const float* feats, int rows, double noise, float* phi,
+                           hipStream_t stream);
+
 /* Releases the plan and its device memory (NULL is a no-op). */
 void safr_destroy(safr_plan* p);
 

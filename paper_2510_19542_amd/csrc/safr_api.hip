@@ -46,6 +46,13 @@ constexpr size_t kMaxLds = 160 * 1024;
 
 }  // namespace
 
+namespace safr {
+safr_status set_error(safr_status st, const char* msg) {
+    g_last_error = msg;
+    return st;
+}
+}  // namespace safr
+
 struct safr_plan {
     int n = 0, M = 0, J = 0, L = 0, Kh = 0;
     int ngroups = 0, mixed = 0;
@@ -319,6 +326,7 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
     double* sig = nullptr;
     float* feats = nullptr;
     float* phi = nullptr;
+    float* mlp_dev = nullptr;
     int* dbad = nullptr;
     do {
         size_t total = 0, total32 = 0;
@@ -369,6 +377,8 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
         if (geo->filter == SAFR_FILTER_MLP) {
             PC_TRY(hipMalloc(&feats, (size_t)H * Cm * 4 * sizeof(float)));
             PC_TRY(hipMalloc(&phi, (size_t)H * Cm * sizeof(float)));
+            PC_TRY(hipMalloc(&mlp_dev, SAFR_MLP_PARAMS * sizeof(float)));
+            PC_TRY(hipMemcpy(mlp_dev, geo->mlp, SAFR_MLP_PARAMS * sizeof(float), hipMemcpyHostToDevice));
         }
         for (int gi = 0; gi < p->ngroups && st == SAFR_OK; ++gi) {
             PrecompArgs a{};
@@ -399,8 +409,8 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
             a.bad = dbad;
             PC_TRY(launch_svd(a, stream));
             if (geo->filter == SAFR_FILTER_MLP) {
-                st = fail(SAFR_ERR_UNSUPPORTED, "learned filter not available in this build");
-                break;
+                const int C = std::min(a.G, L);
+                PC_TRY(launch_mlp_infer(mlp_dev, feats, phi, H * C, (float)a.log10_noise, stream));
             }
             PC_TRY(launch_assemble(a, stream));
         }
@@ -449,6 +459,7 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
     hipFree(sig);
     hipFree(feats);
     hipFree(phi);
+    hipFree(mlp_dev);
     hipFree(dbad);
     if (st != SAFR_OK) {
         free_plan(p);

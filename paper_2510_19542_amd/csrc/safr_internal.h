@@ -121,8 +121,9 @@ struct PrecompArgs {
 };
 hipError_t launch_svd(const PrecompArgs& a, hipStream_t s);
 hipError_t launch_assemble(const PrecompArgs& a, hipStream_t s);
-hipError_t launch_mlp_infer(const float* params_bf16_layout, const float* feats, float* phi, int rows,
+hipError_t launch_mlp_infer(const float* params, const float* feats, float* phi, int rows, float log10_noise,
                             hipStream_t s);
+safr_status set_error(safr_status st, const char* msg);
 hipError_t launch_pack_bf16(int M, int L, int G, const float2* B32, uint16_t* Apack, int lt, int ntile,
                             int ppm, hipStream_t s);
 

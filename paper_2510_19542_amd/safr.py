@@ -31,6 +31,9 @@ EXPORTED = [
     "safr_precompute", "safr_reconstruct", "safr_reconstruct_batched", "safr_workspace_size",
     "safr_set_workspace", "safr_plan_info", "safr_export_B", "safr_set_option", "safr_time_stages",
     "safr_autotune", "safr_destroy", "safr_last_error",
+    # learned filter (bound in learn.py)
+    "safr_trainer_create", "safr_trainer_add_frames", "safr_trainer_set_params", "safr_trainer_get_params",
+    "safr_trainer_step", "safr_trainer_gradient", "safr_trainer_frames", "safr_trainer_destroy", "safr_mlp_infer",
 ]
 
 
@@ -95,7 +98,7 @@ def lib() -> ctypes.CDLL:
     L.safr_destroy.argtypes = [vp]
     L.safr_destroy.restype = None
     L.safr_last_error.restype = ctypes.c_char_p
-    for name in EXPORTED:
+    for name in EXPORTED[:13]:
         if name not in ("safr_destroy", "safr_last_error"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L

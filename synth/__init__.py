@@ -7,3 +7,4 @@ from .configs import (ARCSEC, LGS, NGS, Geometry, PRESETS, circular_pupil, prese
                       c1, c2, c5_small, c5_mid, c5_big)
 from .atmosphere import (frame, frames, random_wavefronts, rng_for, simulate_wavefronts,  # noqa: F401
                          truth_layers, truth_screens, vk_screen)
+from .learning import learn_draws, periodic_layers, vk_amplitude  # noqa: F401,E402

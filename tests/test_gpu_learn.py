@@ -1,0 +1,117 @@
+"""Learned spectral filter on the GPU: gradients and BF16 inference against the FP64 oracle,
+and the gain of the trained network over the Tikhonov filter on held-out frames."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import learn as LR
+from oracle import mlp as N
+from oracle import safr as O
+
+pytestmark = pytest.mark.gpu
+
+
+def _mods():
+    import torch
+    from paper_2510_19542_amd import learn as Lrn
+    from paper_2510_19542_amd import safr as S
+    assert torch.cuda.is_available()
+    S.lib()
+    return torch, S, Lrn
+
+
+def _fs(geo):
+    return LR.frequency_svd(M=geo.M, pitch=geo.pitch, stars=geo.stars, h_lgs=geo.h_lgs, heights=geo.heights,
+                            weights=geo.weights, beta=geo.beta)
+
+
+def test_training_gradient_matches_oracle():
+    """GPU FP32 loss and gradient of a minibatch vs the oracle's FP64 analytic ones (rel <= 1e-4 / 2e-3)."""
+    torch, S, Lrn = _mods()
+    geo = synth.preset("C1")
+    amp = synth.vk_amplitude(geo)
+    tr = Lrn.Trainer(geo, amp.reshape(geo.L, -1), 8)
+    Lrn.add_seeded_frames(tr, 100, 8)
+    p = Lrn.init_params(3)
+    tr.set_params(p)
+    frames = [1, 4, 6]
+    g, loss = tr.gradient(frames)
+    zl, zn, eta = synth.learn_draws(geo, 100, 8)
+    idx = np.array(frames)
+    lref, gref = LR.batch_loss_and_grad(p.astype(np.float64), _fs(geo), amp, zl[idx], zn[idx],
+                                        eta[idx].astype(np.float32).astype(np.float64), geo.M)
+    assert abs(loss - lref) <= 1e-4 * abs(lref), (loss, lref)
+    err = np.linalg.norm(g - gref) / np.linalg.norm(gref)
+    print(f"gradient rel error {err:.2e}, loss {loss:.6e} vs {lref:.6e}")
+    assert err <= 2e-3
+
+
+def test_bf16_inference_matches_oracle_emulation():
+    """BF16 matrix-core inference vs the oracle evaluating the same bf16 roundings in FP64."""
+    torch, S, Lrn = _mods()
+    rng = np.random.default_rng(1)
+    p = Lrn.init_params(5)
+    X = np.stack([rng.uniform(0, 2, 1000), rng.uniform(-3, 0.3, 1000), np.zeros(1000), rng.uniform(0, 1, 1000)], 1)
+    noise = 0.02
+    feats = torch.from_numpy(X.astype(np.float32)).cuda()
+    phi = torch.empty(1000, device="cuda")
+    Lrn.mlp_infer(p, feats, 1000, noise, phi)
+    X2 = X.copy()
+    X2[:, 2] = np.log10(noise)
+    want_bf = N.forward(p.astype(np.float64), X2.astype(np.float32).astype(np.float64), bf16=True)
+    want = N.forward(p.astype(np.float64), X2, bf16=False)
+    got = phi.cpu().numpy()
+    print(f"max |phi - bf16 oracle| {np.max(np.abs(got - want_bf)):.2e}, vs FP64 {np.max(np.abs(got - want)):.2e}")
+    assert np.max(np.abs(got - want_bf)) <= 2e-3
+    assert np.max(np.abs(got - want)) <= 2e-2
+
+
+def test_learned_B_matches_oracle():
+    """B from the GPU precompute with the learned filter vs the oracle's with the same bf16 roundings."""
+    torch, S, Lrn = _mods()
+    geo = synth.preset("C1")
+    p = Lrn.init_params(9)
+    plan = S.precompute_geometry(geo, filter=S.SAFR_FILTER_MLP, mlp=p, noise=0.01)
+    ref = O.precompute_geometry(geo, mlp_params=p.astype(np.float64), eta=np.float32(0.01), mlp_bf16=True)
+    got = S.safr_export_B(plan, 0)
+    want = np.transpose(ref.groups[0].B[:, : geo.M // 2 + 1], (1, 0, 2, 3))
+    err = np.max(np.abs(got - want)) / np.max(np.abs(want))
+    print(f"learned B max rel error {err:.2e}")
+    assert err <= 1e-2
+
+
+def _heldout(geo, seeds, eta):
+    """Periodic-exact held-out frames: truth layers, exact forward operator, white noise (eta x RMS)."""
+    c = O.cone_coefficients(geo.heights, 0, geo.h_lgs)
+    sh = O.layer_shifts(geo.stars, geo.heights, c, geo.pitch)
+    out = []
+    for s in seeds:
+        truth = synth.periodic_layers(geo, s)
+        wf = O.forward_fourier(truth, sh)
+        rng = np.random.default_rng([19542, 4, s, 9])
+        rms = np.sqrt(np.mean(wf ** 2, axis=(1, 2)))
+        wf = wf + eta * rms[:, None, None] * rng.standard_normal(wf.shape)
+        out.append((wf.astype(np.float32), truth))
+    return out
+
+
+def test_learned_filter_beats_tikhonov_on_heldout_frames():
+    torch, S, Lrn = _mods()
+    base = synth.preset("C1")
+    geo = base.replace(n=base.M)                     # periodic-exact: data on the whole grid
+    params, hist = Lrn.train(geo, frames=3000, epochs=3, batch=16, lr=2e-3, seed=1)
+    assert np.all(np.isfinite(params))
+    for eta in (0.005, 0.01, 0.02, 0.05):
+        frames = _heldout(geo, range(20000, 20006), eta)
+        tik = S.precompute_geometry(geo, pupil=None)
+        lrn = S.precompute_geometry(geo, pupil=None, filter=S.SAFR_FILTER_MLP, mlp=params, noise=eta)
+        et, el = [], []
+        for wf, truth in frames:
+            x = torch.from_numpy(wf).cuda()
+            rt = S.reconstruct(tik, x).cpu().numpy()
+            rl = S.reconstruct(lrn, x).cpu().numpy()
+            tz = truth - truth.mean(axis=(1, 2), keepdims=True)
+            et.append(np.linalg.norm(rt - rt.mean(axis=(1, 2), keepdims=True) - tz) / np.linalg.norm(tz))
+            el.append(np.linalg.norm(rl - rl.mean(axis=(1, 2), keepdims=True) - tz) / np.linalg.norm(tz))
+        print(f"eta {eta}: Tikhonov(alpha={geo.alpha}) {np.mean(et):.4f}  learned {np.mean(el):.4f}")
+        assert np.mean(el) < np.mean(et)
