@@ -185,9 +185,31 @@ safr_status safr_time_stages(safr_plan* p, int frames, const float* wavefronts, 
 safr_status safr_autotune(safr_plan* p, int frames, const float* wavefronts, float* layers, int precision,
                           int iters, hipStream_t stream, int* choice);
 
+/* ---- Mixed-size batches -------------------------------------------------------------------
+ * A bundle of plans (different geometries and grid sizes), each with its own frame count.
+ * safr_multi_execute reconstructs every entry's frames (wavefronts[i]: [frames[i]][J][n][n],
+ * layers[i]: [frames[i]][L][M][M] of plan i) in one HIP graph launch on `stream`: the first
+ * call (and any call with other buffers) captures the entries' launch sequences as parallel
+ * branches forked from and joined back to `stream`, later calls replay the graph (on the
+ * legacy default stream the sequences are launched directly).  The bundle owns one workspace
+ * per entry.  Plans must outlive the bundle; one plan may serve several entries (launches only
+ * read it).  Errors: SAFR_ERR_ARG (NULL, count < 1, frames < 1), SAFR_ERR_UNSUPPORTED (BF16X3
+ * for a plan without the matrix-core path), SAFR_ERR_DEVICE (allocation, capture, launch). */
+typedef struct safr_multi safr_multi;
+safr_status safr_multi_create(safr_plan* const* plans, const int* frames, int count, int precision,
+                              safr_multi** out);
+safr_status safr_multi_execute(safr_multi* m, const float* const* wavefronts, float* const* layers,
+                               hipStream_t stream);
+/* safr_autotune for every entry with its frame count and buffers (overwrites layers); a plan
+ * shared by several entries keeps the choice made for the last of them. */
+safr_status safr_multi_autotune(safr_multi* m, const float* const* wavefronts, float* const* layers,
+                                int iters, hipStream_t stream);
+void safr_multi_destroy(safr_multi* m);
+
 /* ---- Learned spectral filter ------------------------------------------------------------
  * The learned filter replaces Tikhonov's filter factors (Sec. 3.1 admits any regularising
- * filter): g_r = phi_r / s_r, phi = MLP(|n|/(2T), log10 s_r, log10 noise, sum_l gamma_l |V_lr|^2),
+ * filter): g_r = phi_r / s_r for s_r > sqrt(eps) s_1 (else 0),
+ * phi = MLP(|n|/(2T), log10 s_r, log10 noise, sum_l gamma_l |V_lr|^2),
  * a 4 -> 64 -> 64 -> 64 -> 1 network (exact GELU, logistic output), SAFR_MLP_PARAMS floats
  * packed W1 (64x4), b1, W2 (64x64), b2, W3, b3, w4 (64), b4 with W[out][in].
  *

@@ -15,7 +15,7 @@ quadratic in phi at every frequency:
     y_r  = U_r^H d,
     Q_rq = Re(conj(y_r) y_q sum_l s_l^2 conj(V_lr) V_lq) / (sigma_r sigma_q),
     c_r  = Re(y_r sum_l conj(F_l) s_l V_lr) / sigma_r.
-Singular values at or below the rank tolerance get no filter (rows zeroed).
+Singular values at or below the learned filter's cutoff sqrt(eps) sigma_1 get no filter.
 The frame loss is sum_n w_n (...) / Z with w_n the half-spectrum multiplicity
 (2 for 0 < k < M/2, 1 for k = 0, 0 on the Nyquist row/column) and
 Z = sum_n w_n sum_l amp_l(n)^2 (the expected |F|^2).
@@ -87,8 +87,7 @@ def statistics(fs, amp, zl, zn, eta, M):
     G, L = fs["G"], fs["L"]
     Fl, D = wavefront_spectra(fs, amp, zl, zn, eta, M)
     y = np.einsum("kjgr,fgkj->fkjr", np.conj(U), D)                  # U_r^H d
-    tol = O.rank_tolerance(sig, G, L)
-    ok = sig > tol
+    ok = sig > O.learned_cutoff(sig)
     inv = np.where(ok, 1.0 / np.where(ok, sig, 1.0), 0.0)            # (K, J, r)
     W = np.einsum("kjl,kjlr,kjlq->kjrq", s ** 2, np.conj(V), V)
     Q = np.real(np.conj(y)[..., :, None] * y[..., None, :] * W[None]) * inv[None, ..., :, None] * inv[None, ..., None, :]

@@ -207,6 +207,17 @@ def rank_tolerance(sigma: np.ndarray, G: int, L: int) -> np.ndarray:
     return max(G, L) * EPS * sigma[..., :1]
 
 
+def learned_cutoff(sigma: np.ndarray) -> np.ndarray:
+    """sqrt(eps) * sigma_1: below it the learned filter treats a singular value as zero.
+
+    A filter factor phi in (0, 1) does not vanish as sigma -> 0, so phi / sigma would
+    turn singular values at rounding level (exactly rank-deficient frequencies) into
+    gains of order 1 / eps; singular directions below sqrt(eps) sigma_1 are not
+    resolved to half the working precision and are dropped instead.
+    """
+    return np.sqrt(EPS) * sigma[..., :1]
+
+
 def tikhonov_filter(sigma: np.ndarray, alpha: float, G: int, L: int) -> np.ndarray:
     """g(s) = s / (s^2 + alpha) (Sec. 3.1); alpha = 0 gives 1/s above the rank tolerance."""
     if alpha > 0.0:
@@ -307,8 +318,7 @@ def precompute(*, n: int, M: int, pitch: float, stars, h_lgs: float, heights, we
         else:
             feats = mlp_features(NX, NY, T, sig, V, gamma, eta)
             phi = np.asarray(phi_fn(feats.reshape(-1, 4))).reshape(sig.shape)
-            tol = rank_tolerance(sig, G, L)
-            ok = sig > tol
+            ok = sig > learned_cutoff(sig)
             g = np.where(ok, phi / np.where(ok, sig, 1.0), 0.0)
         R = regularised_inverse(U, sig, V, g)                                     # (M,M,L,G)
         scale = layer_scale(NX, NY, c, gamma, T, beta)                            # (M,M,L)

@@ -60,7 +60,7 @@ __global__ void learn_setup_kernel(LearnSetupArgs a) {
     const double* sg = a.sigma + (size_t)h * C;
     double smax = 0.0;
     for (int c = 0; c < C; ++c) smax = fmax(smax, sg[c]);
-    const double tol = (double)(G > L ? G : L) * 2.220446049250313e-16 * smax;
+    const double tol = kSqrtEps * smax;                 // the learned filter's cutoff
     LearnFreq* fq = a.freq;
     const size_t H = (size_t)Kh * M;
     for (int c = 0; c < r; ++c) {

@@ -13,7 +13,9 @@
 //     G <  L (U = Q, V = W / sigma):   s_l sum_c W[l, c] h_c conj(Q[g, c]),
 //   with h_c = g(sigma_c) / sigma_c: Tikhonov 1 / (sigma^2 + alpha); alpha = 0
 //   gives 1 / sigma^2 above the rank tolerance max(G, L) eps sigma_1; the learned
-//   filter gives phi_c / sigma^2 above the tolerance.
+//   filter gives phi_c / sigma^2 above sqrt(eps) sigma_1 (a factor phi in (0, 1)
+//   does not vanish as sigma -> 0, so rounding-level singular values of exactly
+//   rank-deficient frequencies would otherwise become gains of order 1 / eps).
 // The k = 0 column is mirrored (B(-j, 0) = conj B(j, 0)) so that B is exactly
 // Hermitian, and the Nyquist row and column are zero.
 #include <cmath>
@@ -156,7 +158,7 @@ __global__ void assemble_kernel(PrecompArgs a) {
     for (int c = 0; c < C; ++c) {
         const double s = sg[c];
         double v;
-        if (a.phi) v = s > tol ? (double)a.phi[(size_t)hs * C + c] / (s * s) : 0.0;
+        if (a.phi) v = s > kSqrtEps * smax ? (double)a.phi[(size_t)hs * C + c] / (s * s) : 0.0;
         else if (a.alpha > 0.0) v = 1.0 / (s * s + a.alpha);
         else v = s > tol ? 1.0 / (s * s) : 0.0;
         hv[c] = v;

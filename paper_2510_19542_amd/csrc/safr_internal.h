@@ -12,6 +12,7 @@ namespace safr {
 constexpr int kMaxG = SAFR_MAX_STARS_PER_GROUP;
 constexpr int kMaxL = SAFR_MAX_LAYERS;
 constexpr int kMaxJ = 2 * kMaxG;
+constexpr double kSqrtEps = 1.4901161193847656e-08;   // 2^-26: the learned filter's relative cutoff
 
 // Per-group description passed by value to the column kernel.
 struct GroupArgs {

@@ -32,7 +32,7 @@ def test_training_gradient_matches_oracle():
     amp = synth.vk_amplitude(geo)
     tr = Lrn.Trainer(geo, amp.reshape(geo.L, -1), 8)
     Lrn.add_seeded_frames(tr, 100, 8)
-    p = Lrn.init_params(3)
+    p = synth.mlp_init(3)
     tr.set_params(p)
     frames = [1, 4, 6]
     g, loss = tr.gradient(frames)
@@ -50,7 +50,7 @@ def test_bf16_inference_matches_oracle_emulation():
     """BF16 matrix-core inference vs the oracle evaluating the same bf16 roundings in FP64."""
     torch, S, Lrn = _mods()
     rng = np.random.default_rng(1)
-    p = Lrn.init_params(5)
+    p = synth.mlp_init(5)
     X = np.stack([rng.uniform(0, 2, 1000), rng.uniform(-3, 0.3, 1000), np.zeros(1000), rng.uniform(0, 1, 1000)], 1)
     noise = 0.02
     feats = torch.from_numpy(X.astype(np.float32)).cuda()
@@ -66,17 +66,19 @@ def test_bf16_inference_matches_oracle_emulation():
     assert np.max(np.abs(got - want)) <= 2e-2
 
 
-def test_learned_B_matches_oracle():
-    """B from the GPU precompute with the learned filter vs the oracle's with the same bf16 roundings."""
+@pytest.mark.parametrize("name,seed,eta", [("C1", 9, 0.01), ("C5-S", 11, 0.02)])
+def test_learned_B_matches_oracle(name, seed, eta):
+    """B from the GPU precompute with the learned filter vs the oracle's with the same bf16 roundings
+    (the 3-layer case has exactly rank-deficient frequencies with rounding-level singular values)."""
     torch, S, Lrn = _mods()
-    geo = synth.preset("C1")
-    p = Lrn.init_params(9)
-    plan = S.precompute_geometry(geo, filter=S.SAFR_FILTER_MLP, mlp=p, noise=0.01)
-    ref = O.precompute_geometry(geo, mlp_params=p.astype(np.float64), eta=np.float32(0.01), mlp_bf16=True)
+    geo = synth.preset(name)
+    p = synth.mlp_init(seed)
+    plan = S.precompute_geometry(geo, filter=S.SAFR_FILTER_MLP, mlp=p, noise=eta)
+    ref = O.precompute_geometry(geo, mlp_params=p.astype(np.float64), eta=np.float32(eta), mlp_bf16=True)
     got = S.safr_export_B(plan, 0)
     want = np.transpose(ref.groups[0].B[:, : geo.M // 2 + 1], (1, 0, 2, 3))
     err = np.max(np.abs(got - want)) / np.max(np.abs(want))
-    print(f"learned B max rel error {err:.2e}")
+    print(f"{name}: learned B max rel error {err:.2e}")
     assert err <= 1e-2
 
 

@@ -60,7 +60,7 @@ def test_quadratic_form_equals_direct_residual():
     Fl, D = LR.wavefront_spectra(fs, amp, zl, zn, eta, M)
     phi = RNG.uniform(0, 1, Q.shape[:-1])
     sig = fs["sigma"]
-    ok = sig > O.rank_tolerance(sig, 4, 2)
+    ok = sig > O.learned_cutoff(sig)
     g = np.where(ok, phi / np.where(ok, sig, 1.0), 0.0)               # (F, K, J, r)
     R = np.einsum("kjlr,fkjr,kjgr->fkjlg", fs["V"], g, np.conj(fs["U"]))
     b = fs["s"][None, :, :, :, None] * R

@@ -127,3 +127,32 @@ def test_forward_range(bf16):
     p = _params()
     phi = N.forward(p, RNG.standard_normal((100, 4)), bf16=bf16)
     assert np.all((phi > 0) & (phi < 1))
+
+
+def test_learned_branch_with_unit_phi_is_library_pinv_with_half_precision_cutoff():
+    """phi = 1 turns g = phi / sigma into the pseudo-inverse with relative cutoff sqrt(eps): on the
+    8 m / 4-star / 3-layer geometry (rank 2 along the frequency axes) B_n = diag(s_l) pinv(A_n)
+    with numpy's pinv at rcond = sqrt(eps), frequencies with rounding-level singular values included."""
+    import synth
+    geo = synth.preset("C5-S")
+    got = O.precompute_geometry(geo, phi_fn=lambda F: np.ones(len(F)))
+    M, T = geo.M, geo.T
+    gamma = O.normalise_weights(geo.weights)
+    c = O.cone_coefficients(geo.heights, 0, geo.h_lgs)
+    nidx, keep = O.shifted_index(M)
+    stars = np.asarray(geo.stars, dtype=np.float64)[:, :2]
+    rank_deficient = 0
+    # includes (29, 0), (0, 35), (39, 0): rank 2 with a smallest singular value at rounding level
+    # that happens to exceed max(G, L) eps sigma_1
+    for j, k in [(j, k) for j in (0, 1, 5, 31, 33, 40) for k in (0, 3, 17, 60)] + [(29, 0), (0, 35), (39, 0)]:
+        if not (keep[j] and keep[k]):
+            continue
+        A = O.tomography_matrix(np.array([[nidx[j]]]), np.array([[nidx[k]]]), stars, geo.heights, c, gamma, T,
+                                geo.beta)[0, 0]
+        sv = np.linalg.svd(A, compute_uv=False)
+        rank_deficient += int(sv[-1] < 1e-12 * sv[0])
+        s = O.layer_scale(np.array([[nidx[j]]]), np.array([[nidx[k]]]), c, gamma, T, geo.beta)[0, 0]
+        want = s[:, None] * np.linalg.pinv(A, rcond=np.sqrt(np.finfo(float).eps))
+        B = got.groups[0].B[j, k]
+        assert np.max(np.abs(B - want)) <= 1e-10 * np.max(np.abs(want)), (j, k)
+    assert rank_deficient >= 3
