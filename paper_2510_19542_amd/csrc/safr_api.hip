@@ -698,6 +698,154 @@ safr_status safr_autotune(safr_plan* p, int frames, const float* wf, float* out,
 
 void safr_destroy(safr_plan* p) { free_plan(p); }
 
+}  // extern "C"
+
+struct safr_multi {
+    int count = 0, precision = SAFR_FP32;
+    std::vector<safr_plan*> plans;
+    std::vector<int> frames;
+    std::vector<void*> ws;
+    std::vector<hipStream_t> side;          // one per entry after the first
+    std::vector<hipEvent_t> done;
+    hipEvent_t fork = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<const float*> g_wf;
+    std::vector<float*> g_out;
+    hipStream_t g_stream = nullptr;
+};
+
+namespace {
+
+void free_multi(safr_multi* m) {
+    if (!m) return;
+    if (m->exec) hipGraphExecDestroy(m->exec);
+    if (m->graph) hipGraphDestroy(m->graph);
+    for (void* w : m->ws) hipFree(w);
+    for (hipStream_t st : m->side) hipStreamDestroy(st);
+    for (hipEvent_t e : m->done) hipEventDestroy(e);
+    if (m->fork) hipEventDestroy(m->fork);
+    delete m;
+}
+
+// every entry's launch sequence, entry 0 on `s`, the others on side streams forked from and joined to `s`
+safr_status multi_launch(safr_multi* m, const float* const* wf, float* const* out, hipStream_t s) {
+    HIP_TRY(hipEventRecord(m->fork, s));
+    for (int i = 1; i < m->count; ++i) {
+        HIP_TRY(hipStreamWaitEvent(m->side[i - 1], m->fork, 0));
+        safr_status st = launch_all(m->plans[i], m->frames[i], wf[i], out[i], m->precision, m->ws[i], m->side[i - 1]);
+        if (st != SAFR_OK) return st;
+        HIP_TRY(hipEventRecord(m->done[i - 1], m->side[i - 1]));
+    }
+    safr_status st = launch_all(m->plans[0], m->frames[0], wf[0], out[0], m->precision, m->ws[0], s);
+    if (st != SAFR_OK) return st;
+    for (int i = 1; i < m->count; ++i) HIP_TRY(hipStreamWaitEvent(s, m->done[i - 1], 0));
+    return SAFR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+safr_status safr_multi_create(safr_plan* const* plans, const int* frames, int count, int precision,
+                              safr_multi** out) {
+    if (!out) return fail(SAFR_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!plans || !frames || count < 1) return fail(SAFR_ERR_ARG, "need at least one plan");
+    if (precision != SAFR_FP32 && precision != SAFR_BF16X3) return fail(SAFR_ERR_ARG, "bad precision");
+    for (int i = 0; i < count; ++i) {
+        if (!plans[i] || frames[i] < 1) return fail(SAFR_ERR_ARG, "entry %d: bad plan or frame count", i);
+        if (precision == SAFR_BF16X3 && !plans[i]->Apack)
+            return fail(SAFR_ERR_UNSUPPORTED, "entry %d: BF16 path not available for its plan", i);
+    }
+    safr_multi* m = new safr_multi();
+    m->count = count;
+    m->precision = precision;
+    for (int i = 0; i < count; ++i) {
+        m->plans.push_back(plans[i]);
+        m->frames.push_back(frames[i]);
+        void* w = nullptr;
+        hipError_t e = hipMalloc(&w, ws_bytes(plans[i], frames[i]));
+        if (e != hipSuccess) {
+            free_multi(m);
+            return fail(SAFR_ERR_DEVICE, "workspace allocation failed: %s", hipGetErrorString(e));
+        }
+        m->ws.push_back(w);
+        if (i > 0) {
+            hipStream_t st = nullptr;
+            hipEvent_t ev = nullptr;
+            if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+                free_multi(m);
+                return fail(SAFR_ERR_DEVICE, "stream or event creation failed");
+            }
+            m->side.push_back(st);
+            m->done.push_back(ev);
+        }
+    }
+    if (hipEventCreateWithFlags(&m->fork, hipEventDisableTiming) != hipSuccess) {
+        free_multi(m);
+        return fail(SAFR_ERR_DEVICE, "event creation failed");
+    }
+    *out = m;
+    return SAFR_OK;
+}
+
+safr_status safr_multi_execute(safr_multi* m, const float* const* wf, float* const* out, hipStream_t s) {
+    if (!m || !wf || !out) return fail(SAFR_ERR_ARG, "NULL argument");
+    for (int i = 0; i < m->count; ++i)
+        if (!wf[i] || !out[i]) return fail(SAFR_ERR_ARG, "entry %d: NULL buffer", i);
+    if (s == nullptr) return multi_launch(m, wf, out, s);       // the legacy stream cannot be captured
+    bool hit = m->exec && m->g_stream == s;
+    for (int i = 0; hit && i < m->count; ++i) hit = m->g_wf[i] == wf[i] && m->g_out[i] == out[i];
+    if (!hit) {
+        if (m->exec) hipGraphExecDestroy(m->exec);
+        if (m->graph) hipGraphDestroy(m->graph);
+        m->exec = nullptr;
+        m->graph = nullptr;
+        HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        safr_status st = multi_launch(m, wf, out, s);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(s, &g);
+        if (st != SAFR_OK) {
+            if (g) hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return fail(SAFR_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+        m->graph = g;
+        HIP_TRY(hipGraphInstantiate(&m->exec, g, nullptr, nullptr, 0));
+        m->g_wf.assign(wf, wf + m->count);
+        m->g_out.assign(out, out + m->count);
+        m->g_stream = s;
+    }
+    HIP_TRY(hipGraphLaunch(m->exec, s));
+    return SAFR_OK;
+}
+
+safr_status safr_multi_autotune(safr_multi* m, const float* const* wf, float* const* out, int iters, hipStream_t s) {
+    if (!m || !wf || !out) return fail(SAFR_ERR_ARG, "NULL argument");
+    for (int i = 0; i < m->count; ++i) {
+        safr_plan* p = m->plans[i];
+        void* save = p->ws_user;
+        const size_t save_b = p->ws_user_bytes;
+        p->ws_user = m->ws[i];
+        p->ws_user_bytes = ws_bytes(p, m->frames[i]);
+        safr_status st = safr_autotune(p, m->frames[i], wf[i], out[i], m->precision, iters, s, nullptr);
+        p->ws_user = save;
+        p->ws_user_bytes = save_b;
+        if (st != SAFR_OK) return st;
+    }
+    if (m->exec) {
+        hipGraphExecDestroy(m->exec);
+        hipGraphDestroy(m->graph);
+        m->exec = nullptr;
+        m->graph = nullptr;
+    }
+    return SAFR_OK;
+}
+
+void safr_multi_destroy(safr_multi* m) { free_multi(m); }
+
 safr_status safr_set_option(safr_plan* p, int option, int value) {
     if (!p) return fail(SAFR_ERR_ARG, "plan is NULL");
     if (p->gexec) {                      // a captured graph holds the old launch shapes

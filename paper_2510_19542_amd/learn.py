@@ -55,17 +55,9 @@ def _geometry_struct(geo, keep):
 
 
 def init_params(seed: int = 0) -> np.ndarray:
-    """Seeded initial parameters: weights N(0, 1 / fan_in), biases zero (FP32)."""
-    rng = np.random.default_rng([19542, 4, seed, 7])
-    parts = []
-    for shp in SHAPES:
-        if len(shp) == 2:
-            parts.append(rng.standard_normal(shp) / np.sqrt(shp[1]))
-        elif shp == (64,) and len(parts) == 6:
-            parts.append(rng.standard_normal(shp) / 8.0)        # output layer weights
-        else:
-            parts.append(np.zeros(shp))
-    return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
+    """Seeded initial parameters (the shared input generator's draw)."""
+    import synth
+    return synth.mlp_init(seed)
 
 
 class Trainer:

@@ -31,6 +31,7 @@ EXPORTED = [
     "safr_precompute", "safr_reconstruct", "safr_reconstruct_batched", "safr_workspace_size",
     "safr_set_workspace", "safr_plan_info", "safr_export_B", "safr_set_option", "safr_time_stages",
     "safr_autotune", "safr_destroy", "safr_last_error",
+    "safr_multi_create", "safr_multi_execute", "safr_multi_autotune", "safr_multi_destroy",
     # learned filter (bound in learn.py)
     "safr_trainer_create", "safr_trainer_add_frames", "safr_trainer_set_params", "safr_trainer_get_params",
     "safr_trainer_step", "safr_trainer_gradient", "safr_trainer_frames", "safr_trainer_destroy", "safr_mlp_infer",
@@ -98,8 +99,14 @@ def lib() -> ctypes.CDLL:
     L.safr_destroy.argtypes = [vp]
     L.safr_destroy.restype = None
     L.safr_last_error.restype = ctypes.c_char_p
-    for name in EXPORTED[:13]:
-        if name not in ("safr_destroy", "safr_last_error"):
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    L.safr_multi_create.argtypes = [pp, ctypes.POINTER(i), i, i, ctypes.POINTER(vp)]
+    L.safr_multi_execute.argtypes = [vp, pp, pp, vp]
+    L.safr_multi_autotune.argtypes = [vp, pp, pp, i, vp]
+    L.safr_multi_destroy.argtypes = [vp]
+    L.safr_multi_destroy.restype = None
+    for name in EXPORTED[:17]:
+        if name not in ("safr_destroy", "safr_last_error", "safr_multi_destroy"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -250,6 +257,42 @@ def safr_export_B(plan: Plan, group: int) -> np.ndarray:
                                buf.size))
     z = buf[0::2] + 1j * buf[1::2]
     return z.reshape(d.M // 2 + 1, d.M, d.L, d.group_size[group])
+
+
+class Multi:
+    """A mixed-size batch: plans with their frame counts, executed in one graph launch."""
+
+    def __init__(self, plans, frames, precision: int = SAFR_FP32):
+        self.plans = list(plans)                 # keep the plans alive
+        self.frames = [int(f) for f in frames]
+        arr = (ctypes.c_void_p * len(self.plans))(*[p.handle for p in self.plans])
+        fr = (ctypes.c_int * len(self.frames))(*self.frames)
+        out = ctypes.c_void_p()
+        _check(lib().safr_multi_create(arr, fr, len(self.plans), int(precision), ctypes.byref(out)))
+        self.handle = out.value
+
+    @staticmethod
+    def _ptrs(bufs):
+        return (ctypes.c_void_p * len(bufs))(*[_ptr(b) for b in bufs])
+
+    def execute(self, wavefronts, layers, stream=None):
+        _check(lib().safr_multi_execute(ctypes.c_void_p(self.handle), self._ptrs(wavefronts), self._ptrs(layers),
+                                        _stream(stream)))
+
+    def autotune(self, wavefronts, layers, iters: int = 5, stream=None):
+        _check(lib().safr_multi_autotune(ctypes.c_void_p(self.handle), self._ptrs(wavefronts), self._ptrs(layers),
+                                         int(iters), _stream(stream)))
+
+    def close(self):
+        if self.handle:
+            lib().safr_multi_destroy(ctypes.c_void_p(self.handle))
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def safr_destroy(plan: Plan):

@@ -161,7 +161,19 @@ def c5_big() -> Geometry:
     return c2().replace(name="C5-Big", config_id=5)
 
 
-PRESETS = {"C1": c1, "C2": c2, "C5-S": c5_small, "C5-Mid": c5_mid, "C5-Big": c5_big}
+def c3() -> Geometry:
+    """The C1 geometry with its own seeds, for batches of consecutive frozen-flow frames."""
+    return c1().replace(name="C3", config_id=3)
+
+
+PRESETS = {"C1": c1, "C2": c2, "C3": c3, "C5-S": c5_small, "C5-Mid": c5_mid, "C5-Big": c5_big}
+C5_SIZES = ("C5-S", "C5-Mid", "C5-Big")
+
+
+def c5_instances(count: int = 64) -> list:
+    """Sizes of the mixed-size workload's instances, drawn uniformly (config 5, stream 2)."""
+    rng = np.random.default_rng([19542, 5, 0, 2])
+    return [C5_SIZES[i] for i in rng.integers(0, len(C5_SIZES), count)]
 
 
 def preset(name: str) -> Geometry:

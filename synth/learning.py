@@ -45,6 +45,24 @@ def vk_amplitude(geo: Geometry) -> np.ndarray:
     return out
 
 
+MLP_SHAPES = [(64, 4), (64,), (64, 64), (64,), (64, 64), (64,), (64,), (1,)]
+
+
+def mlp_init(seed: int = 0) -> np.ndarray:
+    """Seeded initial network parameters (FP32, packed in the order of MLP_SHAPES):
+    weight matrices N(0, 1 / fan_in), output weights N(0, 1/64), biases zero."""
+    rng = np.random.default_rng([19542, 4, seed, 7])
+    parts = []
+    for i, shp in enumerate(MLP_SHAPES):
+        if len(shp) == 2:
+            parts.append(rng.standard_normal(shp) / np.sqrt(shp[1]))
+        elif i == 6:
+            parts.append(rng.standard_normal(shp) / 8.0)
+        else:
+            parts.append(np.zeros(shp))
+    return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
+
+
 def learn_draws(geo: Geometry, first: int, count: int, eta_range=(0.005, 0.05), config_id: int = 4):
     """Frames first .. first+count-1: zl (F, L, K, J), zn (F, J_stars, K, J) complex128 and eta (F,)."""
     M, K = geo.M, geo.M // 2 + 1
