@@ -30,7 +30,12 @@ HBM_PEAK_GBS = 8000.0
 
 
 def algorithmic_bytes(desc, n, frames=1):
-    """Bytes each kernel of one launch must move (inputs + outputs + B read once), per the design notes."""
+    """Algorithmic bytes of one launch sequence: wavefronts in + layers out per frame, B read once.
+
+    Also the bytes each kernel moves including the intermediate spectra (R: row
+    spectra of the pupil rows, C: layer half-spectra), which are implementation
+    overhead of the two-pass transforms and not part of the algorithmic figure.
+    """
     M, J, L, G = desc.M, desc.J, desc.L, desc.groups
     Kh = M // 2 + 1
     wf = J * n * n * 4
@@ -39,11 +44,160 @@ def algorithmic_bytes(desc, n, frames=1):
     C = G * L * Kh * M * 8
     out = L * M * M * 4
     return {
-        "rows": frames * (wf + R),
-        "cols": frames * (R + C) + B,
-        "out": frames * (C + out),
-        "frame": frames * (wf + out) + B,
+        "step": frames * (wf + out) + B,
+        "with_intermediates": {"rows": frames * (wf + R), "cols": frames * (R + C) + B,
+                               "out": frames * (C + out)},
     }
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_morfeo_step.json")
+KERNEL_SOURCES = ["k_rows.hip", "k_cols.hip", "k_out.hip", "fft_device.h", "safr_internal.h"]
+
+
+def kernel_source_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2510_19542_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(frames: int):
+    """HBM bytes per step from the committed counter summary, if it was taken on the current kernels."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_digest") != kernel_source_digest() or int(t.get("frames", -1)) != frames:
+        return None
+    return t.get("bytes_per_step")
+
+
+def _timed(fn, iters, stream, torch):
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(iters):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / iters
+
+
+def run_c3(S, torch, stream):
+    """1024 consecutive frozen-flow frames of the 8 m geometry in one call, FP32 and BF16x3."""
+    import synth
+    geo = synth.preset("C3")
+    F = 1024
+    x = torch.from_numpy(synth.frames(geo, F)).cuda()
+    out = torch.empty((F, geo.L, geo.M, geo.M), device="cuda")
+    res = {"workload": "C1 geometry (J=4 NGS, L=2, n=33, M=64), 1024 frozen-flow frames per call"}
+    for name, prec in (("fp32", S.SAFR_FP32), ("bf16x3", S.SAFR_BF16X3)):
+        plan = S.precompute_geometry(geo)
+        _attach_workspace(S, torch, plan, F, prec)
+        tuned = S.safr_autotune(plan, F, x, out, prec, 3, stream)
+        for _ in range(3):
+            S.safr_reconstruct_batched(plan, F, x, out, prec, stream)
+        ms = _timed(lambda: S.safr_reconstruct_batched(plan, F, x, out, prec, stream), 20, stream, torch)
+        st = S.safr_time_stages(plan, F, x, out, prec, 10, stream)
+        res[name] = {"ms_per_call": round(ms, 5), "frames_per_s": round(F * 1000.0 / ms, 1),
+                     "stage_ms": [round(v, 5) for v in st], "autotuned": tuned}
+    return res
+
+
+_WS = {}
+
+
+def _attach_workspace(S, torch, plan, frames, prec):
+    """Point the plan at one shared workspace (plans here run one after another on one stream)."""
+    need = S.safr_workspace_size(plan, frames, prec)
+    if _WS.get("bytes", 0) < need:
+        _WS["t"] = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+        _WS["bytes"] = need
+    S.safr_set_workspace(plan, (_WS["t"].data_ptr() + 255) & ~255, need)
+
+
+def _layer_error(torch, rec, truth):
+    """Mean over frames of the relative layer residual after per-layer piston removal."""
+    r = rec - rec.mean(dim=(2, 3), keepdim=True)
+    t = truth - truth.mean(dim=(2, 3), keepdim=True)
+    num = torch.linalg.vector_norm((r - t).flatten(1), dim=1)
+    den = torch.linalg.vector_norm(t.flatten(1), dim=1)
+    return float((num / den).mean())
+
+
+def run_c4(S, torch, stream, frames):
+    """Learned filter on the 8 m geometry (periodic-exact data on the whole grid)."""
+    import numpy as np
+
+    import synth
+    from paper_2510_19542_amd import learn as Lrn
+    base = synth.preset("C1")
+    geo = base.replace(n=base.M)
+    t0 = time.perf_counter()
+    params, _ = Lrn.train(geo, frames=frames, epochs=3, batch=16, lr=2e-3, seed=1)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    etas = (0.005, 0.01, 0.02, 0.05)
+    truth, wfs = synth.periodic_frames(geo, range(20000, 21000), etas)
+    tt = torch.from_numpy(truth.astype(np.float32)).cuda()
+    alphas = [geo.alpha] + [float(a) for a in np.logspace(-6, 0, 25)]
+    tik = [S.precompute_geometry(geo, pupil=None, alpha=a) for a in alphas]
+    F = len(truth)
+    for p in tik:
+        _attach_workspace(S, torch, p, F, S.SAFR_FP32)
+    out = torch.empty((F, geo.L, geo.M, geo.M), device="cuda")
+    res = {"workload": f"C1 geometry with data on the whole 64x64 grid; trained on {frames} frames "
+                       f"(eta ~ U[0.5%, 5%]), evaluated on 1000 held-out seeds",
+           "train_s": round(train_s, 2), "heldout": {}}
+    speed = {}
+    for eta, wf in zip(etas, wfs):
+        x = torch.from_numpy(wf).cuda()
+        lrn = S.precompute_geometry(geo, pupil=None, filter=S.SAFR_FILTER_MLP, mlp=params, noise=eta)
+        _attach_workspace(S, torch, lrn, F, S.SAFR_FP32)
+        S.safr_reconstruct_batched(lrn, F, x, out, S.SAFR_FP32, stream)
+        e_l = _layer_error(torch, out, tt)
+        errs = []
+        for p in tik:
+            S.safr_reconstruct_batched(p, F, x, out, S.SAFR_FP32, stream)
+            errs.append(_layer_error(torch, out, tt))
+        b = int(np.argmin(errs[1:])) + 1
+        res["heldout"][str(eta)] = {"learned": round(e_l, 5), f"tikhonov_alpha_{geo.alpha:g}": round(errs[0], 5),
+                                    "tikhonov_best": round(errs[b], 5), "best_alpha": float(f"{alphas[b]:.3g}")}
+        if not speed:
+            for name, p in (("learned", lrn), ("tikhonov", tik[0])):
+                speed[name] = round(F * 1000.0 / _timed(
+                    lambda: S.safr_reconstruct_batched(p, F, x, out, S.SAFR_FP32, stream), 20, stream, torch), 1)
+    res["frames_per_s"] = speed
+    return res, params
+
+
+def run_c5(S, torch, stream, params):
+    """64 instances of three sizes (16 frames each) with the learned filter, one graph launch per step."""
+    import collections
+
+    import synth
+    count = collections.Counter(synth.c5_instances(64))
+    names = [n for n in synth.C5_SIZES if count[n]]
+    geos = [synth.preset(n) for n in names]
+    frames = [16 * count[n] for n in names]
+    plans = [S.precompute_geometry(g, filter=S.SAFR_FILTER_MLP, mlp=params, noise=0.02) for g in geos]
+    wf = [torch.from_numpy(synth.random_wavefronts(g, f, seed=50 + i)).cuda()
+          for i, (g, f) in enumerate(zip(geos, frames))]
+    outs = [torch.empty((f, g.L, g.M, g.M), device="cuda") for g, f in zip(geos, frames)]
+    m = S.Multi(plans, frames)
+    m.autotune(wf, outs, iters=3, stream=stream)
+    for _ in range(3):
+        m.execute(wf, outs, stream=stream)
+    ms = _timed(lambda: m.execute(wf, outs, stream=stream), 20, stream, torch)
+    total = sum(frames)
+    m.close()
+    return {"workload": "64 instances drawn from {8 m/4 NGS/M=64/L=3, 20 m/6 LGS/M=128/L=5, "
+                        "39 m MORFEO-like/M=256/L=9}, 16 frames each, learned filter (eta 2%), one graph launch",
+            "instances": {n: count[n] for n in names}, "frames_per_step": total,
+            "ms_per_step": round(ms, 5), "frames_per_s": round(total * 1000.0 / ms, 1)}
 
 
 def cpu_baseline(geo, budget_s: float):
@@ -82,6 +236,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the 1024-frame, learned-filter and mixed-size runs")
+    ap.add_argument("--c4-frames", type=int, default=20000, help="training frames of the learned filter")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this build measures one GPU (use --gpus 1)",
@@ -144,10 +300,9 @@ def main():
     stage1_ms = S.safr_time_stages(plan1, 1, pool[0], out[0], S.SAFR_FP32, 50, stream)
     names = ["rows", "cols", "out"]
     ab = algorithmic_bytes(desc, geo.n, F)
-    dom = int(np.argmax(stage_ms))
-    achieved = ab[names[dom]] / (stage_ms[dom] * 1e-3) / 1e9
-    kernel_names = {"rows": f"safr::rows_kernel<{geo.M}>", "cols": f"safr::cols_fixed<{geo.M}, 9, 6, 3>",
-                    "out": f"safr::out_kernel<{geo.M}, rows, true>"}
+    step_kernel_ms = float(sum(stage_ms))
+    achieved = ab["step"] / (step_kernel_ms * 1e-3) / 1e9
+    traffic = measured_traffic(F)
     result = {
         "metric": METRIC,
         "value": round(fps, 1),
@@ -165,15 +320,24 @@ def main():
                                f"M=256, FP32; {F} independent frames per step in one batched call",
                    "frames_per_step": F, "J": geo.J, "L": geo.L, "M": geo.M, "n": geo.n,
                    "autotuned": {"batched": tuned, "single": tuned1}},
-        "roofline": {"kernel": kernel_names[names[dom]], "bound": "hbm",
+        "roofline": {"kernel": "rows + cols + out (the three kernels of one step)", "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "alg_bytes_per_launch": ab[names[dom]], "kernel_ms": round(stage_ms[dom], 6)},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "alg_bytes_per_launch": ab["step"], "kernel_ms": round(step_kernel_ms, 6),
+                     "per_kernel_GBs_with_intermediates": {
+                         k: round(ab["with_intermediates"][k] / (v * 1e-3) / 1e9, 1) for k, v in zip(names, stage_ms)}},
         "stage_ms": {k: round(v, 6) for k, v in zip(names, stage_ms)},
-        "frame_alg_bytes": algorithmic_bytes(desc, geo.n, 1)["frame"],
+        "frame_alg_bytes": algorithmic_bytes(desc, geo.n, 1)["step"],
         "single_frame": {"us_per_frame": round(us_single, 3), "frames_per_s": round(1e6 / us_single, 1),
                          "stage_ms": {k: round(v, 6) for k, v in zip(names, stage1_ms)}},
     }
+    if not args.no_extras:
+        print("bench: 1024-frame batches (C1 geometry)", file=sys.stderr, flush=True)
+        result["c3_batched_1024"] = run_c3(S, torch, stream)
+        print("bench: learned filter (train 20k frames, held-out evaluation)", file=sys.stderr, flush=True)
+        result["c4_learned_filter"], params = run_c4(S, torch, stream, args.c4_frames)
+        print("bench: mixed-size bundle", file=sys.stderr, flush=True)
+        result["c5_mixed_sizes"] = run_c5(S, torch, stream, params)
     if not args.no_cpu_baseline:
         print("bench: CPU baseline (FP64 oracle)", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(geo, args.cpu_budget)

@@ -7,4 +7,5 @@ from .configs import (ARCSEC, LGS, NGS, Geometry, PRESETS, circular_pupil, prese
                       c1, c2, c3, c5_small, c5_mid, c5_big, C5_SIZES, c5_instances)
 from .atmosphere import (frame, frames, random_wavefronts, rng_for, simulate_wavefronts,  # noqa: F401
                          truth_layers, truth_screens, vk_screen)
-from .learning import MLP_SHAPES, learn_draws, mlp_init, periodic_layers, vk_amplitude  # noqa: F401,E402
+from .learning import (MLP_SHAPES, learn_draws, mlp_init, periodic_frames, periodic_layers,  # noqa: F401
+                       periodic_wavefronts, vk_amplitude)  # noqa: F401,E402

@@ -98,3 +98,47 @@ def periodic_layers(geo: Geometry, seed: int, config_id: int = 4) -> np.ndarray:
         F[:, :, M // 2] = 0.0
     F[:, 0, 0] = 0.0
     return np.fft.ifft2(F).real
+
+
+def periodic_wavefronts(geo: Geometry, layers: np.ndarray) -> np.ndarray:
+    """Noise-free data of periodic layers (L, M, M) on the full M x M grid (periodic-exact mode).
+
+    Star g sees layer l shifted by alpha_g h_l / (c_l pitch) layer pixels: an exact
+    Fourier shift of the layer's trigonometric interpolant (Nyquist dropped for even M).
+    Returns (J, M, M).
+    """
+    M = geo.M
+    idx = np.arange(M)
+    n = np.where(idx <= (M - 1) // 2, idx, idx - M).astype(np.float64)
+    keep = np.ones(M, dtype=bool)
+    if M % 2 == 0:
+        keep[M // 2] = False
+    K = keep[:, None] & keep[None, :]
+    Fl = np.fft.fft2(layers) * K
+    h = np.asarray(geo.heights, dtype=np.float64)
+    out = np.empty((geo.J, M, M))
+    for g, (ax, ay, kind) in enumerate(np.asarray(geo.stars, dtype=np.float64).reshape(-1, 3)):
+        c = 1.0 - h / geo.h_lgs if int(kind) == LGS else np.ones_like(h)
+        sx = ax * h / (c * geo.pitch)
+        sy = ay * h / (c * geo.pitch)
+        ph = np.exp(2j * np.pi * (n[None, :, None] * sx[:, None, None] + n[None, None, :] * sy[:, None, None]) / M)
+        out[g] = np.fft.ifft2(np.sum(ph * Fl, axis=0)).real
+    return out
+
+
+def periodic_frames(geo: Geometry, seeds, etas, config_id: int = 4):
+    """Held-out periodic-exact frames: truth (F, L, M, M) from periodic_layers and, for each noise
+    level in etas, data (F, J, M, M) float32 with white noise of std eta x the RMS of each star's
+    noise-free data (one noise draw per seed, scaled by eta).  Returns (truth, [data per eta])."""
+    seeds = list(seeds)
+    etas = list(np.atleast_1d(etas))
+    truth = np.empty((len(seeds), geo.L, geo.M, geo.M))
+    wfs = [np.empty((len(seeds), geo.J, geo.M, geo.M), dtype=np.float32) for _ in etas]
+    for i, s in enumerate(seeds):
+        truth[i] = periodic_layers(geo, s, config_id)
+        d = periodic_wavefronts(geo, truth[i])
+        rms = np.sqrt(np.mean(d ** 2, axis=(1, 2)))
+        z = rng_for(config_id, s, 9).standard_normal(d.shape)
+        for wf, eta in zip(wfs, etas):
+            wf[i] = d + eta * rms[:, None, None] * z
+    return truth, wfs

@@ -82,29 +82,16 @@ def test_learned_B_matches_oracle(name, seed, eta):
     assert err <= 1e-2
 
 
-def _heldout(geo, seeds, eta):
-    """Periodic-exact held-out frames: truth layers, exact forward operator, white noise (eta x RMS)."""
-    c = O.cone_coefficients(geo.heights, 0, geo.h_lgs)
-    sh = O.layer_shifts(geo.stars, geo.heights, c, geo.pitch)
-    out = []
-    for s in seeds:
-        truth = synth.periodic_layers(geo, s)
-        wf = O.forward_fourier(truth, sh)
-        rng = np.random.default_rng([19542, 4, s, 9])
-        rms = np.sqrt(np.mean(wf ** 2, axis=(1, 2)))
-        wf = wf + eta * rms[:, None, None] * rng.standard_normal(wf.shape)
-        out.append((wf.astype(np.float32), truth))
-    return out
-
-
 def test_learned_filter_beats_tikhonov_on_heldout_frames():
     torch, S, Lrn = _mods()
     base = synth.preset("C1")
     geo = base.replace(n=base.M)                     # periodic-exact: data on the whole grid
     params, hist = Lrn.train(geo, frames=3000, epochs=3, batch=16, lr=2e-3, seed=1)
     assert np.all(np.isfinite(params))
-    for eta in (0.005, 0.01, 0.02, 0.05):
-        frames = _heldout(geo, range(20000, 20006), eta)
+    etas = (0.005, 0.01, 0.02, 0.05)
+    truth_all, wf_all = synth.periodic_frames(geo, range(20000, 20006), etas)
+    for eta, wfe in zip(etas, wf_all):
+        frames = list(zip(wfe, truth_all))
         tik = S.precompute_geometry(geo, pupil=None)
         lrn = S.precompute_geometry(geo, pupil=None, filter=S.SAFR_FILTER_MLP, mlp=params, noise=eta)
         et, el = [], []
