@@ -158,15 +158,21 @@ safr_status safr_export_B(const safr_plan* p, int group, double* host, size_t co
  *   SAFR_OPT_GRAPH       1 = capture the launch sequence in a HIP graph and replay it
  *                        (non-default streams only), 0 = launch directly (default);
  *   SAFR_OPT_ROW_TEAMS   transform teams per block of the row pass (2 rows per team);
- *   SAFR_OPT_OUT_ROWS    output rows per block of the output pass (>= 2);
+ *   SAFR_OPT_OUT_ROWS    output rows per block of the output pass: 8, 16 or 32, at most M
+ *                        and at least 1024 / M (each block transforms (256 / team) / (rows / 2)
+ *                        frames at a time; teams are 16 threads at M = 256, 4 at M = 32, 8 else);
+ *   SAFR_OPT_OUT_FRAMES  frames per block of the output pass (>= 1; mixed asterisms keep the
+ *                        block's natural-star basis pixels in registers across them);
  *   SAFR_OPT_MFMA_FRAMES frames per block of the BF16 apply (4, 8 or 16; default: the
  *                        largest that fits in LDS);
- *   SAFR_OPT_COL_FRAMES  frames per block of the FP32 column pass (B stays in registers
- *                        across them; 1 = one frame per block);
- *   SAFR_OPT_COL_PREFETCH 1 = the column pass keeps each block's B in registers when
- *                        L * G <= 64 (default), 0 = it reads B inside the apply loop. */
+ *   SAFR_OPT_COL_FRAMES  frames per block of the FP32 column pass (>= 1);
+ *   SAFR_OPT_COL_TOGETHER frames the FP32 column pass transforms together (1, 2 or 4; B is
+ *                        read once for them; compile-time shapes only, others use 1);
+ *   SAFR_OPT_COL_PREFETCH 1 = the column pass uses its compile-time kernel when the shape
+ *                        has one (default), 0 = always the generic kernel. */
 enum { SAFR_OPT_GRAPH = 0, SAFR_OPT_ROW_TEAMS = 1, SAFR_OPT_OUT_ROWS = 2, SAFR_OPT_MFMA_FRAMES = 3,
-       SAFR_OPT_COL_FRAMES = 4, SAFR_OPT_COL_PREFETCH = 5 };
+       SAFR_OPT_COL_FRAMES = 4, SAFR_OPT_COL_PREFETCH = 5, SAFR_OPT_OUT_FRAMES = 6,
+       SAFR_OPT_COL_TOGETHER = 7 };
 safr_status safr_set_option(safr_plan* p, int option, int value);
 
 /* Measures the three kernels of the hard-real-time step (row pass, column pass
@@ -178,10 +184,12 @@ safr_status safr_time_stages(safr_plan* p, int frames, const float* wavefronts, 
                              int precision, int iters, hipStream_t stream, double* ms);
 
 /* Autotuner: for the given frame count and precision, times every admissible
- * row-pass block shape (SAFR_OPT_ROW_TEAMS), output-pass tile (SAFR_OPT_OUT_ROWS)
- * and, for several FP32 frames, column-pass frames per block (SAFR_OPT_COL_FRAMES)
- * with HIP events over `iters` synchronised launches each, and keeps the fastest.
- * Overwrites `layers`.  choice (may be NULL) receives the three values chosen. */
+ * row-pass block shape (SAFR_OPT_ROW_TEAMS), output-pass tile and frames per block
+ * (SAFR_OPT_OUT_ROWS, SAFR_OPT_OUT_FRAMES) and, for several FP32 frames, column-pass
+ * frames per block (SAFR_OPT_COL_FRAMES) with HIP events over `iters` synchronised
+ * launches each, and keeps the fastest.  Overwrites `layers`.  choice (may be NULL)
+ * receives five ints: row teams, output rows, column frames per block, output frames
+ * per block, column frames transformed together. */
 safr_status safr_autotune(safr_plan* p, int frames, const float* wavefronts, float* layers, int precision,
                           int iters, hipStream_t stream, int* choice);
 

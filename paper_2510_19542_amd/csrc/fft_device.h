@@ -155,4 +155,29 @@ __device__ __forceinline__ void fft_pass2(int t, const float2* __restrict__ lds,
     }
 }
 
+// Pass 2 split in two, for transforms whose output overwrites the exchange buffer:
+// fft_pass2_load takes every value the thread needs into registers (a barrier may
+// then separate it from the stores), fft_pass2_regs transforms and stores.
+template <int M>
+__device__ __forceinline__ void fft_pass2_load(int t, const float2* __restrict__ lds,
+                                               float2 (&z)[FftShape<M>::N1 / FftShape<M>::T][FftShape<M>::N2]) {
+    using S = FftShape<M>;
+#pragma unroll
+    for (int s = 0; s < S::N1 / S::T; ++s)
+#pragma unroll
+        for (int n2 = 0; n2 < S::N2; ++n2) z[s][n2] = lds[(t + S::T * s) * (S::N2 + 1) + n2];
+}
+
+template <int M, int DIR, class Store>
+__device__ __forceinline__ void fft_pass2_regs(int t, float2 (&z)[FftShape<M>::N1 / FftShape<M>::T][FftShape<M>::N2],
+                                               Store store) {
+    using S = FftShape<M>;
+#pragma unroll
+    for (int s = 0; s < S::N1 / S::T; ++s) {
+        dft<S::N2, DIR>(z[s]);
+#pragma unroll
+        for (int k2 = 0; k2 < S::N2; ++k2) store(t + S::T * s + S::N1 * k2, z[s][k2]);
+    }
+}
+
 }  // namespace safr

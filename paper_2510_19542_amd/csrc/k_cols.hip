@@ -3,27 +3,34 @@
 //      is nonzero in the n pupil rows only, read directly from the row pass);
 //   2. per-frequency apply b_l(j, k) = sum_g B[k][l][g][j] d_g(j, k) with the
 //      group's FP32 B (Eq. sparseM: B is diagonal in frequency);
-//   3. inverse column FFT of each layer spectrum, written as C[f][grp][l][k][p].
-// The spectra d and b live only in LDS.  One block of 256 threads owns
-// 256 / M columns of one group and loops over a chunk of frames.
+//   3. inverse column FFT of each layer spectrum, written to C in row tiles of 8
+//      (C[f][l][p / 8][k][p % 8]).
+// Split tomography (Sec. 3.3): for the laser stars of a mixed asterism the
+// least-squares plane b x + c y over the pupil (from the row-pass moments) is
+// removed; the transform being linear, that is d_g -= b DFT2(x mask) +
+// c DFT2(y mask), with the two transforms precomputed in FP64 per plan.  The
+// natural stars are added in the output pass.
 //
-// B is stored per block of columns as [l][g][column][j], so the block's whole
-// B slice is one contiguous run and thread t owns the entries t, t + 256, ...
+// One block of 256 threads owns CPW = 256 / M columns and a run of frames,
+// transformed NF frames at a time.  LDS holds one slot of team_lds<M>() float2
+// per (column, frame, star-or-layer); a slot is in turn a transform's exchange
+// buffer and its spectrum: forward transforms leave d_g in the star slots, the
+// apply (thread = column, frequency j) reads every d_g(j) of its frames into
+// registers and writes b_l(j) into the layer slots (which overlap the star
+// slots only at its own index j), and the inverse transforms run in place in
+// the layer slots.  Phases that overwrite a slot first take what they need into
+// registers, with a barrier in between.  The next iteration's forward inputs
+// are loaded into registers while the current one is transformed.
 //
-// Split tomography (Sec. 3.3): the least-squares plane b x + c y of each
-// wavefront over the pupil is obtained from the moments written by the row
-// pass; since the transform is linear, removing the plane (laser stars) is
-// d_g -= b DFT2(x mask) + c DFT2(y mask) and keeping only the plane (natural
-// stars) is d_g = b DFT2(x mask) + c DFT2(y mask), with the two transforms
-// precomputed in FP64 per plan.
+// B is stored per block of columns as [l][g][column][j] (thread t owns entries
+// t, t + 256, ...) and is read from global memory at each apply, once for NF
+// frames.  Blocks are mapped XCD-aware: the blocks of one column block (all
+// its frame runs) are consecutive on the same XCD, so its B stays in that
+// XCD's L2.
 //
-// Two kernels:
-//   cols_fixed<M, L, G0, G1>: shapes known at compile time (the configured
-//     geometries).  The block's B slice is loaded into registers once, right
-//     after the first column-FFT inputs (loads retire in order, so the first
-//     transform does not wait for B), and the apply is a branch-free unrolled
-//     L x G product whose LDS reads issue together.
-//   cols_generic<M>: any shape; B is read inside the apply loop.
+// cols_kernel<M, NF, G, L, MODE> with compile-time G, L (the configured
+// geometries) keeps d in registers; G = L = 0 is the generic kernel (any shape,
+// NF = 1, separate star and layer slots, d re-read from LDS).
 #include "fft_device.h"
 #include "safr_internal.h"
 
@@ -31,298 +38,294 @@ namespace safr {
 
 namespace {
 
-struct ColGeom {
-    int kb, k0, tid, team, t, c, j, k;
-    bool kvalid;
-    int f0, f1;
-};
-
-template <int M>
-__device__ __forceinline__ ColGeom col_geom(const ColArgs& a) {
-    using S = FftShape<M>;
-    ColGeom q;
-    q.kb = blockIdx.x;
-    q.k0 = q.kb * (256 / M);
-    q.tid = threadIdx.x;
-    q.team = q.tid / S::T;
-    q.t = q.tid % S::T;
-    q.c = q.tid / M;
-    q.j = q.tid % M;
-    q.k = q.k0 + q.c;
-    q.kvalid = q.k < M / 2 + 1;
-    q.f0 = blockIdx.z * a.frames_per_block;
-    q.f1 = min(a.frames, q.f0 + a.frames_per_block);
-    return q;
-}
-
-// plane coefficients (b, c) of every star of the group for frame f, from the row-pass moments
-__device__ __forceinline__ void plane_coefs(const ColArgs& a, const GroupArgs& gr, int G, int f, int tid,
-                                            float2* coef) {
-    if (tid < G) {
-        const float* mo = a.mom + ((size_t)f * a.J + gr.star[tid]) * a.nchunk * 4;
-        float m0 = 0.f, m1 = 0.f, m2 = 0.f;
-        for (int q = 0; q < a.nchunk; ++q) {
-            m0 += mo[4 * q + 0];
-            m1 += mo[4 * q + 1];
-            m2 += mo[4 * q + 2];
-        }
-        coef[tid] = make_float2(a.tt_b[0] * m0 + a.tt_b[1] * m1 + a.tt_b[2] * m2,
-                                a.tt_c[0] * m0 + a.tt_c[1] * m1 + a.tt_c[2] * m2);
-    }
-}
-
 __device__ __forceinline__ float2 plane_value(float2 cf, float2 xh, float2 yh) {
     return make_float2(cf.x * xh.x + cf.y * yh.x, cf.x * xh.y + cf.y * yh.y);
 }
 
-// column-FFT inputs of task `task` (= column * G + member) for thread t: x[n1] = R[.][k][N2 n1 + t - p0]
-template <int M>
-__device__ __forceinline__ void load_column(const ColArgs& a, const GroupArgs& gr, int G, int ftasks, int k0,
-                                            int f, int task, int t, float2 (&x)[FftShape<M>::N1]) {
-    using S = FftShape<M>;
-    const int cc = task / G, g = task - cc * G;
-    const int kk = k0 + cc;
-    if (task < ftasks && kk < M / 2 + 1) {
-        const float2* col = a.R + (((size_t)f * a.J + gr.star[g]) * (M / 2 + 1) + kk) * a.n;
-#pragma unroll
-        for (int n1 = 0; n1 < S::N1; ++n1) {
-            const int pr = S::N2 * n1 + t - a.p0;
-            x[n1] = (pr >= 0 && pr < a.n) ? col[pr] : make_float2(0.f, 0.f);
-        }
-    }
+// Raw buffer access to the block's B slice: the descriptor is uniform (scalar registers) and each
+// (l, g) entry is one 32-bit lane offset plus a scalar offset, so the loop-invariant addresses of the
+// L x G loads do not each occupy a 64-bit vector register pair.  Word 3 is the gfx9-family default.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t block_rsrc(const void* base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
 }
 
-// inverse column transforms of the L layer spectra in Bsp, written to C
-template <int M>
-__device__ __forceinline__ void inverse_columns(const ColArgs& a, const ColGeom& q, int gi, int L, int f,
-                                                const float2* tws, float2* xch, const float2* Bsp) {
-    constexpr int CPW = 256 / M, Kh = M / 2 + 1, NTEAM = 256 / FftShape<M>::T;
-    const int itasks = CPW * L;
-    for (int base = 0; base < itasks; base += NTEAM) {
-        const int task = base + q.team;
-        const int cc = task / L, l = task - cc * L;
-        const int kk = q.k0 + cc;
-        const bool active = task < itasks && kk < Kh;
-        if (active) {
-            const float2* src = Bsp + (cc * L + l) * M;
-            fft_pass1<M, +1>(q.t, xch, tws, [&](int jj) -> float2 { return src[jj]; });
-        }
-        __syncthreads();
-        if (active) {
-            float2* dst = a.C + ((((size_t)f * a.groups.count + gi) * L + l) * Kh + kk) * M;
-            fft_pass2<M, +1>(q.t, xch, [&](int p, float2 v) { dst[p] = v; });
-        }
-        __syncthreads();
-    }
+__device__ __forceinline__ float2 load_b(__amdgpu_buffer_rsrc_t r, int lane_bytes, int entry) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, lane_bytes, entry * 2048, 0));
 }
 
-// LDS: tws[M] | xch[NTEAM][TL] | D[CPW][gmax][M] | Bsp[CPW][L][M] | coef[16]
-template <int M>
-__device__ __forceinline__ void carve(float2* smem, int gmax, int L, float2*& tws, float2*& xall, float2*& D,
-                                      float2*& Bsp, float2*& coef) {
-    constexpr int CPW = 256 / M, NTEAM = 256 / FftShape<M>::T;
-    tws = smem;
-    xall = tws + M;
-    D = xall + NTEAM * team_lds<M>();
-    Bsp = D + CPW * gmax * M;
-    coef = Bsp + CPW * L * M;
+__device__ __forceinline__ float2 load_f2(__amdgpu_buffer_rsrc_t r, int byte_off) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0));
 }
 
-template <int M, int L, int G, int MODE>
-__device__ __forceinline__ void cols_body(const ColArgs& a, int gi, float2* smem) {
-    using S = FftShape<M>;
-    constexpr int CPW = 256 / M, NTEAM = 256 / S::T;
-    constexpr int FT = MODE == 2 ? 0 : CPW * G;          // forward transforms per frame
-    const GroupArgs& gr = a.groups.g[gi];
-    const ColGeom q = col_geom<M>(a);
-    float2 *tws, *xall, *D, *Bsp, *coef;
-    carve<M>(smem, a.gmax, L, tws, xall, D, Bsp, coef);
-    float2* xch = xall + q.team * team_lds<M>();
+__device__ __forceinline__ void store_f2(__amdgpu_buffer_rsrc_t r, int byte_off, float2 v) {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, byte_off, 0, 0);
+}
 
-    // loads, oldest first: twiddles, first column inputs, B
-    const float2 twv = q.tid < M ? a.tw[q.tid] : make_float2(0.f, 0.f);
-    float2 x[S::N1];
-    if constexpr (FT > 0) load_column<M>(a, gr, G, FT, q.k0, q.f0, q.team, q.t, x);
-    const float2* Bblk = a.B + gr.b_off + (size_t)q.kb * L * G * 256;
-    float2 breg[L * G];
-#pragma unroll
-    for (int i = 0; i < L * G; ++i) breg[i] = Bblk[(size_t)i * 256 + q.tid];
-    float2 xh = make_float2(0.f, 0.f), yh = make_float2(0.f, 0.f);
-    if (MODE != 0 && q.kvalid) {
-        xh = a.Xh[(size_t)q.k * M + q.j];
-        yh = a.Yh[(size_t)q.k * M + q.j];
-    }
-    if (q.tid < M) tws[q.tid] = twv;
-    __syncthreads();
-
-    for (int f = q.f0; f < q.f1; ++f) {
-        if (MODE != 0) plane_coefs(a, gr, G, f, q.tid, coef);
-        if constexpr (FT > 0) {
-#pragma unroll
-            for (int base = 0; base < FT; base += NTEAM) {
-                const int task = base + q.team;
-                const int cc = task / G, g = task - cc * G;
-                const bool active = task < FT && q.k0 + cc < M / 2 + 1;
-                if (f != q.f0 || base != 0) load_column<M>(a, gr, G, FT, q.k0, f, task, q.t, x);
-                if (active) fft_pass1_regs<M, -1>(q.t, xch, tws, x);
-                __syncthreads();
-                if (active) {
-                    float2* d = D + (cc * G + g) * M;
-                    fft_pass2<M, -1>(q.t, xch, [&](int jj, float2 v) { d[jj] = v; });
-                }
-                __syncthreads();
-            }
-        } else {
-            __syncthreads();
-        }
-        if (q.kvalid) {
-            float2 dv[G];
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-                if constexpr (MODE == 0) dv[g] = D[(q.c * G + g) * M + q.j];
-                else if constexpr (MODE == 1) dv[g] = csub(D[(q.c * G + g) * M + q.j], plane_value(coef[g], xh, yh));
-                else dv[g] = plane_value(coef[g], xh, yh);
-            }
-#pragma unroll
-            for (int l = 0; l < L; ++l) {
-                float2 acc = make_float2(0.f, 0.f);
-#pragma unroll
-                for (int g = 0; g < G; ++g) {
-                    const float2 bv = breg[l * G + g];
-                    acc.x += bv.x * dv[g].x - bv.y * dv[g].y;
-                    acc.y += bv.x * dv[g].y + bv.y * dv[g].x;
-                }
-                Bsp[(q.c * L + l) * M + q.j] = acc;
-            }
-        }
-        __syncthreads();
-        inverse_columns<M>(a, q, gi, L, f, tws, xch, Bsp);
-    }
+// linear block -> (column block, frame run), XCD-contiguous (blocks are dealt to the 8 XCDs round-robin)
+__device__ __forceinline__ bool xcd_work(int nwork, int& w) {
+    const int b = blockIdx.x, per = gridDim.x / 8;
+    w = (b % 8) * per + b / 8;
+    return w < nwork;
 }
 
 }  // namespace
 
-template <int M, int L, int G0, int G1>
-__global__ __launch_bounds__(256, 2) void cols_fixed(ColArgs a) {
-    extern __shared__ float2 smem[];
-    if constexpr (G1 == 0) {
-        cols_body<M, L, G0, 0>(a, 0, smem);
-    } else {
-        if (blockIdx.y == 0) cols_body<M, L, G0, 1>(a, 0, smem);
-        else cols_body<M, L, G1, 2>(a, 1, smem);
-    }
-}
-
-template <int M>
-__global__ __launch_bounds__(256) void cols_generic(ColArgs a) {
+template <int M, int NF, int GC, int LC, int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 2 : 3))) void cols_kernel(ColArgs a) {
     using S = FftShape<M>;
-    constexpr int CPW = 256 / M, NTEAM = 256 / S::T;
+    constexpr int T = S::T, N1 = S::N1, NTEAM = 256 / T, TL = team_lds<M>();
+    constexpr int CPW = 256 / M, Kh = M / 2 + 1;
+    constexpr bool FIX = GC > 0;
+    const int G = FIX ? GC : a.grp.G;
+    const int L = FIX ? LC : a.L;
+    // slots: star slots [c][f][g] at 0, layer slots [c][f][l] at LS (overlapping when FIX)
+    const int SPF = FIX ? (GC > LC ? GC : LC) : G + L;          // slots per (column, frame)
+    const int LS = FIX ? 0 : G;
+
     extern __shared__ float2 smem[];
-    const int gi = blockIdx.y;
-    const GroupArgs& gr = a.groups.g[gi];
-    const int G = gr.G, mode = gr.mode, L = a.L;
-    const ColGeom q = col_geom<M>(a);
-    float2 *tws, *xall, *D, *Bsp, *coef;
-    carve<M>(smem, a.gmax, L, tws, xall, D, Bsp, coef);
-    float2* xch = xall + q.team * team_lds<M>();
-    const int ftasks = mode == 2 ? 0 : CPW * G;
-    const float2* Bblk = a.B + gr.b_off + (size_t)q.kb * L * G * 256;
-    for (int i = q.tid; i < M; i += 256) tws[i] = a.tw[i];
-    float2 xh = make_float2(0.f, 0.f), yh = make_float2(0.f, 0.f);
-    if (mode != 0 && q.kvalid) {
-        xh = a.Xh[(size_t)q.k * M + q.j];
-        yh = a.Yh[(size_t)q.k * M + q.j];
-    }
-    __syncthreads();
-    for (int f = q.f0; f < q.f1; ++f) {
-        if (mode != 0) plane_coefs(a, gr, G, f, q.tid, coef);
-        for (int base = 0; base < max(ftasks, 1); base += NTEAM) {
-            const int task = base + q.team;
-            const int cc = task / G, g = task - cc * G;
-            const bool active = task < ftasks && q.k0 + cc < M / 2 + 1;
-            float2 x[S::N1];
-            load_column<M>(a, gr, G, ftasks, q.k0, f, task, q.t, x);
-            if (active) fft_pass1_regs<M, -1>(q.t, xch, tws, x);
-            __syncthreads();
-            if (active) {
-                float2* d = D + (cc * G + g) * M;
-                fft_pass2<M, -1>(q.t, xch, [&](int jj, float2 v) { d[jj] = v; });
-            }
-            __syncthreads();
+    float2* tws = smem;                                        // [M]
+    float2* slots = smem + M;                                  // [CPW][NF][SPF][TL]
+    float2* coef = slots + (size_t)CPW * NF * SPF * TL;        // [NF][G]
+
+    const int kblocks = (Kh + CPW - 1) / CPW;
+    const int runs = (a.frames + a.frames_per_block - 1) / a.frames_per_block;
+    int w;
+    if (!xcd_work(kblocks * runs, w)) return;                  // the whole block leaves before any barrier
+    const int kb = w / runs, run = w - kb * runs;
+    const int fbeg = run * a.frames_per_block;
+    const int fend = min(a.frames, fbeg + a.frames_per_block);
+    const int tid = threadIdx.x, team = tid / T, t = tid % T;
+    const int c = tid / M, j = tid % M;                        // apply: column in block, frequency
+    const int k = kb * CPW + c;
+    const bool kvalid = k < Kh;
+    const GroupArgs& gr = a.grp;
+    auto slot = [&](int cc, int f, int s) { return slots + ((size_t)(cc * NF + f) * SPF + s) * TL; };
+
+    // forward tasks: (column, frame, star); rounds of NTEAM teams
+    const int ftasks = CPW * NF * G;
+    constexpr int FR_MAX = FIX ? (CPW * NF * GC + NTEAM - 1) / NTEAM : 1;
+    float2 xf[FR_MAX][N1];
+    // R of frames f0 .. f0 + NF - 1 through one descriptor (byte offsets stay below 2^31)
+    const int fstride = a.J * Kh * a.n;                        // float2 per frame of R
+    auto load_fwd = [&](int f0, int round, float2 (&x)[N1]) {
+        const int task = round * NTEAM + team;
+        const int cc = task / (NF * G), rem = task - cc * (NF * G);
+        const int fl = rem / G, g = rem - fl * G;
+        const int kk = kb * CPW + cc, f = f0 + fl;
+        const bool ok = task < ftasks && kk < Kh && f < fend;
+        const int nfr = min(NF, fend - f0);
+        const __amdgpu_buffer_rsrc_t rr = block_rsrc(a.R + (size_t)f0 * fstride, (unsigned)(nfr * fstride * 8));
+        const int colb = ((fl * a.J + gr.star[g]) * Kh + kk) * a.n;
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) {
+            const int pr = S::N2 * n1 + t - a.p0;
+            x[n1] = (ok && pr >= 0 && pr < a.n) ? load_f2(rr, (colb + pr) * 8) : make_float2(0.f, 0.f);
         }
-        if (q.kvalid) {
-            for (int l = 0; l < L; ++l) {
-                float2 acc = make_float2(0.f, 0.f);
-                for (int g = 0; g < G; ++g) {
-                    float2 dv;
-                    if (mode == 2) dv = plane_value(coef[g], xh, yh);
-                    else {
-                        dv = D[(q.c * G + g) * M + q.j];
-                        if (mode == 1) dv = csub(dv, plane_value(coef[g], xh, yh));
-                    }
-                    const float2 bv = Bblk[(size_t)(l * G + g) * 256 + q.tid];
-                    acc.x += bv.x * dv.x - bv.y * dv.y;
-                    acc.y += bv.x * dv.y + bv.y * dv.x;
-                }
-                Bsp[(q.c * L + l) * M + q.j] = acc;
+    };
+
+    const float2 twv = tid < M ? a.tw[tid] : make_float2(0.f, 0.f);
+    if constexpr (FIX) {
+#pragma unroll
+        for (int r = 0; r < FR_MAX; ++r) load_fwd(fbeg, r, xf[r]);
+    }
+    float2 xh = make_float2(0.f, 0.f), yh = make_float2(0.f, 0.f);
+    if (MODE != 0 && kvalid) {
+        xh = a.Xh[(size_t)k * M + j];
+        yh = a.Yh[(size_t)k * M + j];
+    }
+    if (tid < M) tws[tid] = twv;
+    const __amdgpu_buffer_rsrc_t Brs = block_rsrc(a.B + (size_t)kb * L * G * 256, (unsigned)(L * G * 256 * 8));
+
+    for (int f0 = fbeg; f0 < fend; f0 += NF) {
+        __syncthreads();                                        // previous inverse transforms done with the slots
+        if (MODE != 0 && tid < NF * G) {
+            const int fl = tid / G, g = tid - fl * G;
+            const int f = min(f0 + fl, fend - 1);
+            const float* mo = a.mom + ((size_t)f * a.J + gr.star[g]) * a.nchunk * 4;
+            float m0 = 0.f, m1 = 0.f, m2 = 0.f;
+            for (int q = 0; q < a.nchunk; ++q) {
+                m0 += mo[4 * q + 0];
+                m1 += mo[4 * q + 1];
+                m2 += mo[4 * q + 2];
+            }
+            coef[fl * G + g] = make_float2(a.tt_b[0] * m0 + a.tt_b[1] * m1 + a.tt_b[2] * m2,
+                                           a.tt_c[0] * m0 + a.tt_c[1] * m1 + a.tt_c[2] * m2);
+        }
+        // 1. forward column transforms into the star slots
+        const int frounds = FIX ? FR_MAX : (ftasks + NTEAM - 1) / NTEAM;
+#pragma unroll
+        for (int r = 0; r < frounds; ++r) {
+            const int task = r * NTEAM + team;
+            const int cc = task / (NF * G), rem = task - cc * (NF * G);
+            const int fl = rem / G, g = rem - fl * G;
+            const bool active = task < ftasks;
+            float2* sl = active ? slot(cc, fl, g) : slots;
+            float2 x[N1];
+            if constexpr (FIX) {
+#pragma unroll
+                for (int n1 = 0; n1 < N1; ++n1) x[n1] = xf[r][n1];
+            } else {
+                load_fwd(f0, r, x);
+            }
+            if (active) fft_pass1_regs<M, -1>(t, sl, tws, x);
+            __syncthreads();
+            float2 z[N1 / T][S::N2];
+            if (active) fft_pass2_load<M>(t, sl, z);
+            __syncthreads();
+            if (active) fft_pass2_regs<M, -1>(t, z, [&](int jj, float2 v) { sl[jj] = v; });
+        }
+        // the next iteration's forward inputs, in flight during the apply and the inverse transforms
+        if constexpr (FIX) {
+            if (f0 + NF < fend) {
+#pragma unroll
+                for (int r = 0; r < FR_MAX; ++r) load_fwd(f0 + NF, r, xf[r]);
             }
         }
         __syncthreads();
-        inverse_columns<M>(a, q, gi, L, f, tws, xch, Bsp);
+
+        // 2. apply: b_l(j) = sum_g B[l][g][j] d_g(j) for the NF frames
+        if (kvalid) {
+            if constexpr (FIX) {
+                float2 dv[NF][GC];
+#pragma unroll
+                for (int fl = 0; fl < NF; ++fl)
+#pragma unroll
+                    for (int g = 0; g < GC; ++g) {
+                        const float2 d = slot(c, fl, g)[j];
+                        dv[fl][g] = MODE != 0 ? csub(d, plane_value(coef[fl * GC + g], xh, yh)) : d;
+                    }
+#pragma unroll
+                for (int l = 0; l < LC; ++l) {
+                    float2 bv[GC];
+#pragma unroll
+                    for (int g = 0; g < GC; ++g) bv[g] = load_b(Brs, tid * 8, l * GC + g);
+#pragma unroll
+                    for (int fl = 0; fl < NF; ++fl) {
+                        float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+                        for (int g = 0; g < GC; ++g) {
+                            acc.x += bv[g].x * dv[fl][g].x - bv[g].y * dv[fl][g].y;
+                            acc.y += bv[g].x * dv[fl][g].y + bv[g].y * dv[fl][g].x;
+                        }
+                        slot(c, fl, l)[j] = acc;
+                    }
+                }
+            } else {
+                for (int l = 0; l < L; ++l) {
+                    float2 acc = make_float2(0.f, 0.f);
+                    for (int g = 0; g < G; ++g) {
+                        float2 d = slot(c, 0, g)[j];
+                        if (MODE != 0) d = csub(d, plane_value(coef[g], xh, yh));
+                        const float2 bv = load_b(Brs, tid * 8, l * G + g);
+                        acc.x += bv.x * d.x - bv.y * d.y;
+                        acc.y += bv.x * d.y + bv.y * d.x;
+                    }
+                    slot(c, 0, LS + l)[j] = acc;
+                }
+            }
+        }
+        __syncthreads();
+
+        // 3. inverse column transforms of the layer slots, in place, written to C
+        const int itasks = CPW * NF * L;
+        for (int base = 0; base < itasks; base += NTEAM) {
+            const int task = base + team;
+            const int cc = task / (NF * L), rem = task - cc * (NF * L);
+            const int fl = rem / L, l = rem - fl * L;
+            const int kk = kb * CPW + cc, f = f0 + fl;
+            const bool active = task < itasks;
+            float2* sl = active ? slot(cc, fl, LS + l) : slots;
+            float2 x[N1];
+            if (active) {
+#pragma unroll
+                for (int n1 = 0; n1 < N1; ++n1) x[n1] = sl[S::N2 * n1 + t];
+            }
+            __syncthreads();
+            if (active) fft_pass1_regs<M, +1>(t, sl, tws, x);
+            __syncthreads();
+            if (active && kk < Kh && f < fend) {
+                const int nfr = min(NF, fend - f0);
+                const size_t cfr = (size_t)L * Kh * M;        // float2 per frame of C
+                const __amdgpu_buffer_rsrc_t cr = block_rsrc(a.C + c_index(f0, 0, L, M, 0, 0), (unsigned)(nfr * cfr * 8));
+                const int base = (int)(c_index(fl, l, L, M, kk, 0));
+                fft_pass2<M, +1>(t, sl, [&](int p, float2 v) {
+                    store_f2(cr, (base + (p >> 3) * (Kh * 8) + (p & 7)) * 8, v);
+                });
+            }
+        }
     }
 }
 
-size_t cols_lds_bytes(int M, int gmax, int L) {
+size_t cols_lds_bytes(int M, int G, int L, int nf, bool fixed) {
     const int N1 = M == 32 ? 8 : (M == 64 ? 8 : 16), N2 = M / N1;
-    const int T = M == 256 ? 16 : (M == 32 ? 4 : 8);
-    return ((size_t)M + (size_t)(256 / T) * N1 * (N2 + 1) + (size_t)(256 / M) * (gmax + L) * M + kMaxG) *
-           sizeof(float2);
+    const size_t tl = (size_t)N1 * (N2 + 1);
+    const int spf = fixed ? (G > L ? G : L) : G + L;
+    return ((size_t)M + (size_t)(256 / M) * nf * spf * tl + (size_t)nf * G) * sizeof(float2);
 }
 
 namespace {
 
 template <class K>
-hipError_t launch_cols_kernel(K kernel, int M, const ColArgs& a, int frames, hipStream_t s) {
+hipError_t launch_cols_kernel(K kernel, int M, int nf, bool fixed, const ColArgs& a, int frames, hipStream_t s) {
     const int CPW = 256 / M, Kh = M / 2 + 1;
-    const size_t lds = cols_lds_bytes(M, a.gmax, a.L);
-    const dim3 grid((Kh + CPW - 1) / CPW, a.groups.count, (frames + a.frames_per_block - 1) / a.frames_per_block);
+    const size_t lds = cols_lds_bytes(M, a.grp.G, a.L, nf, fixed);
+    const int kblocks = (Kh + CPW - 1) / CPW;
+    const int runs = (frames + a.frames_per_block - 1) / a.frames_per_block;
+    const int nblk = (kblocks * runs + 7) / 8 * 8;
     allow_large_lds(reinterpret_cast<const void*>(kernel));
-    hipLaunchKernelGGL(kernel, grid, dim3(256), lds, s, a);
+    hipLaunchKernelGGL(kernel, dim3(nblk), dim3(256), lds, s, a);
     return hipGetLastError();
 }
 
-// shapes with a compile-time kernel: (M, L, laser-or-only group size, natural group size or 0)
+// shapes with a compile-time kernel: (M, L, group size, mode)
 #define SAFR_FIXED_SHAPES(X) \
-    X(256, 9, 6, 3)          \
+    X(256, 9, 6, 1)          \
     X(256, 9, 6, 0)          \
     X(128, 5, 6, 0)          \
     X(64, 2, 4, 0)           \
     X(64, 3, 4, 0)
 
-bool fixed_shape_known(int M, int L, int G0, int G1) {
-#define SAFR_MATCH(m, l, g0, g1) \
-    if (M == m && L == l && G0 == g0 && G1 == g1) return true;
+template <int M, int G, int L, int MODE>
+hipError_t launch_fixed(const ColArgs& a, int nf, int frames, hipStream_t s) {
+    switch (nf) {
+        case 1: return launch_cols_kernel(&cols_kernel<M, 1, G, L, MODE>, M, 1, true, a, frames, s);
+        case 2: return launch_cols_kernel(&cols_kernel<M, 2, G, L, MODE>, M, 2, true, a, frames, s);
+        case 4: return launch_cols_kernel(&cols_kernel<M, 4, G, L, MODE>, M, 4, true, a, frames, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int M>
+hipError_t launch_generic(const ColArgs& a, int frames, hipStream_t s) {
+    return a.grp.mode ? launch_cols_kernel(&cols_kernel<M, 1, 0, 0, 1>, M, 1, false, a, frames, s)
+                      : launch_cols_kernel(&cols_kernel<M, 1, 0, 0, 0>, M, 1, false, a, frames, s);
+}
+
+}  // namespace
+
+bool cols_fixed_shape(int M, int L, int G, int mode) {
+#define SAFR_MATCH(m, l, g, md) \
+    if (M == m && L == l && G == g && mode == md) return true;
     SAFR_FIXED_SHAPES(SAFR_MATCH)
 #undef SAFR_MATCH
     return false;
 }
 
-}  // namespace
-
-hipError_t launch_cols(int M, const ColArgs& a, int frames, hipStream_t s) {
-    const int G0 = a.groups.g[0].G, G1 = a.groups.count > 1 ? a.groups.g[1].G : 0;
-    if (a.prefetch && fixed_shape_known(M, a.L, G0, G1)) {
-#define SAFR_LAUNCH(m, l, g0, g1)                           \
-    if (M == m && a.L == l && G0 == g0 && G1 == g1)         \
-        return launch_cols_kernel(&cols_fixed<m, l, g0, g1>, M, a, frames, s);
+hipError_t launch_cols(int M, const ColArgs& a, int nf, int frames, hipStream_t s) {
+    const int G = a.grp.G, mode = a.grp.mode;
+    if (a.prefetch && cols_fixed_shape(M, a.L, G, mode)) {
+#define SAFR_LAUNCH(m, l, g, md)                    \
+    if (M == m && a.L == l && G == g && mode == md) \
+        return launch_fixed<m, g, l, md>(a, nf, frames, s);
         SAFR_FIXED_SHAPES(SAFR_LAUNCH)
 #undef SAFR_LAUNCH
     }
     switch (M) {
-        case 32: return launch_cols_kernel(&cols_generic<32>, M, a, frames, s);
-        case 64: return launch_cols_kernel(&cols_generic<64>, M, a, frames, s);
-        case 128: return launch_cols_kernel(&cols_generic<128>, M, a, frames, s);
-        case 256: return launch_cols_kernel(&cols_generic<256>, M, a, frames, s);
+        case 32: return launch_generic<32>(a, frames, s);
+        case 64: return launch_generic<64>(a, frames, s);
+        case 128: return launch_generic<128>(a, frames, s);
+        case 256: return launch_generic<256>(a, frames, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -82,20 +82,19 @@ __global__ __launch_bounds__(256) void cols_mfma_kernel(MfmaArgs a) {
     constexpr int T = S::T, Kh = M / 2 + 1, NTEAM = 256 / T, TL = team_lds<M>();
     extern __shared__ float2 smem[];
     const int k = blockIdx.x;
-    const int gi = blockIdx.y;
     const int fb = blockIdx.z * NF;
     const int nf = min(NF, a.frames - fb);
-    const GroupArgs& gr = a.groups.g[gi];
+    const GroupArgs& gr = a.grp;
     const int G = gr.G, mode = gr.mode, L = a.L, n = a.n;
-    const int lt = a.lt[gi], ntile = a.ntile[gi], ppm = a.ppm[gi];
+    const int lt = a.lt, ntile = a.ntile, ppm = a.ppm;
     const int tid = threadIdx.x, team = tid / T, t = tid % T;
     const int lane = tid & 63, wave = tid >> 6;
 
     float2* tws = smem;                                    // [M]
     float2* xch = tws + M + team * TL;                     // [NTEAM][TL]
-    float2* D = tws + M + NTEAM * TL;                      // [NF][gmax][M]
-    float2* Bsp = D + NF * a.gmax * M;                     // [NF][L][M]
-    float2* coef = Bsp + NF * L * M;                       // [NF][gmax]
+    float2* D = tws + M + NTEAM * TL;                      // [NF][G][M]
+    float2* Bsp = D + NF * G * M;                          // [NF][L][M]
+    float2* coef = Bsp + NF * L * M;                       // [NF][G]
 
     for (int i = tid; i < M; i += 256) tws[i] = a.tw[i];
     if (mode != 0) {
@@ -115,7 +114,7 @@ __global__ __launch_bounds__(256) void cols_mfma_kernel(MfmaArgs a) {
     __syncthreads();
 
     // 1. forward column transforms of the NF frames
-    const int ftasks = mode == 2 ? 0 : nf * G;
+    const int ftasks = nf * G;
     for (int base = 0; base < ftasks; base += NTEAM) {
         const int task = base + team;
         const bool active = task < ftasks;
@@ -136,7 +135,7 @@ __global__ __launch_bounds__(256) void cols_mfma_kernel(MfmaArgs a) {
     }
 
     // 2. apply on matrix cores: one wave per (layer tile, frequency group) item
-    const bf16x8_t* Ap = reinterpret_cast<const bf16x8_t*>(a.Apack + a.a_off[gi]);
+    const bf16x8_t* Ap = reinterpret_cast<const bf16x8_t*>(a.Apack);
     const int nq = M / ppm;
     const int fl = lane % 16;                          // frame of this lane's B-operand column and D column
     float* bspf = reinterpret_cast<float*>(Bsp);
@@ -153,13 +152,11 @@ __global__ __launch_bounds__(256) void cols_mfma_kernel(MfmaArgs a) {
             float val = 0.f;
             if (fl < nf && p < ppm) {
                 const int g = s % G, j = q * ppm + p;
-                float2 d = make_float2(0.f, 0.f);
-                if (mode != 2) d = D[(fl * G + g) * M + j];
+                float2 d = D[(fl * G + g) * M + j];
                 if (mode != 0) {
                     const float2 cf = coef[fl * G + g];
                     const float2 xh = a.Xh[(size_t)k * M + j], yh = a.Yh[(size_t)k * M + j];
-                    const float2 pl = make_float2(cf.x * xh.x + cf.y * yh.x, cf.x * xh.y + cf.y * yh.y);
-                    d = mode == 2 ? pl : csub(d, pl);
+                    d = csub(d, make_float2(cf.x * xh.x + cf.y * yh.x, cf.x * xh.y + cf.y * yh.y));
                 }
                 val = s < G ? d.x : d.y;
             }
@@ -197,27 +194,27 @@ __global__ __launch_bounds__(256) void cols_mfma_kernel(MfmaArgs a) {
         }
         __syncthreads();
         if (active) {
-            float2* dst = a.C + ((((size_t)(fb + f) * a.groups.count + gi) * L + l) * Kh + k) * M;
-            fft_pass2<M, +1>(t, xch, [&](int p, float2 v) { dst[p] = v; });
+            float2* dst = a.C + c_index(fb + f, l, L, M, k, 0);
+            fft_pass2<M, +1>(t, xch, [&](int p, float2 v) { dst[(size_t)(p >> 3) * (Kh * 8) + (p & 7)] = v; });
         }
         __syncthreads();
     }
 }
 
-size_t mfma_lds_bytes(int M, int NF, int gmax, int L) {
+size_t mfma_lds_bytes(int M, int NF, int G, int L) {
     const int N1 = M == 32 ? 8 : (M == 64 ? 8 : 16), N2 = M / N1;
     const int T = M == 256 ? 16 : (M == 32 ? 4 : 8);
-    return ((size_t)M + (size_t)(256 / T) * N1 * (N2 + 1) + (size_t)NF * gmax * M + (size_t)NF * L * M +
-            (size_t)NF * gmax) * sizeof(float2);
+    return ((size_t)M + (size_t)(256 / T) * N1 * (N2 + 1) + (size_t)NF * G * M + (size_t)NF * L * M +
+            (size_t)NF * G) * sizeof(float2);
 }
 
 namespace {
 
 template <int M, int NF>
 hipError_t launch_mfma_t(const MfmaArgs& a, int frames, hipStream_t s) {
-    const size_t lds = mfma_lds_bytes(M, NF, a.gmax, a.L);
+    const size_t lds = mfma_lds_bytes(M, NF, a.grp.G, a.L);
     allow_large_lds(reinterpret_cast<const void*>(&cols_mfma_kernel<M, NF>));
-    const dim3 grid(M / 2 + 1, a.groups.count, (frames + NF - 1) / NF);
+    const dim3 grid(M / 2 + 1, 1, (frames + NF - 1) / NF);
     hipLaunchKernelGGL((cols_mfma_kernel<M, NF>), grid, dim3(256), lds, s, a);
     return hipGetLastError();
 }

@@ -1,201 +1,275 @@
 // Output pass of SAFR's hard-real-time step (Alg. 1, last loop), fused with the
 // split-tomography sum (Sec. 3.3):
-//   - C2R row transforms of the layer spectra C[f][grp][l][k][p] (two real rows
-//     packed into one complex inverse FFT), scaled by 1/M^2 (IDFT2 of Sec. 3.2);
-//   - mixed asterisms: the natural-star layer (grid spacing pitch) is resampled
-//     bilinearly and periodically at the laser layer grid points (spacing
-//     c_l * pitch), i.e. at fractional index u = c_l (p - M/2) + M/2, and added.
-// One block of 256 threads writes RT output rows of one layer of one frame; the
-// natural-star rows it needs (at most RT + 1, since c_l <= 1) are transformed
-// in the same block.  All global loads of a phase are issued before any is used.
+//   - C2R row transforms of the layer spectra (two real rows packed into one
+//     complex inverse FFT), scaled by 1/M^2 (IDFT2 of Sec. 3.2);
+//   - mixed asterisms: the natural-star layers, sum_g b_g P[l][2g] + c_g P[l][2g+1]
+//     with the frame's tip/tilt plane coefficients (b_g, c_g) from the row-pass
+//     moments and the precomputed basis images P (already resampled onto the
+//     laser layer grids), added to every output pixel.
+//
+// One block of 256 threads owns RT rows of one layer and loops over a run of
+// frames, NF frames per iteration so that every team of the block transforms
+// one row pair: NF = (256 / T) / (RT / 2).  Each team's LDS region holds, in
+// turn, its two input rows (Hermitian half spectra), the pass-1 -> pass-2
+// exchange and its two output rows; loads of a phase are taken into registers
+// and a barrier separates them from the stores that overwrite the region.  The
+// next iteration's spectra are loaded into registers while the current one is
+// transformed.  The epilogue is pixel-stationary (thread -> 4-pixel groups of
+// the block's rows), so the basis images of those pixels stay in registers for
+// all frames of the block.
+//
+// C layout (row tiles of 8): C[f][l][p / 8][k][p % 8]; a block's rows of one
+// frame are one contiguous run.
 #include "fft_device.h"
 #include "safr_internal.h"
 
 namespace safr {
 
+namespace {
+
+constexpr int kBasisRegs = 8;       // natural-star basis images held in registers (the rest are re-read)
+
+template <int M, int RT>
+struct OutShape {
+    static constexpr int T = FftShape<M>::T;
+    static constexpr int NTEAM = 256 / T;
+    static constexpr int TL = team_lds<M>();
+    static constexpr int Kh = M / 2 + 1;
+    static constexpr int TPF = RT / 2;                              // row pairs (teams) per frame
+    static constexpr int NF = NTEAM / TPF;                          // frames per iteration
+    static constexpr int V4 = RT * M / (4 * 256);                   // 4-pixel groups per thread per frame
+    static constexpr int RUN4 = RT * Kh / 2;                        // float4 loads per frame
+    static constexpr int NLD = (NF * RUN4 + 255) / 256;             // float4 loads per thread per iteration
+    static_assert(TPF <= NTEAM && NTEAM % TPF == 0, "row pairs must tile the teams");
+    static_assert(V4 >= 1 && (RT * M) % 1024 == 0, "at least one 4-pixel group per thread");
+    static_assert(2 * Kh <= TL && M <= TL, "a team region holds two rows");
+};
+
+}  // namespace
+
 template <int M, int RT, bool MIXED>
 __global__ __launch_bounds__(256) void out_kernel(OutArgs a) {
     using S = FftShape<M>;
-    constexpr int T = S::T;
-    constexpr int Kh = M / 2 + 1;
-    constexpr int NTEAM = 256 / T;
-    constexpr int TL = team_lds<M>();
-    constexpr int NS = MIXED ? RT + 2 : 0;             // natural-star row slots
-    constexpr int TR = RT + NS;
+    using O = OutShape<M, RT>;
+    constexpr int T = O::T, TL = O::TL, Kh = O::Kh, NF = O::NF, TPF = O::TPF;
     extern __shared__ float2 smem[];
 
     const int l = blockIdx.y;
-    const int f = blockIdx.z;
     const int r0 = blockIdx.x * RT;
+    const int fbeg = blockIdx.z * a.frames_per_block;
+    const int fend = min(a.frames, fbeg + a.frames_per_block);
     const int tid = threadIdx.x;
     const int team = tid / T;
     const int t = tid % T;
-    const float cl = a.c[l];
-    const float hm = 0.5f * (float)M;
+    const int L = a.L;
 
-    float2* tws = smem;                                         // [M]
-    float2* xch = tws + M + team * TL;                          // [NTEAM][TL]
-    float2* tile = tws + M + NTEAM * TL;                        // [TR][Kh]
-    float* real = reinterpret_cast<float*>(tile + TR * Kh);     // [TR][M]
+    float2* tws = smem;                                             // [M]
+    float2* reg = tws + M + team * TL;                              // this team's region
+    float* coef = reinterpret_cast<float*>(tws + M + O::NTEAM * TL); // [NF][nb]
 
-    int nlo = 0, nrows = 0;
-    if (MIXED) {
-        nlo = (int)floorf(cl * ((float)r0 - hm) + hm);
-        const int nhi = (int)floorf(cl * ((float)(r0 + RT - 1) - hm) + hm) + 1;
-        nrows = nhi - nlo + 1;                                  // <= RT + 1
+    // spectra of frame f: RT rows of layer l = one run of RT * Kh float2 (two float2 per float4)
+    auto run = [&](int f) {
+        return reinterpret_cast<const float4*>(a.C + (((size_t)f * L + l) * (M / 8) + r0 / 8) * Kh * 8);
+    };
+    float4 ld[O::NLD];
+    auto issue = [&](int fi0) {
+#pragma unroll
+        for (int i = 0; i < O::NLD; ++i) {
+            const int e = tid + 256 * i;
+            const int fi = e / O::RUN4, s = e - fi * O::RUN4;
+            const int f = fi0 + fi;
+            ld[i] = (e < NF * O::RUN4 && f < fend) ? run(f)[s] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int i = 0; i < O::NLD; ++i) {
+            const int e = tid + 256 * i;
+            if (e >= NF * O::RUN4) break;
+            const int fi = e / O::RUN4, s = e - fi * O::RUN4;
+            // float2 index 2s -> tile, k, row pair
+            const int pb = (2 * s) / (Kh * 8), rem = (2 * s) - pb * Kh * 8;
+            const int k = rem >> 3, rr = rem & 7;
+            const int task = fi * TPF + (pb * 8 + rr) / 2;
+            float2* dst = smem + M + task * TL;
+            dst[k] = make_float2(ld[i].x, ld[i].y);
+            dst[Kh + k] = make_float2(ld[i].z, ld[i].w);
+        }
+    };
+
+    // natural-star basis images of this thread's pixels (first kBasisRegs of them)
+    float4 pb4[MIXED ? O::V4 : 1][MIXED ? kBasisRegs : 1];
+    if constexpr (MIXED) {
+#pragma unroll
+        for (int v = 0; v < O::V4; ++v) {
+            const int e = 4 * (tid + 256 * v);
+            const int r = e / M, q = e % M;
+#pragma unroll
+            for (int i = 0; i < kBasisRegs; ++i)
+                if (i < a.nb)
+                    pb4[v][i] = *reinterpret_cast<const float4*>(a.P + (((size_t)l * a.nb + i) * M + r0 + r) * M + q);
+        }
     }
 
-    const size_t lstride = (size_t)Kh * M;
-    const float2* Cl = a.C + ((size_t)f * a.groups + 0) * a.L * lstride + (size_t)l * lstride;
-    const float2* Cn = a.C + ((size_t)f * a.groups + a.ngs_group) * a.L * lstride + (size_t)l * lstride;
-
-    // issue every load of the block, then store to LDS: twiddles, laser rows, natural rows
-    constexpr int NL = (Kh * RT + 255) / 256;
-    constexpr int NN = (Kh * NS + 255) / 256;
     const float2 twv = tid < M ? a.tw[tid] : make_float2(0.f, 0.f);
-    float2 vl[NL], vn[NN > 0 ? NN : 1];
-#pragma unroll
-    for (int i = 0; i < NL; ++i) {
-        const int idx = tid + 256 * i;                          // r fastest: RT consecutive values per k
-        if (idx < Kh * RT) vl[i] = Cl[(size_t)(idx / RT) * M + r0 + (idx % RT)];
-    }
-    if constexpr (MIXED) {
-#pragma unroll
-        for (int i = 0; i < NN; ++i) {
-            const int idx = tid + 256 * i;
-            const int k = idx / NS, r = idx % NS;
-            if (idx < Kh * NS && r < nrows) vn[i] = Cn[(size_t)k * M + ((nlo + r) & (M - 1))];
-        }
-    }
+    issue(fbeg);
     if (tid < M) tws[tid] = twv;
-#pragma unroll
-    for (int i = 0; i < NL; ++i) {
-        const int idx = tid + 256 * i;
-        if (idx < Kh * RT) tile[(idx % RT) * Kh + idx / RT] = vl[i];
-    }
-    if constexpr (MIXED) {
-#pragma unroll
-        for (int i = 0; i < NN; ++i) {
-            const int idx = tid + 256 * i;
-            const int k = idx / NS, r = idx % NS;
-            if (idx < Kh * NS && r < nrows) tile[(RT + r) * Kh + k] = vn[i];
-        }
-    }
-    __syncthreads();
-
-    // packed C2R: Z[q] = A[q] + i B[q] over the Hermitian extension of the two rows
     const float scale = 1.0f / ((float)M * (float)M);
-    constexpr int LP = RT / 2;
-    const int np = (nrows + 1) / 2;
-    const int tasks = LP + np;
-    for (int base = 0; base < tasks; base += NTEAM) {
-        const int task = base + team;
-        const bool active = task < tasks;
-        int ra = 0, rb = -1;
-        if (active) {
-            if (task < LP) {
-                ra = 2 * task;
-                rb = ra + 1;
-            } else {
-                ra = RT + 2 * (task - LP);
-                rb = (2 * (task - LP) + 1 < nrows) ? ra + 1 : -1;
-            }
-            const float2* A = tile + ra * Kh;
-            const float2* Bv = tile + (rb >= 0 ? rb : ra) * Kh;
-            const bool hb = rb >= 0;
-            fft_pass1<M, +1>(t, xch, tws, [&](int q) -> float2 {
-                if (q == 0 || q == M / 2) return make_float2(A[q].x, hb ? Bv[q].x : 0.f);
-                if (q < M / 2) {
-                    const float2 x = A[q];
-                    const float2 y = hb ? Bv[q] : make_float2(0.f, 0.f);
-                    return make_float2(x.x - y.y, x.y + y.x);
-                }
-                const float2 x = A[M - q];
-                const float2 y = hb ? Bv[M - q] : make_float2(0.f, 0.f);
-                return make_float2(x.x + y.y, y.x - x.y);
-            });
-        }
-        __syncthreads();
-        if (active) {
-            float* oa = real + (size_t)ra * M;
-            float* ob = real + (size_t)(rb >= 0 ? rb : ra) * M;
-            const bool hb = rb >= 0;
-            fft_pass2<M, +1>(t, xch, [&](int p, float2 v) {
-                oa[p] = v.x * scale;
-                if (hb) ob[p] = v.y * scale;
-            });
-        }
-        __syncthreads();
-    }
 
-    // write rows (+ resampled natural-star layer)
-    float* out = a.out + (((size_t)f * a.L + l) * M + r0) * M;
-#pragma unroll
-    for (int i = 0; i < (RT * M + 255) / 256; ++i) {
-        const int idx = tid + 256 * i;
-        if (idx >= RT * M) break;
-        const int r = idx / M, q = idx % M;
-        float v = real[r * M + q];
+    for (int f0 = fbeg; f0 < fend; f0 += NF) {
+        __syncthreads();                                    // previous epilogue done with the regions
+        stash();
+        if (f0 + NF < fend) issue(f0 + NF);
         if constexpr (MIXED) {
-            const float u = cl * ((float)(r0 + r) - hm) + hm;
-            const float w = cl * ((float)q - hm) + hm;
-            const float fu0 = floorf(u), fw0 = floorf(w);
-            const float fu = u - fu0, fw = w - fw0;
-            const int i0 = min(max((int)fu0 - nlo, 0), nrows - 2);
-            const int j0 = ((int)fw0) & (M - 1);
-            const int j1 = (j0 + 1) & (M - 1);
-            const float* n0 = real + (size_t)(RT + i0) * M;
-            const float* n1 = n0 + M;
-            const float top = (1.f - fw) * n0[j0] + fw * n0[j1];
-            const float bot = (1.f - fw) * n1[j0] + fw * n1[j1];
-            v += (1.f - fu) * top + fu * bot;
+            const int ng = a.nb / 2;
+            if (tid < NF * ng) {
+                const int fi = tid / ng, g = tid - fi * ng;
+                const int f = min(f0 + fi, fend - 1);
+                const float* mo = a.mom + ((size_t)f * a.J + a.ngs_star[g]) * a.nchunk * 4;
+                float m0 = 0.f, m1 = 0.f, m2 = 0.f;
+                for (int c = 0; c < a.nchunk; ++c) {
+                    m0 += mo[4 * c + 0];
+                    m1 += mo[4 * c + 1];
+                    m2 += mo[4 * c + 2];
+                }
+                coef[fi * a.nb + 2 * g] = a.tt_b[0] * m0 + a.tt_b[1] * m1 + a.tt_b[2] * m2;
+                coef[fi * a.nb + 2 * g + 1] = a.tt_c[0] * m0 + a.tt_c[1] * m1 + a.tt_c[2] * m2;
+            }
         }
-        out[(size_t)r * M + q] = v;
+        __syncthreads();
+
+        // packed C2R: Z[q] = A[q] + i B[q] over the Hermitian extensions of the team's two rows
+        float2 x[S::N1];
+        {
+            const float2* A = reg;
+            const float2* B = reg + Kh;
+#pragma unroll
+            for (int n1 = 0; n1 < S::N1; ++n1) {
+                const int q = S::N2 * n1 + t;
+                float2 z;
+                if (q == 0 || q == M / 2) {
+                    z = make_float2(A[q].x, B[q].x);
+                } else if (q < M / 2) {
+                    const float2 u = A[q], w = B[q];
+                    z = make_float2(u.x - w.y, u.y + w.x);
+                } else {
+                    const float2 u = A[M - q], w = B[M - q];
+                    z = make_float2(u.x + w.y, w.x - u.y);
+                }
+                x[n1] = z;
+            }
+        }
+        __syncthreads();
+        fft_pass1_regs<M, +1>(t, reg, tws, x);
+        __syncthreads();
+        float2 z[S::N1 / S::T][S::N2];
+        fft_pass2_load<M>(t, reg, z);
+        __syncthreads();
+        {
+            float* rows = reinterpret_cast<float*>(reg);    // [2][M]
+            fft_pass2_regs<M, +1>(t, z, [&](int p, float2 v) {
+                rows[p] = v.x * scale;
+                rows[M + p] = v.y * scale;
+            });
+        }
+        __syncthreads();
+
+        // epilogue: 4-pixel groups, coalesced stores
+#pragma unroll
+        for (int fi = 0; fi < NF; ++fi) {
+            const int f = f0 + fi;
+            if (f >= fend) break;
+#pragma unroll
+            for (int v = 0; v < O::V4; ++v) {
+                const int e = 4 * (tid + 256 * v);
+                const int r = e / M, q = e % M;
+                const float* src = reinterpret_cast<const float*>(smem + M + (fi * TPF + r / 2) * TL) + (r & 1) * M + q;
+                float4 o = *reinterpret_cast<const float4*>(src);
+                if constexpr (MIXED) {
+                    const float* cf = coef + fi * a.nb;
+#pragma unroll
+                    for (int i = 0; i < kBasisRegs; ++i) {
+                        if (i < a.nb) {
+                            const float c = cf[i];
+                            o.x += c * pb4[v][i].x;
+                            o.y += c * pb4[v][i].y;
+                            o.z += c * pb4[v][i].z;
+                            o.w += c * pb4[v][i].w;
+                        }
+                    }
+                    for (int i = kBasisRegs; i < a.nb; ++i) {
+                        const float c = cf[i];
+                        const float4 pv =
+                            *reinterpret_cast<const float4*>(a.P + (((size_t)l * a.nb + i) * M + r0 + r) * M + q);
+                        o.x += c * pv.x;
+                        o.y += c * pv.y;
+                        o.z += c * pv.z;
+                        o.w += c * pv.w;
+                    }
+                }
+                *reinterpret_cast<float4*>(a.out + (((size_t)f * L + l) * M + r0 + r) * M + q) = o;
+            }
+        }
     }
 }
 
-size_t out_lds_bytes(int M, int RT, bool mixed) {
+bool out_rows_supported(int M, int RT) {
+    if (RT != 8 && RT != 16 && RT != 32) return false;
+    if (RT > M || RT * M < 1024) return false;
+    const int T = M == 256 ? 16 : (M == 32 ? 4 : 8);
+    return RT / 2 <= 256 / T;
+}
+
+int out_frames_per_iter(int M, int RT) {
+    const int T = M == 256 ? 16 : (M == 32 ? 4 : 8);
+    return (256 / T) / (RT / 2);
+}
+
+size_t out_lds_bytes(int M, int RT, int nb) {
     const int N1 = M == 32 ? 8 : (M == 64 ? 8 : 16), N2 = M / N1;
     const int T = M == 256 ? 16 : (M == 32 ? 4 : 8);
-    const int TR = RT + (mixed ? RT + 2 : 0);
-    return ((size_t)M + (size_t)(256 / T) * N1 * (N2 + 1) + (size_t)TR * (M / 2 + 1)) * sizeof(float2) +
-           (size_t)TR * M * sizeof(float);
+    const int NF = out_frames_per_iter(M, RT);
+    return ((size_t)M + (size_t)(256 / T) * N1 * (N2 + 1)) * sizeof(float2) + (size_t)NF * nb * sizeof(float);
 }
 
 namespace {
 
 template <int M, int RT, bool MIXED>
 hipError_t launch_out_t(const OutArgs& a, int frames, hipStream_t s) {
-    const size_t lds = out_lds_bytes(M, RT, MIXED);
+    const size_t lds = out_lds_bytes(M, RT, a.nb);
     allow_large_lds(reinterpret_cast<const void*>(&out_kernel<M, RT, MIXED>));
-    hipLaunchKernelGGL((out_kernel<M, RT, MIXED>), dim3(M / RT, a.L, frames), dim3(256), lds, s, a);
+    const int fpb = a.frames_per_block;
+    hipLaunchKernelGGL((out_kernel<M, RT, MIXED>), dim3(M / RT, a.L, (frames + fpb - 1) / fpb), dim3(256), lds, s,
+                       a);
     return hipGetLastError();
 }
 
 template <int M, bool MIXED>
-hipError_t launch_out_rt(const OutArgs& a, int frames, hipStream_t s) {
-    switch (a.rows_per_block) {
-        case 2: return launch_out_t<M, 2, MIXED>(a, frames, s);
-        case 4: return launch_out_t<M, 4, MIXED>(a, frames, s);
-        case 8: return launch_out_t<M, 8, MIXED>(a, frames, s);
-        case 16: return launch_out_t<M, 16, MIXED>(a, frames, s);
-        default: return hipErrorInvalidValue;
+hipError_t launch_out_rt(const OutArgs& a, int rt, int frames, hipStream_t s) {
+    if constexpr (M >= 128) {
+        if (rt == 8) return launch_out_t<M, 8, MIXED>(a, frames, s);
     }
+    if constexpr (M >= 64) {
+        if (rt == 16) return launch_out_t<M, 16, MIXED>(a, frames, s);
+    }
+    if (rt == 32) return launch_out_t<M, 32, MIXED>(a, frames, s);
+    return hipErrorInvalidValue;
 }
 
 template <int M>
-hipError_t launch_out_m(const OutArgs& a, int frames, hipStream_t s) {
-    return a.mixed ? launch_out_rt<M, true>(a, frames, s) : launch_out_rt<M, false>(a, frames, s);
+hipError_t launch_out_m(const OutArgs& a, int rt, int frames, hipStream_t s) {
+    return a.nb > 0 ? launch_out_rt<M, true>(a, rt, frames, s) : launch_out_rt<M, false>(a, rt, frames, s);
 }
 
 }  // namespace
 
-hipError_t launch_out(int M, const OutArgs& a, int frames, hipStream_t s) {
+hipError_t launch_out(int M, const OutArgs& a, int rows_per_block, int frames, hipStream_t s) {
+    if (!out_rows_supported(M, rows_per_block) || a.frames_per_block < 1) return hipErrorInvalidValue;
     switch (M) {
-        case 32: return launch_out_m<32>(a, frames, s);
-        case 64: return launch_out_m<64>(a, frames, s);
-        case 128: return launch_out_m<128>(a, frames, s);
-        case 256: return launch_out_m<256>(a, frames, s);
+        case 32: return launch_out_m<32>(a, rows_per_block, frames, s);
+        case 64: return launch_out_m<64>(a, rows_per_block, frames, s);
+        case 128: return launch_out_m<128>(a, rows_per_block, frames, s);
+        case 256: return launch_out_m<256>(a, rows_per_block, frames, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -75,6 +75,8 @@ struct safr_plan {
     float2* tw = nullptr;
     float2* Xh = nullptr;           // DFT2 of x * pupil (tip/tilt plane transforms), [Kh][M]
     float2* Yh = nullptr;
+    float* P = nullptr;             // natural-star basis images [L][nb][M][M] (mixed asterisms)
+    int nb = 0;
     unsigned char* pupil = nullptr;
     int* tt_mode = nullptr;
     void* ws_own = nullptr;
@@ -82,7 +84,7 @@ struct safr_plan {
     void* ws_user = nullptr;
     size_t ws_user_bytes = 0;
     // tuning
-    int row_teams = 0, out_rows = 0, mfma_frames = 16, col_frames = 1, col_prefetch = 1;
+    int row_teams = 0, out_rows = 0, out_frames = 1, mfma_frames = 16, col_frames = 1, col_nf = 1, col_prefetch = 1;
     int use_graph = 0;
     // graph cache
     hipGraphExec_t gexec = nullptr;
@@ -98,7 +100,7 @@ namespace {
 // workspace: row spectra R, layer column spectra C, partial moments (sized for the smallest row blocks)
 size_t ws_r(const safr_plan* p, int frames) { return align256((size_t)frames * p->J * p->Kh * p->n * sizeof(float2)); }
 size_t ws_c(const safr_plan* p, int frames) {
-    return align256((size_t)frames * p->ngroups * p->L * p->Kh * p->M * sizeof(float2));
+    return align256((size_t)frames * p->L * p->Kh * p->M * sizeof(float2));
 }
 size_t ws_m(const safr_plan* p, int frames) {
     return align256((size_t)frames * p->J * ((p->n + 1) / 2) * 4 * sizeof(float));
@@ -115,6 +117,7 @@ void free_plan(safr_plan* p) {
     hipFree(p->tw);
     hipFree(p->Xh);
     hipFree(p->Yh);
+    hipFree(p->P);
     hipFree(p->pupil);
     hipFree(p->tt_mode);
     hipFree(p->ws_own);
@@ -148,8 +151,8 @@ bool tt_inverse(const std::vector<unsigned char>& pup, int n, double inv[9]) {
 }
 
 // DFT2 (FP64, direct) of x * pupil and y * pupil zero-extended at offset p0, half spectrum [k][j].
-void tt_transforms(const std::vector<unsigned char>& pup, int n, int M, int p0, std::vector<float2>& X,
-                   std::vector<float2>& Y) {
+void tt_transforms(const std::vector<unsigned char>& pup, int n, int M, int p0, std::vector<double2>& X,
+                   std::vector<double2>& Y) {
     const int Kh = M / 2 + 1;
     const double half = 0.5 * (n - 1);
     auto w = [M](long e) {
@@ -174,8 +177,8 @@ void tt_transforms(const std::vector<unsigned char>& pup, int n, int M, int p0, 
             ryr[(size_t)p * Kh + k] = br;
             ryi[(size_t)p * Kh + k] = bi;
         }
-    X.assign((size_t)Kh * M, make_float2(0.f, 0.f));
-    Y.assign((size_t)Kh * M, make_float2(0.f, 0.f));
+    X.assign((size_t)Kh * M, make_double2(0.0, 0.0));
+    Y.assign((size_t)Kh * M, make_double2(0.0, 0.0));
     for (int k = 0; k < Kh; ++k)
         for (int j = 0; j < M; ++j) {
             double xr = 0, xi = 0, yr = 0, yi = 0;
@@ -189,8 +192,8 @@ void tt_transforms(const std::vector<unsigned char>& pup, int n, int M, int p0, 
                 yr += e.first * dr - e.second * di;
                 yi += e.first * di + e.second * dr;
             }
-            X[(size_t)k * M + j] = make_float2((float)xr, (float)xi);
-            Y[(size_t)k * M + j] = make_float2((float)yr, (float)yi);
+            X[(size_t)k * M + j] = make_double2(xr, xi);
+            Y[(size_t)k * M + j] = make_double2(yr, yi);
         }
 }
 
@@ -318,7 +321,10 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
     const int T = team_size(M);
     p->row_teams = std::min(256 / T, std::max(1, (n + 1) / 2));
     if (M == 256) p->row_teams = std::min(p->row_teams, 8);
-    p->out_rows = p->mixed ? (M == 256 ? 8 : 16) : 16;
+    p->out_rows = M >= 128 ? 8 : (M == 64 ? 16 : 32);
+    p->out_frames = out_frames_per_iter(M, p->out_rows);
+    p->col_nf = 2;
+    p->col_frames = 2;
 
     safr_status st = SAFR_OK;
     double2* W = nullptr;
@@ -328,6 +334,11 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
     float* phi = nullptr;
     float* mlp_dev = nullptr;
     int* dbad = nullptr;
+    double2* X64 = nullptr;
+    double2* Y64 = nullptr;
+    double2* tw64 = nullptr;
+    double2* Tb = nullptr;
+    double* Eb = nullptr;
     do {
         size_t total = 0, total32 = 0;
         const int cpw = 256 / M, kblocks = (p->Kh + cpw - 1) / cpw;
@@ -350,12 +361,21 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
         PC_TRY(hipMalloc(&p->B32, total32 * sizeof(float2)));
         PC_TRY(hipMemsetAsync(p->B32, 0, total32 * sizeof(float2), stream));
         if (p->mixed) {
-            std::vector<float2> X, Y;
+            std::vector<double2> X, Y;
             tt_transforms(pup, n, M, p->p0, X, Y);
-            PC_TRY(hipMalloc(&p->Xh, X.size() * sizeof(float2)));
-            PC_TRY(hipMalloc(&p->Yh, Y.size() * sizeof(float2)));
-            PC_TRY(hipMemcpy(p->Xh, X.data(), X.size() * sizeof(float2), hipMemcpyHostToDevice));
-            PC_TRY(hipMemcpy(p->Yh, Y.data(), Y.size() * sizeof(float2), hipMemcpyHostToDevice));
+            std::vector<float2> Xf(X.size()), Yf(Y.size());
+            for (size_t i = 0; i < X.size(); ++i) {
+                Xf[i] = make_float2((float)X[i].x, (float)X[i].y);
+                Yf[i] = make_float2((float)Y[i].x, (float)Y[i].y);
+            }
+            PC_TRY(hipMalloc(&p->Xh, Xf.size() * sizeof(float2)));
+            PC_TRY(hipMalloc(&p->Yh, Yf.size() * sizeof(float2)));
+            PC_TRY(hipMemcpy(p->Xh, Xf.data(), Xf.size() * sizeof(float2), hipMemcpyHostToDevice));
+            PC_TRY(hipMemcpy(p->Yh, Yf.data(), Yf.size() * sizeof(float2), hipMemcpyHostToDevice));
+            PC_TRY(hipMalloc(&X64, X.size() * sizeof(double2)));
+            PC_TRY(hipMalloc(&Y64, Y.size() * sizeof(double2)));
+            PC_TRY(hipMemcpy(X64, X.data(), X.size() * sizeof(double2), hipMemcpyHostToDevice));
+            PC_TRY(hipMemcpy(Y64, Y.data(), Y.size() * sizeof(double2), hipMemcpyHostToDevice));
         }
         std::vector<float2> tw(M);
         for (int e = 0; e < M; ++e)
@@ -422,31 +442,49 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
             st = fail(SAFR_ERR_NUMERIC, "non-finite value in the precomputed operator");
             break;
         }
-        // BF16 hi/lo tiles of the real-split B for the matrix-core apply (M <= 128)
+        // natural-star basis images of a mixed asterism (group 1 enters the output pass through them)
+        if (p->mixed) {
+            const int Gn = p->gsize[1];
+            p->nb = 2 * Gn;
+            std::vector<double2> t64(M);
+            for (int e = 0; e < M; ++e)
+                t64[e] = make_double2(std::cos(2.0 * M_PI * e / M), std::sin(2.0 * M_PI * e / M));
+            PC_TRY(hipMalloc(&tw64, M * sizeof(double2)));
+            PC_TRY(hipMemcpy(tw64, t64.data(), M * sizeof(double2), hipMemcpyHostToDevice));
+            PC_TRY(hipMalloc(&Tb, (size_t)L * p->nb * p->Kh * M * sizeof(double2)));
+            PC_TRY(hipMalloc(&Eb, (size_t)L * p->nb * M * M * sizeof(double)));
+            PC_TRY(hipMalloc(&p->P, (size_t)L * p->nb * M * M * sizeof(float)));
+            BasisArgs ba{};
+            ba.M = M;
+            ba.L = L;
+            ba.G = Gn;
+            for (int l = 0; l < L; ++l) ba.c[l] = cgrp[0][l];
+            ba.B64 = p->B64 + p->boff[1];
+            ba.X = X64;
+            ba.Y = Y64;
+            ba.tw64 = tw64;
+            ba.T = Tb;
+            ba.E = Eb;
+            ba.P = p->P;
+            PC_TRY(launch_ngs_basis(ba, stream));
+        }
+        // BF16 hi/lo tiles of the real-split B for the matrix-core apply (M <= 128), column group only
         if (M <= 128) {
-            const int gm = std::max(p->gsize[0], p->gsize[1]);
+            const int G = p->gsize[0];
             int nf = 0;
             for (int cand : {16, 8, 4})
-                if (!nf && mfma_lds_bytes(M, cand, gm, L) <= 160 * 1024) nf = cand;
+                if (!nf && mfma_lds_bytes(M, cand, G, L) <= 160 * 1024) nf = cand;
             if (nf) {
                 p->mfma_frames = nf;
-                size_t tot = 0;
-                for (int gi = 0; gi < p->ngroups; ++gi) {
-                    const int G = p->gsize[gi];
-                    const int lt = std::min(L, 8), ntile = (L + lt - 1) / lt;
-                    int ppm = std::max(1, std::min(16 / (2 * lt), 32 / (2 * G)));
-                    while (ppm & (ppm - 1)) --ppm;             // a power of two, so it divides M
-                    p->mf_lt[gi] = lt;
-                    p->mf_ntile[gi] = ntile;
-                    p->mf_ppm[gi] = ppm;
-                    p->apack_off[gi] = tot;
-                    tot += (size_t)p->Kh * (M / ppm) * ntile * 2 * 64 * 8;
-                }
+                const int lt = std::min(L, 8), ntile = (L + lt - 1) / lt;
+                int ppm = std::max(1, std::min(16 / (2 * lt), 32 / (2 * G)));
+                while (ppm & (ppm - 1)) --ppm;                 // a power of two, so it divides M
+                p->mf_lt[0] = lt;
+                p->mf_ntile[0] = ntile;
+                p->mf_ppm[0] = ppm;
+                const size_t tot = (size_t)p->Kh * (M / ppm) * ntile * 2 * 64 * 8;
                 PC_TRY(hipMalloc(&p->Apack, tot * sizeof(uint16_t)));
-                for (int gi = 0; gi < p->ngroups; ++gi)
-                    PC_TRY(launch_pack_bf16(M, L, p->gsize[gi], p->B32 + p->boff32[gi], p->Apack + p->apack_off[gi],
-                                            p->mf_lt[gi], p->mf_ntile[gi], p->mf_ppm[gi], stream));
-                if (st != SAFR_OK) break;
+                PC_TRY(launch_pack_bf16(M, L, G, p->B32 + p->boff32[0], p->Apack, lt, ntile, ppm, stream));
             }
         }
         p->ws_own_bytes = ws_bytes(p, 1);
@@ -461,6 +499,11 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
     hipFree(phi);
     hipFree(mlp_dev);
     hipFree(dbad);
+    hipFree(X64);
+    hipFree(Y64);
+    hipFree(tw64);
+    hipFree(Tb);
+    hipFree(Eb);
     if (st != SAFR_OK) {
         free_plan(p);
         return st;
@@ -655,31 +698,55 @@ safr_status safr_autotune(safr_plan* p, int frames, const float* wf, float* out,
         }
         p->row_teams = best;
     }
-    // output pass: rows per block
+    // output pass: rows per block, then frames per block (multiples of the frames one iteration transforms)
     if (st == SAFR_OK) {
-        int best = p->out_rows;
+        int best = p->out_rows, bestf = p->out_frames;
         double bt = 1e30;
-        for (int rows : {2, 4, 8, 16}) {
-            if (rows > p->M || out_lds_bytes(p->M, rows, p->mixed) > kMaxLds) continue;
-            p->out_rows = rows;
-            double ms = 0.0;
-            if ((st = time_stage(p, frames, wf, out, precision, ws, iters, s, ev, 2, &ms)) != SAFR_OK) break;
-            if (ms < bt) { bt = ms; best = rows; }
+        for (int rows : {8, 16, 32}) {
+            if (!out_rows_supported(p->M, rows) || out_lds_bytes(p->M, rows, p->nb) > kMaxLds) continue;
+            const int nf = out_frames_per_iter(p->M, rows);
+            for (int mult : {1, 2, 4, 8, 16}) {
+                if (mult > 1 && nf * mult / 2 >= frames) break;
+                p->out_rows = rows;
+                p->out_frames = nf * mult;
+                double ms = 0.0;
+                if ((st = time_stage(p, frames, wf, out, precision, ws, iters, s, ev, 2, &ms)) != SAFR_OK) break;
+                if (ms < bt) {
+                    bt = ms;
+                    best = rows;
+                    bestf = nf * mult;
+                }
+            }
+            if (st != SAFR_OK) break;
         }
         p->out_rows = best;
+        p->out_frames = bestf;
     }
-    // column pass (FP32): frames per block (B reused from registers across them)
-    if (st == SAFR_OK && precision == SAFR_FP32 && frames > 1) {
-        int best = p->col_frames;
+    // column pass (FP32): frames transformed together (B read once for them) and frames per block
+    if (st == SAFR_OK && precision == SAFR_FP32) {
+        int best = p->col_frames, bestn = p->col_nf;
         double bt = 1e30;
-        for (int cf : {1, 2, 4, 8, 16}) {
-            if (cf > frames) continue;
-            p->col_frames = cf;
-            double ms = 0.0;
-            if ((st = time_stage(p, frames, wf, out, precision, ws, iters, s, ev, 1, &ms)) != SAFR_OK) break;
-            if (ms < bt) { bt = ms; best = cf; }
+        const bool fixed = p->col_prefetch && cols_fixed_shape(p->M, p->L, p->gsize[0], p->mixed ? 1 : 0);
+        for (int nf : {1, 2, 4}) {
+            if (nf > 1 && (!fixed || nf > frames)) break;
+            if (cols_lds_bytes(p->M, p->gsize[0], p->L, nf, fixed) > kMaxLds) break;
+            for (int mult : {1, 2, 4, 8, 16}) {
+                const int cf = nf * mult;
+                if (mult > 1 && cf / 2 >= frames) break;
+                p->col_nf = nf;
+                p->col_frames = cf;
+                double ms = 0.0;
+                if ((st = time_stage(p, frames, wf, out, precision, ws, iters, s, ev, 1, &ms)) != SAFR_OK) break;
+                if (ms < bt) {
+                    bt = ms;
+                    best = cf;
+                    bestn = nf;
+                }
+            }
+            if (st != SAFR_OK) break;
         }
         p->col_frames = best;
+        p->col_nf = bestn;
     }
     for (auto& e : ev) hipEventDestroy(e);
     if (p->gexec) {                      // a captured graph holds the old launch shapes
@@ -692,6 +759,8 @@ safr_status safr_autotune(safr_plan* p, int frames, const float* wf, float* out,
         choice[0] = p->row_teams;
         choice[1] = p->out_rows;
         choice[2] = p->col_frames;
+        choice[3] = p->out_frames;
+        choice[4] = p->col_nf;
     }
     return st;
 }
@@ -863,16 +932,16 @@ safr_status safr_set_option(safr_plan* p, int option, int value) {
             p->row_teams = value;
             return SAFR_OK;
         case 2:
-            if (value != 2 && value != 4 && value != 8 && value != 16)
-                return fail(SAFR_ERR_ARG, "output rows per block must be 2, 4, 8 or 16");
-            if (out_lds_bytes(p->M, value, p->mixed) > kMaxLds)
+            if (!out_rows_supported(p->M, value))
+                return fail(SAFR_ERR_ARG, "output rows per block must be 8, 16 or 32, at most M and at least 1024 / M");
+            if (out_lds_bytes(p->M, value, p->nb) > kMaxLds)
                 return fail(SAFR_ERR_ARG, "%d output rows per block need more than 160 KiB of LDS", value);
             p->out_rows = value;
             return SAFR_OK;
         case 3:
             if (value != 4 && value != 8 && value != 16) return fail(SAFR_ERR_ARG, "frames per MFMA block: 4, 8 or 16");
             if (!p->Apack) return fail(SAFR_ERR_UNSUPPORTED, "BF16 path not available for this plan");
-            if (mfma_lds_bytes(p->M, value, std::max(p->gsize[0], p->gsize[1]), p->L) > kMaxLds)
+            if (mfma_lds_bytes(p->M, value, p->gsize[0], p->L) > kMaxLds)
                 return fail(SAFR_ERR_ARG, "%d frames per MFMA block need more than 160 KiB of LDS", value);
             p->mfma_frames = value;
             return SAFR_OK;
@@ -881,6 +950,17 @@ safr_status safr_set_option(safr_plan* p, int option, int value) {
             p->col_frames = value;
             return SAFR_OK;
         case 5: p->col_prefetch = value != 0; return SAFR_OK;
+        case 6:
+            if (value < 1 || value > 4096) return fail(SAFR_ERR_ARG, "bad frames per output block");
+            p->out_frames = value;
+            return SAFR_OK;
+        case 7:
+            if (value != 1 && value != 2 && value != 4)
+                return fail(SAFR_ERR_ARG, "frames transformed together in the column pass: 1, 2 or 4");
+            if (cols_lds_bytes(p->M, p->gsize[0], p->L, value, true) > kMaxLds)
+                return fail(SAFR_ERR_ARG, "%d frames together need more than 160 KiB of LDS", value);
+            p->col_nf = value;
+            return SAFR_OK;
         default: return fail(SAFR_ERR_ARG, "unknown option %d", option);
     }
 }
@@ -911,20 +991,14 @@ safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, in
     HIP_TRY(launch_rows(p->M, ra, frames, nchunk, p->row_teams, s));
     if (ev) HIP_TRY(hipEventRecord(ev[1], s));
 
-    GroupSet gs{};
-    gs.count = p->ngroups;
-    int gmax = 0;
-    for (int gi = 0; gi < p->ngroups; ++gi) {
-        gs.g[gi].G = p->gsize[gi];
-        gs.g[gi].mode = p->mixed ? (p->gkind[gi] == SAFR_LGS ? 1 : 2) : 0;
-        for (int m = 0; m < p->gsize[gi]; ++m) gs.g[gi].star[m] = p->gstar[gi][m];
-        gs.g[gi].b_off = p->boff32[gi];
-        gmax = std::max(gmax, p->gsize[gi]);
-    }
+    GroupArgs grp{};
+    grp.G = p->gsize[0];
+    grp.mode = p->mixed ? 1 : 0;
+    for (int m = 0; m < grp.G; ++m) grp.star[m] = p->gstar[0][m];
     if (precision == SAFR_FP32) {
         ColArgs ca{};
         ca.R = R;
-        ca.B = p->B32;
+        ca.B = p->B32 + p->boff32[0];
         ca.C = C;
         ca.tw = p->tw;
         ca.mom = mom;
@@ -934,30 +1008,29 @@ safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, in
             ca.tt_b[i] = p->tt_b[i];
             ca.tt_c[i] = p->tt_c[i];
         }
-        ca.groups = gs;
+        ca.grp = grp;
         ca.n = p->n;
         ca.J = p->J;
         ca.L = p->L;
         ca.p0 = p->p0;
         ca.frames = frames;
+        const bool fixed = p->col_prefetch && cols_fixed_shape(p->M, p->L, grp.G, grp.mode);
+        int nf = fixed ? p->col_nf : 1;
+        while (nf > 1 && nf > frames) nf /= 2;
         ca.frames_per_block = std::max(1, std::min(p->col_frames, frames));
         ca.nchunk = nchunk;
-        ca.gmax = gmax;
         ca.prefetch = p->col_prefetch;
-        HIP_TRY(launch_cols(p->M, ca, frames, s));
+        HIP_TRY(launch_cols(p->M, ca, nf, frames, s));
     } else {
         MfmaArgs ma{};
         ma.R = R;
         ma.Apack = p->Apack;
         ma.C = C;
         ma.tw = p->tw;
-        ma.groups = gs;
-        for (int gi = 0; gi < 2; ++gi) {
-            ma.a_off[gi] = p->apack_off[gi];
-            ma.lt[gi] = p->mf_lt[gi];
-            ma.ntile[gi] = p->mf_ntile[gi];
-            ma.ppm[gi] = p->mf_ppm[gi];
-        }
+        ma.grp = grp;
+        ma.lt = p->mf_lt[0];
+        ma.ntile = p->mf_ntile[0];
+        ma.ppm = p->mf_ppm[0];
         ma.mom = mom;
         ma.Xh = p->Xh;
         ma.Yh = p->Yh;
@@ -971,7 +1044,6 @@ safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, in
         ma.p0 = p->p0;
         ma.frames = frames;
         ma.nchunk = nchunk;
-        ma.gmax = gmax;
         HIP_TRY(launch_cols_mfma(p->M, ma, frames, p->mfma_frames, s));
     }
     if (ev) HIP_TRY(hipEventRecord(ev[2], s));
@@ -980,13 +1052,20 @@ safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, in
     oa.C = C;
     oa.out = out;
     oa.tw = p->tw;
-    for (int l = 0; l < p->L; ++l) oa.c[l] = (float)p->c_out[l];
+    oa.P = p->P;
+    oa.mom = mom;
+    for (int i = 0; i < 3; ++i) {
+        oa.tt_b[i] = p->tt_b[i];
+        oa.tt_c[i] = p->tt_c[i];
+    }
+    oa.nb = p->nb;
+    for (int m = 0; m < p->nb / 2; ++m) oa.ngs_star[m] = p->gstar[1][m];
     oa.L = p->L;
-    oa.groups = p->ngroups;
-    oa.mixed = p->mixed;
-    oa.rows_per_block = p->out_rows;
-    oa.ngs_group = p->mixed ? 1 : 0;
-    HIP_TRY(launch_out(p->M, oa, frames, s));
+    oa.J = p->J;
+    oa.nchunk = nchunk;
+    oa.frames = frames;
+    oa.frames_per_block = std::max(1, p->out_frames);
+    HIP_TRY(launch_out(p->M, oa, p->out_rows, frames, s));
     if (ev) HIP_TRY(hipEventRecord(ev[3], s));
     return SAFR_OK;
 }

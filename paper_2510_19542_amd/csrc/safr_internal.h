@@ -14,55 +14,62 @@ constexpr int kMaxL = SAFR_MAX_LAYERS;
 constexpr int kMaxJ = 2 * kMaxG;
 constexpr double kSqrtEps = 1.4901161193847656e-08;   // 2^-26: the learned filter's relative cutoff
 
-// Per-group description passed by value to the column kernel.
+// The star group the column kernels transform: all stars of a single-kind
+// asterism (mode 0), or the laser stars of a mixed one (mode 1: tip/tilt plane
+// removed).  The natural stars of a mixed asterism enter through precomputed
+// basis images in the output pass (Sec. 3.3).
 struct GroupArgs {
     int G;                  // stars in the group
-    int mode;               // 0 plain, 1 remove the tip/tilt plane, 2 keep only the plane
+    int mode;               // 0 plain, 1 remove the tip/tilt plane
     int star[kMaxG];        // star index of member g
-    size_t b_off;           // offset of the group's B in the FP32 B array (complex elements)
 };
 
-struct GroupSet {
-    int count;
-    GroupArgs g[2];
-};
-
-// Row pass (forward): pupil mask, tip/tilt handling and the R2C FFT of the n
+// Row pass (forward): pupil mask, tip/tilt moments and the R2C FFT of the n
 // nonzero rows of each zero-extended wavefront.  R layout [f][star][k][n].
 struct RowArgs {
     const float* wf;            // [F][J][n][n]
     float2* R;                  // [F][J][Kh][n]
     float* mom;                 // [F][J][nchunk][4] partial moments (sum v, sum x v, sum y v, 0)
     const unsigned char* pupil; // [n][n]
-    const int* tt_mode;         // [J]: 0 none, 1 remove tip/tilt, 2 keep tip/tilt
+    const int* tt_mode;         // [J]: 0 none, 1 remove tip/tilt, 2 plane only (moments, no transform)
     const float2* tw;           // (cos, sin)(2 pi e / M), e < M
     int n, J, p0, rows_per_block;
 };
 
-// Column pass: column FFT of the J spectra, per-frequency apply of B, inverse
-// column FFT of the L layer spectra.  C layout [f][group][l][k][p].
+// Layer spectra after the inverse column transforms, in row tiles of 8:
+// C[f][l][p / 8][k][p % 8] (float2), so that a tile of 8 rows is contiguous.
+__host__ __device__ inline size_t c_index(int f, int l, int L, int M, int k, int p) {
+    return ((((size_t)f * L + l) * (M / 8) + (p >> 3)) * (M / 2 + 1) + k) * 8 + (p & 7);
+}
+
+// Column pass: column FFT of the group's spectra, per-frequency apply of B,
+// inverse column FFT of the L layer spectra into C.
 struct ColArgs {
     const float2* R;            // [F][J][Kh][n]
-    const float2* B;            // per group: [column block][l][g][column in block][j] (FP32 complex)
-    float2* C;                  // [F][groups][L][Kh][M]
+    const float2* B;            // [column block][l][g][column in block][j] (FP32 complex)
+    float2* C;                  // see c_index
     const float2* tw;
     const float* mom;           // partial moments from the row pass
     const float2* Xh;           // DFT2 of x * pupil, [Kh][M]
     const float2* Yh;           // DFT2 of y * pupil, [Kh][M]
     float tt_b[3], tt_c[3];     // rows 1 and 2 of the inverse normal matrix of the fit of [1, x, y]
-    GroupSet groups;
-    int n, J, L, p0, frames, frames_per_block, nchunk, gmax;
-    int prefetch;               // 1 = keep the block's B in registers (L * G <= 64)
+    GroupArgs grp;
+    int n, J, L, p0, frames, frames_per_block, nchunk;
+    int prefetch;               // 1 = compile-time shape (d in registers, inputs prefetched), when available
 };
 
 // Output pass: C2R row transforms, scaling by 1/M^2, and (mixed asterisms) the
-// bilinear resample-and-add of the natural-star layers.
+// natural-star layers from the basis images.
 struct OutArgs {
-    const float2* C;            // [F][groups][L][Kh][M]
+    const float2* C;            // see c_index
     float* out;                 // [F][L][M][M]
     const float2* tw;
-    float c[kMaxL];             // output-grid cone coefficients (resample positions)
-    int L, groups, mixed, rows_per_block, ngs_group;
+    const float* P;             // [L][nb][M][M] natural-star basis images (mixed asterisms)
+    const float* mom;           // partial moments from the row pass
+    float tt_b[3], tt_c[3];
+    int ngs_star[kMaxG];        // star index of natural star g
+    int nb;                     // 2 x natural stars (0: no natural-star part)
+    int L, J, nchunk, frames, frames_per_block;
 };
 
 // BF16 hi/lo split apply on matrix cores (batched path).
@@ -75,12 +82,24 @@ struct MfmaArgs {
     const float2* Xh;
     const float2* Yh;
     float tt_b[3], tt_c[3];
-    GroupSet groups;
-    size_t a_off[2];            // per-group offset into Apack (uint16 elements)
-    int n, J, L, p0, frames, nchunk, gmax;
-    int lt[2];                  // layers per tile (per group)
-    int ntile[2];               // layer tiles per group
-    int ppm[2];                 // frequencies packed per matrix op (per group)
+    GroupArgs grp;
+    int n, J, L, p0, frames, nchunk;
+    int lt;                     // layers per tile
+    int ntile;                  // layer tiles
+    int ppm;                    // frequencies packed per matrix op
+};
+
+// Natural-star basis images (FP64 precompute of a mixed asterism).
+struct BasisArgs {
+    int M, L, G;                // G natural stars
+    double c[kMaxL];            // laser-grid cone coefficients (resample positions)
+    const double2* B64;         // natural group's B, [Kh][L][G][M]
+    const double2* X;           // DFT2 of x * pupil, [Kh][M]
+    const double2* Y;           // DFT2 of y * pupil, [Kh][M]
+    const double2* tw64;        // e^(2 pi i e / M), e < M
+    double2* T;                 // scratch [L * G * 2][Kh][M]
+    double* E;                  // scratch [L * G * 2][M][M]
+    float* P;                   // [L][2 G][M][M]
 };
 
 // Lets a kernel use up to the full 160 KiB of LDS of a gfx950 compute unit (once per kernel).
@@ -96,13 +115,17 @@ inline void allow_large_lds(const void* kernel) {
 
 // Launchers (defined in the .hip files); return hipSuccess or the launch error.
 hipError_t launch_rows(int M, const RowArgs& a, int frames, int nchunk, int teams, hipStream_t s);
-hipError_t launch_cols(int M, const ColArgs& a, int frames, hipStream_t s);
-hipError_t launch_out(int M, const OutArgs& a, int frames, hipStream_t s);
+hipError_t launch_cols(int M, const ColArgs& a, int frames_together, int frames, hipStream_t s);
+bool cols_fixed_shape(int M, int L, int G, int mode);
+hipError_t launch_out(int M, const OutArgs& a, int rows_per_block, int frames, hipStream_t s);
+hipError_t launch_ngs_basis(const BasisArgs& a, hipStream_t s);
+bool out_rows_supported(int M, int rows_per_block);
+int out_frames_per_iter(int M, int rows_per_block);
 hipError_t launch_cols_mfma(int M, const MfmaArgs& a, int frames, int frames_per_block, hipStream_t s);
 size_t rows_lds_bytes(int M, int n, int teams);
-size_t out_lds_bytes(int M, int rows_per_block, bool mixed);
+size_t out_lds_bytes(int M, int rows_per_block, int nb);
 size_t mfma_lds_bytes(int M, int frames_per_block, int gmax, int L);
-size_t cols_lds_bytes(int M, int gmax, int L);
+size_t cols_lds_bytes(int M, int G, int L, int frames_together, bool fixed);
 
 // Precompute (FP64): SVD per half-spectrum frequency and the assembly of B.
 struct PrecompArgs {

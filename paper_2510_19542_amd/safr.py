@@ -23,7 +23,7 @@ SAFR_NGS, SAFR_LGS = 0, 1
 SAFR_FILTER_TIKHONOV, SAFR_FILTER_MLP = 0, 1
 SAFR_FP32, SAFR_BF16X3 = 0, 1
 SAFR_OPT_GRAPH, SAFR_OPT_ROW_TEAMS, SAFR_OPT_OUT_ROWS, SAFR_OPT_MFMA_FRAMES, SAFR_OPT_COL_FRAMES = 0, 1, 2, 3, 4
-SAFR_OPT_COL_PREFETCH = 5
+SAFR_OPT_COL_PREFETCH, SAFR_OPT_OUT_FRAMES, SAFR_OPT_COL_TOGETHER = 5, 6, 7
 SAFR_MAX_LAYERS = 16
 SAFR_MLP_PARAMS = 8705
 
@@ -235,8 +235,9 @@ def safr_time_stages(plan: Plan, frames: int, wavefronts, layers, precision: int
 def safr_autotune(plan: Plan, frames: int, wavefronts, layers, precision: int = SAFR_FP32, iters: int = 10,
                   stream=None):
     """Times the admissible block shapes of each stage and keeps the fastest; returns
-    (row teams, output rows per block, column frames per block)."""
-    ch = (ctypes.c_int * 3)()
+    (row teams, output rows per block, column frames per block, output frames per block,
+    column frames transformed together)."""
+    ch = (ctypes.c_int * 5)()
     _check(lib().safr_autotune(plan._as_parameter_, int(frames), _ptr(wavefronts), _ptr(layers), int(precision),
                                int(iters), _stream(stream), ch))
     return tuple(int(x) for x in ch)

@@ -222,23 +222,28 @@ def test_tuning_options_do_not_change_results():
     S = _lib()
     geo = _geo("C2")
     plan = S.precompute_geometry(geo)
-    wf = torch.from_numpy(synth.random_wavefronts(geo, 1)[0]).cuda()
-    ref = S.reconstruct(plan, wf)
+    F = 5
+    wf = torch.from_numpy(synth.random_wavefronts(geo, F)).cuda()
+    ref = S.reconstruct(plan, wf).cpu().numpy().astype(np.float64)
     for teams in (1, 4, 16):
-        for rows in (2, 4, 8, 16):
-            S.safr_set_option(plan, S.SAFR_OPT_ROW_TEAMS, teams)
-            S.safr_set_option(plan, S.SAFR_OPT_OUT_ROWS, rows)
-            got = S.reconstruct(plan, wf)
-            torch.cuda.synchronize()
-            # a different row pairing in the packed transforms changes only the rounding
-            assert rel_l2(got.cpu().numpy(), ref.cpu().numpy().astype(np.float64)) <= 1e-6, (teams, rows)
+        for rows in (8, 16, 32):
+            for ofr in (1, 3, 8):
+                S.safr_set_option(plan, S.SAFR_OPT_ROW_TEAMS, teams)
+                S.safr_set_option(plan, S.SAFR_OPT_OUT_ROWS, rows)
+                S.safr_set_option(plan, S.SAFR_OPT_OUT_FRAMES, ofr)
+                got = S.reconstruct(plan, wf)
+                torch.cuda.synchronize()
+                # a different row pairing in the packed transforms changes only the rounding
+                for f in range(F):
+                    assert rel_l2(got[f].cpu().numpy(), ref[f]) <= 1e-6, (teams, rows, ofr, f)
 
 
-def test_oversized_output_tile_is_rejected():
+@pytest.mark.parametrize("name,rows", [("C2", 64), ("C2", 4), ("C1", 8), ("C2", 0)])
+def test_unsupported_output_tile_is_rejected(name, rows):
     S = _lib()
-    plan = S.precompute_geometry(_geo("C2"))
+    plan = S.precompute_geometry(_geo(name))
     with pytest.raises(S.SafrError) as e:
-        S.safr_set_option(plan, S.SAFR_OPT_OUT_ROWS, 64)       # would need more than 160 KiB of LDS
+        S.safr_set_option(plan, S.SAFR_OPT_OUT_ROWS, rows)     # not 8/16/32, or fewer than 1024 / M
     assert e.value.status == S.SAFR_ERR_ARG
 
 
@@ -266,8 +271,8 @@ def test_autotune_picks_valid_shapes_and_keeps_results():
     ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
     S.safr_set_workspace(plan, (ws.data_ptr() + 255) & ~255, need)
     out = torch.empty((F, geo.L, geo.M, geo.M), device="cuda")
-    teams, rows, cf = S.safr_autotune(plan, F, wf, out, S.SAFR_FP32, 2)
-    assert teams in (1, 2, 4, 8, 16) and rows in (2, 4, 8, 16) and 1 <= cf <= F
+    teams, rows, cf, ofr, nf = S.safr_autotune(plan, F, wf, out, S.SAFR_FP32, 2)
+    assert teams in (1, 2, 4, 8, 16) and rows in (8, 16, 32) and 1 <= cf <= 2 * F and ofr >= 1 and nf in (1, 2, 4)
     S.safr_reconstruct_batched(plan, F, wf, out)
     torch.cuda.synchronize()
     assert rel_l2(out.cpu().numpy(), ref) <= 1e-6
