@@ -30,7 +30,10 @@
 //
 // cols_kernel<M, NF, G, L, MODE> with compile-time G, L (the configured
 // geometries) keeps d in registers; G = L = 0 is the generic kernel (any shape,
-// NF = 1, separate star and layer slots, d re-read from LDS).
+// NF = 1, separate star and layer slots, d re-read from LDS).  The apply reads
+// the G entries of B of each layer just before its products: requesting all
+// L x G entries up front (or keeping them in registers across frames) does not
+// fit the register file next to the transforms at M = 256 and spills.
 #include "fft_device.h"
 #include "safr_internal.h"
 
@@ -74,7 +77,7 @@ __device__ __forceinline__ bool xcd_work(int nwork, int& w) {
 template <int M, int NF, int GC, int LC, int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 2 : 3))) void cols_kernel(ColArgs a) {
     using S = FftShape<M>;
-    constexpr int T = S::T, N1 = S::N1, NTEAM = 256 / T, TL = team_lds<M>();
+    constexpr int T = S::T, N1 = S::N1, NTEAM = 256 / T, TL = team_lds<M>() + 2;   // slot stride, 4 banks apart
     constexpr int CPW = 256 / M, Kh = M / 2 + 1;
     constexpr bool FIX = GC > 0;
     const int G = FIX ? GC : a.grp.G;
@@ -259,7 +262,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
 
 size_t cols_lds_bytes(int M, int G, int L, int nf, bool fixed) {
     const int N1 = M == 32 ? 8 : (M == 64 ? 8 : 16), N2 = M / N1;
-    const size_t tl = (size_t)N1 * (N2 + 1);
+    const size_t tl = (size_t)N1 * (N2 + 1) + 2;
     const int spf = fixed ? (G > L ? G : L) : G + L;
     return ((size_t)M + (size_t)(256 / M) * nf * spf * tl + (size_t)nf * G) * sizeof(float2);
 }

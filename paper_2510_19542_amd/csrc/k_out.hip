@@ -27,13 +27,20 @@ namespace safr {
 
 namespace {
 
-constexpr int kBasisRegs = 8;       // natural-star basis images held in registers (the rest are re-read)
+// linear block -> (row block, layer, frame run), XCD-contiguous (blocks are dealt to the 8 XCDs
+// round-robin), so the frame runs of one row block and layer share an L2 and its basis pixels
+__device__ __forceinline__ bool xcd_work(int nwork, int& w) {
+    const int b = blockIdx.x, per = gridDim.x / 8;
+    w = (b % 8) * per + b / 8;
+    return w < nwork;
+}
 
 template <int M, int RT>
 struct OutShape {
     static constexpr int T = FftShape<M>::T;
     static constexpr int NTEAM = 256 / T;
     static constexpr int TL = team_lds<M>();
+    static constexpr int RS = TL + 2;                               // region stride: 16-byte aligned, 4 banks apart
     static constexpr int Kh = M / 2 + 1;
     static constexpr int TPF = RT / 2;                              // row pairs (teams) per frame
     static constexpr int NF = NTEAM / TPF;                          // frames per iteration
@@ -47,16 +54,21 @@ struct OutShape {
 
 }  // namespace
 
-template <int M, int RT, bool MIXED>
+// NB: natural-star basis images held in registers (0: none; a.nb <= NB, the rest are re-read)
+template <int M, int RT, int NB>
 __global__ __launch_bounds__(256) void out_kernel(OutArgs a) {
+    constexpr bool MIXED = NB > 0;
     using S = FftShape<M>;
     using O = OutShape<M, RT>;
-    constexpr int T = O::T, TL = O::TL, Kh = O::Kh, NF = O::NF, TPF = O::TPF;
+    constexpr int T = O::T, RS = O::RS, Kh = O::Kh, NF = O::NF, TPF = O::TPF;
     extern __shared__ float2 smem[];
 
-    const int l = blockIdx.y;
-    const int r0 = blockIdx.x * RT;
-    const int fbeg = blockIdx.z * a.frames_per_block;
+    const int runs = (a.frames + a.frames_per_block - 1) / a.frames_per_block;
+    int w;
+    if (!xcd_work((M / RT) * a.L * runs, w)) return;               // the whole block leaves before any barrier
+    const int frun = w % runs, l = (w / runs) % a.L;
+    const int r0 = (w / runs / a.L) * RT;
+    const int fbeg = frun * a.frames_per_block;
     const int fend = min(a.frames, fbeg + a.frames_per_block);
     const int tid = threadIdx.x;
     const int team = tid / T;
@@ -64,8 +76,8 @@ __global__ __launch_bounds__(256) void out_kernel(OutArgs a) {
     const int L = a.L;
 
     float2* tws = smem;                                             // [M]
-    float2* reg = tws + M + team * TL;                              // this team's region
-    float* coef = reinterpret_cast<float*>(tws + M + O::NTEAM * TL); // [NF][nb]
+    float2* reg = tws + M + team * RS;                              // this team's region
+    float* coef = reinterpret_cast<float*>(tws + M + O::NTEAM * RS); // [NF][nb]
 
     // spectra of frame f: RT rows of layer l = one run of RT * Kh float2 (two float2 per float4)
     auto run = [&](int f) {
@@ -91,21 +103,21 @@ __global__ __launch_bounds__(256) void out_kernel(OutArgs a) {
             const int pb = (2 * s) / (Kh * 8), rem = (2 * s) - pb * Kh * 8;
             const int k = rem >> 3, rr = rem & 7;
             const int task = fi * TPF + (pb * 8 + rr) / 2;
-            float2* dst = smem + M + task * TL;
+            float2* dst = smem + M + task * RS;
             dst[k] = make_float2(ld[i].x, ld[i].y);
             dst[Kh + k] = make_float2(ld[i].z, ld[i].w);
         }
     };
 
-    // natural-star basis images of this thread's pixels (first kBasisRegs of them)
-    float4 pb4[MIXED ? O::V4 : 1][MIXED ? kBasisRegs : 1];
+    // natural-star basis images of this thread's pixels
+    float4 pb4[MIXED ? O::V4 : 1][MIXED ? NB : 1];
     if constexpr (MIXED) {
 #pragma unroll
         for (int v = 0; v < O::V4; ++v) {
             const int e = 4 * (tid + 256 * v);
             const int r = e / M, q = e % M;
 #pragma unroll
-            for (int i = 0; i < kBasisRegs; ++i)
+            for (int i = 0; i < NB; ++i)
                 if (i < a.nb)
                     pb4[v][i] = *reinterpret_cast<const float4*>(a.P + (((size_t)l * a.nb + i) * M + r0 + r) * M + q);
         }
@@ -183,12 +195,12 @@ __global__ __launch_bounds__(256) void out_kernel(OutArgs a) {
             for (int v = 0; v < O::V4; ++v) {
                 const int e = 4 * (tid + 256 * v);
                 const int r = e / M, q = e % M;
-                const float* src = reinterpret_cast<const float*>(smem + M + (fi * TPF + r / 2) * TL) + (r & 1) * M + q;
+                const float* src = reinterpret_cast<const float*>(smem + M + (fi * TPF + r / 2) * RS) + (r & 1) * M + q;
                 float4 o = *reinterpret_cast<const float4*>(src);
                 if constexpr (MIXED) {
                     const float* cf = coef + fi * a.nb;
 #pragma unroll
-                    for (int i = 0; i < kBasisRegs; ++i) {
+                    for (int i = 0; i < NB; ++i) {
                         if (i < a.nb) {
                             const float c = cf[i];
                             o.x += c * pb4[v][i].x;
@@ -197,7 +209,7 @@ __global__ __launch_bounds__(256) void out_kernel(OutArgs a) {
                             o.w += c * pb4[v][i].w;
                         }
                     }
-                    for (int i = kBasisRegs; i < a.nb; ++i) {
+                    for (int i = NB; i < a.nb; ++i) {
                         const float c = cf[i];
                         const float4 pv =
                             *reinterpret_cast<const float4*>(a.P + (((size_t)l * a.nb + i) * M + r0 + r) * M + q);
@@ -229,36 +241,43 @@ size_t out_lds_bytes(int M, int RT, int nb) {
     const int N1 = M == 32 ? 8 : (M == 64 ? 8 : 16), N2 = M / N1;
     const int T = M == 256 ? 16 : (M == 32 ? 4 : 8);
     const int NF = out_frames_per_iter(M, RT);
-    return ((size_t)M + (size_t)(256 / T) * N1 * (N2 + 1)) * sizeof(float2) + (size_t)NF * nb * sizeof(float);
+    return ((size_t)M + (size_t)(256 / T) * (N1 * (N2 + 1) + 2)) * sizeof(float2) + (size_t)NF * nb * sizeof(float);
 }
 
 namespace {
 
-template <int M, int RT, bool MIXED>
+template <int M, int RT, int NB>
 hipError_t launch_out_t(const OutArgs& a, int frames, hipStream_t s) {
     const size_t lds = out_lds_bytes(M, RT, a.nb);
-    allow_large_lds(reinterpret_cast<const void*>(&out_kernel<M, RT, MIXED>));
+    allow_large_lds(reinterpret_cast<const void*>(&out_kernel<M, RT, NB>));
     const int fpb = a.frames_per_block;
-    hipLaunchKernelGGL((out_kernel<M, RT, MIXED>), dim3(M / RT, a.L, (frames + fpb - 1) / fpb), dim3(256), lds, s,
-                       a);
+    const int nwork = (M / RT) * a.L * ((frames + fpb - 1) / fpb);
+    hipLaunchKernelGGL((out_kernel<M, RT, NB>), dim3((nwork + 7) / 8 * 8), dim3(256), lds, s, a);
     return hipGetLastError();
 }
 
-template <int M, bool MIXED>
+template <int M, int NB>
 hipError_t launch_out_rt(const OutArgs& a, int rt, int frames, hipStream_t s) {
     if constexpr (M >= 128) {
-        if (rt == 8) return launch_out_t<M, 8, MIXED>(a, frames, s);
+        if (rt == 8) return launch_out_t<M, 8, NB>(a, frames, s);
     }
     if constexpr (M >= 64) {
-        if (rt == 16) return launch_out_t<M, 16, MIXED>(a, frames, s);
+        if (rt == 16) return launch_out_t<M, 16, NB>(a, frames, s);
     }
-    if (rt == 32) return launch_out_t<M, 32, MIXED>(a, frames, s);
+    if (rt == 32) return launch_out_t<M, 32, NB>(a, frames, s);
     return hipErrorInvalidValue;
 }
 
+// basis images in registers: exactly 2, 4 or 6 of them (one to three natural stars), else the first 8
 template <int M>
 hipError_t launch_out_m(const OutArgs& a, int rt, int frames, hipStream_t s) {
-    return a.nb > 0 ? launch_out_rt<M, true>(a, rt, frames, s) : launch_out_rt<M, false>(a, rt, frames, s);
+    switch (a.nb) {
+        case 0: return launch_out_rt<M, 0>(a, rt, frames, s);
+        case 2: return launch_out_rt<M, 2>(a, rt, frames, s);
+        case 4: return launch_out_rt<M, 4>(a, rt, frames, s);
+        case 6: return launch_out_rt<M, 6>(a, rt, frames, s);
+        default: return launch_out_rt<M, 8>(a, rt, frames, s);
+    }
 }
 
 }  // namespace

@@ -323,8 +323,8 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
     if (M == 256) p->row_teams = std::min(p->row_teams, 8);
     p->out_rows = M >= 128 ? 8 : (M == 64 ? 16 : 32);
     p->out_frames = out_frames_per_iter(M, p->out_rows);
-    p->col_nf = 2;
-    p->col_frames = 2;
+    p->col_nf = M == 256 ? 4 : 2;           // 4 frames at once spill registers at M = 128
+    p->col_frames = p->col_nf;
 
     safr_status st = SAFR_OK;
     double2* W = nullptr;
@@ -730,7 +730,7 @@ safr_status safr_autotune(safr_plan* p, int frames, const float* wf, float* out,
         for (int nf : {1, 2, 4}) {
             if (nf > 1 && (!fixed || nf > frames)) break;
             if (cols_lds_bytes(p->M, p->gsize[0], p->L, nf, fixed) > kMaxLds) break;
-            for (int mult : {1, 2, 4, 8, 16}) {
+            for (int mult : {1, 2, 4, 8}) {
                 const int cf = nf * mult;
                 if (mult > 1 && cf / 2 >= frames) break;
                 p->col_nf = nf;
