@@ -40,13 +40,12 @@ __global__ void rows_kernel(RowArgs a) {
     const float* wf = a.wf + ((size_t)f * a.J + star) * (size_t)n * n + (size_t)r0 * n;
     const unsigned char* pup = a.pupil + (size_t)r0 * n;
 
-    // LDS: twiddles [M], then per team (stride TS, odd so that teams fall on different banks)
-    // the pass-1 -> pass-2 exchange [TL] and the packed spectrum [M], then the staged rows, then
-    // 3 floats per wavefront for the moment reduction
-    constexpr int TS = TL + M + 1;
+    // LDS: twiddles [M], then one region per team (stride TS, 4 banks apart) that holds in turn the
+    // pass-1 -> pass-2 exchange and the packed spectrum, then the staged rows, then 3 floats per
+    // wavefront for the moment reduction
+    constexpr int TS = TL + 2;
     float2* tws = smem;
     float2* xch = smem + M + team * TS;
-    float2* zb = xch + TL;
     float* vals = reinterpret_cast<float*>(smem + M + nteams * TS);
     float* red = vals + a.rows_per_block * n;
 
@@ -131,14 +130,17 @@ __global__ void rows_kernel(RowArgs a) {
             });
         }
         __syncthreads();
-        if (active) fft_pass2<M, -1>(t, xch, [&](int k, float2 v) { zb[k] = v; });
+        float2 zr[S::N1 / T][S::N2];
+        if (active) fft_pass2_load<M>(t, xch, zr);
+        __syncthreads();
+        if (active) fft_pass2_regs<M, -1>(t, zr, [&](int k, float2 v) { xch[k] = v; });
         __syncthreads();
         // separate the two real rows and write the half spectrum, rows contiguous
         const int nrow = min(2 * nteams, rows - 2 * base);
         for (int idx = tid; idx < Kh * nrow; idx += nthr) {
             const int k = idx / nrow;
             const int r = idx - k * nrow;
-            const float2* z = smem + M + (r >> 1) * TS + TL;
+            const float2* z = smem + M + (r >> 1) * TS;
             const float2 zk = z[k];
             const float2 zm = cconj(z[(M - k) & (M - 1)]);
             float2 v;
@@ -175,7 +177,7 @@ hipError_t launch_rows(int M, const RowArgs& a, int frames, int nchunk, int team
 
 size_t rows_lds_bytes(int M, int n, int teams) {
     const int N1 = M == 32 ? 8 : (M == 64 ? 8 : 16), N2 = M / N1;
-    return ((size_t)M + (size_t)teams * (N1 * (N2 + 1) + M + 1)) * sizeof(float2) +
+    return ((size_t)M + (size_t)teams * (N1 * (N2 + 1) + 2)) * sizeof(float2) +
            (size_t)(2 * teams) * n * sizeof(float) + 64 * sizeof(float);
 }
 
