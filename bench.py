@@ -27,6 +27,33 @@ if ROOT not in sys.path:
 
 METRIC = "SAFR frames/s at MORFEO scale (J=9,L=9,256²) + HBM/MFMA roofline % at rel-L2≤1e-4"
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3          # MI355X FP32 vector peak (published)
+
+# launch shapes of the MORFEO-like plans, chosen by safr_autotune on an MI355X
+# (row teams, output rows, column frames per block, output frames per block, column frames together)
+TUNED_BATCHED = (16, 8, 4, 8, 4)
+TUNED_SINGLE = (1, 8, 1, 4, 1)
+
+
+def apply_shape(S, plan, shape):
+    for opt, v in zip((S.SAFR_OPT_ROW_TEAMS, S.SAFR_OPT_OUT_ROWS, S.SAFR_OPT_COL_FRAMES, S.SAFR_OPT_OUT_FRAMES,
+                       S.SAFR_OPT_COL_TOGETHER), shape):
+        S.safr_set_option(plan, opt, int(v))
+
+
+def algorithmic_flops(desc, frames=1):
+    """Operation count of the method per the cost model of Table 1 (benchFFT convention
+    2.5 N log2 N per real 2-D transform of N = M^2 points; 8 L J per half-spectrum frequency
+    for the apply): J forward and (groups x L) inverse transforms.  Attributed to the passes
+    as rows = half the forward transforms, cols = the other half + the apply + half the inverse
+    transforms, out = the other half of the inverse transforms."""
+    import math
+    M, J, L, G = desc.M, desc.J, desc.L, desc.groups
+    N = M * M
+    fft = 2.5 * N * math.log2(N)
+    fwd, inv, app = J * fft, G * L * fft, 8.0 * L * J * (M // 2 + 1) * M
+    per = {"rows": fwd / 2, "cols": fwd / 2 + app + inv / 2, "out": inv / 2}
+    return {"step": frames * (fwd + inv + app), "per_kernel": {k: frames * v for k, v in per.items()}}
 
 
 def algorithmic_bytes(desc, n, frames=1):
@@ -235,7 +262,11 @@ def main():
     ap.add_argument("--single-calls", type=int, default=2000, help="one-frame calls timed for the latency figure")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--autotune", action="store_true", help="re-tune the launch shapes instead of the stored ones")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="time the batched step only (no single-frame, extra or CPU legs): for counter runs")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="after timing, copy 256 MiB device to device three times (counter calibration)")
     ap.add_argument("--no-extras", action="store_true", help="skip the 1024-frame, learned-filter and mixed-size runs")
     ap.add_argument("--c4-frames", type=int, default=20000, help="training frames of the learned filter")
     args = ap.parse_args()
@@ -263,11 +294,14 @@ def main():
     ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
     S.safr_set_workspace(plan, (ws.data_ptr() + 255) & ~255, need)
     stream = torch.cuda.current_stream()
-    tuned = tuned1 = None
-    if not args.no_autotune:
+    if args.autotune:
         tuned = S.safr_autotune(plan, F, pool[:F], out, S.SAFR_FP32, 5, stream)
         tuned1 = S.safr_autotune(plan1, 1, pool[0], out[0], S.SAFR_FP32, 20, stream)
         print(f"bench: autotuned batched {tuned}, single {tuned1}", file=sys.stderr, flush=True)
+    else:
+        tuned, tuned1 = TUNED_BATCHED, TUNED_SINGLE
+        apply_shape(S, plan, tuned)
+        apply_shape(S, plan1, tuned1)
 
     # batched throughput: each step reconstructs F frames in one call
     batches = [pool[:F], pool[F:]]
@@ -284,25 +318,46 @@ def main():
     ms_step = t0.elapsed_time(t1) / args.steps
     fps = F * 1000.0 / ms_step
 
-    # single-frame calls (the real-time mode): latency per frame
-    for i in range(200):
-        S.safr_reconstruct(plan1, pool[i % len(pool)], out[0], stream)
-    torch.cuda.synchronize()
-    t0.record(stream)
-    for i in range(args.single_calls):
-        S.safr_reconstruct(plan1, pool[i % len(pool)], out[0], stream)
-    t1.record(stream)
-    torch.cuda.synchronize()
-    us_single = t0.elapsed_time(t1) * 1000.0 / args.single_calls
-
     # per-kernel durations of the batched call (HIP events on the launch stream, inside the library)
     stage_ms = S.safr_time_stages(plan, F, batches[0], out, S.SAFR_FP32, 20, stream)
-    stage1_ms = S.safr_time_stages(plan1, 1, pool[0], out[0], S.SAFR_FP32, 50, stream)
     names = ["rows", "cols", "out"]
+    if args.calibration_copy:
+        a = torch.empty(64 * 1024 * 1024, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     ab = algorithmic_bytes(desc, geo.n, F)
+    af = algorithmic_flops(desc, F)
     step_kernel_ms = float(sum(stage_ms))
-    achieved = ab["step"] / (step_kernel_ms * 1e-3) / 1e9
+    t_hbm = ab["step"] / (HBM_PEAK_GBS * 1e9)
+    t_alu = af["step"] / (FP32_PEAK_TFLOPS * 1e12)
+    gbs = ab["step"] / (step_kernel_ms * 1e-3) / 1e9
+    tfl = af["step"] / (step_kernel_ms * 1e-3) / 1e12
     traffic = measured_traffic(F)
+    if t_alu >= t_hbm:
+        roof = {"bound": "alu", "achieved": round(tfl, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(tfl / FP32_PEAK_TFLOPS, 4)}
+        other = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    else:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        other = {"bound": "alu", "achieved": round(tfl, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                 "frac": round(tfl / FP32_PEAK_TFLOPS, 4)}
+    dom = int(np.argmax(stage_ms))
+    dk = names[dom]
+    dom_tfl = af["per_kernel"][dk] / (stage_ms[dom] * 1e-3) / 1e12
+    roof.update({"kernel": "rows + cols + out (the three kernels of one batched step)",
+                 "traffic": traffic, "alg_bytes_per_launch": ab["step"], "alg_flops_per_launch": af["step"],
+                 "kernel_ms": round(step_kernel_ms, 6), "other_bound": other,
+                 "dominant_kernel": {"kernel": dk, "ms": round(stage_ms[dom], 6), "bound": "alu",
+                                     "alg_flops": af["per_kernel"][dk], "achieved": round(dom_tfl, 3),
+                                     "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                     "frac": round(dom_tfl / FP32_PEAK_TFLOPS, 4)},
+                 "per_kernel_GBs_with_intermediates": {
+                     k: round(ab["with_intermediates"][k] / (v * 1e-3) / 1e9, 1) for k, v in zip(names, stage_ms)}})
     result = {
         "metric": METRIC,
         "value": round(fps, 1),
@@ -319,18 +374,30 @@ def main():
         "config": {"workload": f"MORFEO-like frames: J=9 (6 LGS + 3 NGS, split tomography), L=9, n=69, "
                                f"M=256, FP32; {F} independent frames per step in one batched call",
                    "frames_per_step": F, "J": geo.J, "L": geo.L, "M": geo.M, "n": geo.n,
-                   "autotuned": {"batched": tuned, "single": tuned1}},
-        "roofline": {"kernel": "rows + cols + out (the three kernels of one step)", "bound": "hbm",
-                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "alg_bytes_per_launch": ab["step"], "kernel_ms": round(step_kernel_ms, 6),
-                     "per_kernel_GBs_with_intermediates": {
-                         k: round(ab["with_intermediates"][k] / (v * 1e-3) / 1e9, 1) for k, v in zip(names, stage_ms)}},
+                   "launch_shapes": {"batched": list(tuned), "single": list(tuned1), "autotuned_now": args.autotune}},
+        "roofline": roof,
         "stage_ms": {k: round(v, 6) for k, v in zip(names, stage_ms)},
         "frame_alg_bytes": algorithmic_bytes(desc, geo.n, 1)["step"],
-        "single_frame": {"us_per_frame": round(us_single, 3), "frames_per_s": round(1e6 / us_single, 1),
-                         "stage_ms": {k: round(v, 6) for k, v in zip(names, stage1_ms)}},
+        "frame_alg_flops": algorithmic_flops(desc, 1)["step"],
     }
+    if args.only_batched:
+        print(json.dumps(result), flush=True)
+        return
+
+    # single-frame calls (the real-time mode): latency per frame
+    for i in range(200):
+        S.safr_reconstruct(plan1, pool[i % len(pool)], out[0], stream)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for i in range(args.single_calls):
+        S.safr_reconstruct(plan1, pool[i % len(pool)], out[0], stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    us_single = t0.elapsed_time(t1) * 1000.0 / args.single_calls
+
+    stage1_ms = S.safr_time_stages(plan1, 1, pool[0], out[0], S.SAFR_FP32, 50, stream)
+    result["single_frame"] = {"us_per_frame": round(us_single, 3), "frames_per_s": round(1e6 / us_single, 1),
+                              "stage_ms": {k: round(v, 6) for k, v in zip(names, stage1_ms)}}
     if not args.no_extras:
         print("bench: 1024-frame batches (C1 geometry)", file=sys.stderr, flush=True)
         result["c3_batched_1024"] = run_c3(S, torch, stream)
