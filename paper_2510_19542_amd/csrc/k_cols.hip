@@ -19,8 +19,8 @@
 // registers and writes b_l(j) into the layer slots (which overlap the star
 // slots only at its own index j), and the inverse transforms run in place in
 // the layer slots.  Phases that overwrite a slot first take what they need into
-// registers, with a barrier in between.  The next iteration's forward inputs
-// are loaded into registers while the current one is transformed.
+// registers, with a barrier in between.  The forward inputs
+// of an iteration are all requested before its first transform.
 //
 // B is stored per block of columns as [l][g][column][j] (thread t owns entries
 // t, t + 256, ...) and is read from global memory at each apply, once for NF
@@ -128,10 +128,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
     };
 
     const float2 twv = tid < M ? a.tw[tid] : make_float2(0.f, 0.f);
-    if constexpr (FIX) {
-#pragma unroll
-        for (int r = 0; r < FR_MAX; ++r) load_fwd(fbeg, r, xf[r]);
-    }
     float2 xh = make_float2(0.f, 0.f), yh = make_float2(0.f, 0.f);
     if (MODE != 0 && kvalid) {
         xh = a.Xh[(size_t)k * M + j];
@@ -141,6 +137,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
     const __amdgpu_buffer_rsrc_t Brs = block_rsrc(a.B + (size_t)kb * L * G * 256, (unsigned)(L * G * 256 * 8));
 
     for (int f0 = fbeg; f0 < fend; f0 += NF) {
+        // this iteration's forward inputs, all requested before the first transform
+        if constexpr (FIX) {
+#pragma unroll
+            for (int r = 0; r < FR_MAX; ++r) load_fwd(f0, r, xf[r]);
+        }
         __syncthreads();                                        // previous inverse transforms done with the slots
         if (MODE != 0 && tid < NF * G) {
             const int fl = tid / G, g = tid - fl * G;
@@ -178,13 +179,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
             __syncthreads();
             if (active) fft_pass2_regs<M, -1>(t, z, [&](int jj, float2 v) { sl[jj] = v; });
         }
-        // the next iteration's forward inputs, in flight during the apply and the inverse transforms
-        if constexpr (FIX) {
-            if (f0 + NF < fend) {
-#pragma unroll
-                for (int r = 0; r < FR_MAX; ++r) load_fwd(f0 + NF, r, xf[r]);
-            }
-        }
         __syncthreads();
 
         // 2. apply: b_l(j) = sum_g B[l][g][j] d_g(j) for the NF frames
@@ -198,11 +192,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
                         const float2 d = slot(c, fl, g)[j];
                         dv[fl][g] = MODE != 0 ? csub(d, plane_value(coef[fl * GC + g], xh, yh)) : d;
                     }
+                // B of layer l + 1 is requested before the products of layer l
+                float2 bv[GC], bn[GC];
+#pragma unroll
+                for (int g = 0; g < GC; ++g) bn[g] = load_b(Brs, tid * 8, g);
 #pragma unroll
                 for (int l = 0; l < LC; ++l) {
-                    float2 bv[GC];
 #pragma unroll
-                    for (int g = 0; g < GC; ++g) bv[g] = load_b(Brs, tid * 8, l * GC + g);
+                    for (int g = 0; g < GC; ++g) bv[g] = bn[g];
+                    if (l + 1 < LC) {
+#pragma unroll
+                        for (int g = 0; g < GC; ++g) bn[g] = load_b(Brs, tid * 8, (l + 1) * GC + g);
+                    }
 #pragma unroll
                     for (int fl = 0; fl < NF; ++fl) {
                         float2 acc = make_float2(0.f, 0.f);
