@@ -137,24 +137,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
     const __amdgpu_buffer_rsrc_t Brs = block_rsrc(a.B + (size_t)kb * L * G * 256, (unsigned)(L * G * 256 * 8));
 
     for (int f0 = fbeg; f0 < fend; f0 += NF) {
-        // this iteration's forward inputs, all requested before the first transform
-        if constexpr (FIX) {
-#pragma unroll
-            for (int r = 0; r < FR_MAX; ++r) load_fwd(f0, r, xf[r]);
-        }
+        // the first round's forward inputs; each later round's are requested after the previous
+        // round's first pass, so at most two rounds of inputs are held at once
+        if constexpr (FIX) load_fwd(f0, 0, xf[0]);
         __syncthreads();                                        // previous inverse transforms done with the slots
+        // tip/tilt plane sums of this iteration's frames: requested now, used after the forward transforms
+        float4 msum = make_float4(0.f, 0.f, 0.f, 0.f);
         if (MODE != 0 && tid < NF * G) {
             const int fl = tid / G, g = tid - fl * G;
             const int f = min(f0 + fl, fend - 1);
-            const float* mo = a.mom + ((size_t)f * a.J + gr.star[g]) * a.nchunk * 4;
-            float m0 = 0.f, m1 = 0.f, m2 = 0.f;
+            const float4* mo = reinterpret_cast<const float4*>(a.mom) + ((size_t)f * a.J + gr.star[g]) * a.nchunk;
             for (int q = 0; q < a.nchunk; ++q) {
-                m0 += mo[4 * q + 0];
-                m1 += mo[4 * q + 1];
-                m2 += mo[4 * q + 2];
+                const float4 v = mo[q];
+                msum.x += v.x;
+                msum.y += v.y;
+                msum.z += v.z;
             }
-            coef[fl * G + g] = make_float2(a.tt_b[0] * m0 + a.tt_b[1] * m1 + a.tt_b[2] * m2,
-                                           a.tt_c[0] * m0 + a.tt_c[1] * m1 + a.tt_c[2] * m2);
         }
         // 1. forward column transforms into the star slots
         const int frounds = FIX ? FR_MAX : (ftasks + NTEAM - 1) / NTEAM;
@@ -173,11 +171,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
                 load_fwd(f0, r, x);
             }
             if (active) fft_pass1_regs<M, -1>(t, sl, tws, x);
+            if constexpr (FIX) {
+                if (r + 1 < FR_MAX) load_fwd(f0, r + 1, xf[r + 1 < FR_MAX ? r + 1 : r]);
+            }
             __syncthreads();
             float2 z[N1 / T][S::N2];
             if (active) fft_pass2_load<M>(t, sl, z);
             __syncthreads();
             if (active) fft_pass2_regs<M, -1>(t, z, [&](int jj, float2 v) { sl[jj] = v; });
+        }
+        if (MODE != 0 && tid < NF * G) {
+            coef[tid] = make_float2(a.tt_b[0] * msum.x + a.tt_b[1] * msum.y + a.tt_b[2] * msum.z,
+                                    a.tt_c[0] * msum.x + a.tt_c[1] * msum.y + a.tt_c[2] * msum.z);
         }
         __syncthreads();
 

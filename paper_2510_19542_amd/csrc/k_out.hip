@@ -132,20 +132,18 @@ __global__ __launch_bounds__(256) void out_kernel(OutArgs a) {
         __syncthreads();                                    // previous epilogue done with the regions
         stash();
         if (f0 + NF < fend) issue(f0 + NF);
-        if constexpr (MIXED) {
-            const int ng = a.nb / 2;
-            if (tid < NF * ng) {
-                const int fi = tid / ng, g = tid - fi * ng;
-                const int f = min(f0 + fi, fend - 1);
-                const float* mo = a.mom + ((size_t)f * a.J + a.ngs_star[g]) * a.nchunk * 4;
-                float m0 = 0.f, m1 = 0.f, m2 = 0.f;
-                for (int c = 0; c < a.nchunk; ++c) {
-                    m0 += mo[4 * c + 0];
-                    m1 += mo[4 * c + 1];
-                    m2 += mo[4 * c + 2];
-                }
-                coef[fi * a.nb + 2 * g] = a.tt_b[0] * m0 + a.tt_b[1] * m1 + a.tt_b[2] * m2;
-                coef[fi * a.nb + 2 * g + 1] = a.tt_c[0] * m0 + a.tt_c[1] * m1 + a.tt_c[2] * m2;
+        // tip/tilt plane sums of the natural stars: requested now, turned into coefficients after the transforms
+        float4 msum = make_float4(0.f, 0.f, 0.f, 0.f);
+        const int ng = a.nb / 2;
+        if (MIXED && tid < NF * ng) {
+            const int fi = tid / ng, g = tid - fi * ng;
+            const int f = min(f0 + fi, fend - 1);
+            const float4* mo = reinterpret_cast<const float4*>(a.mom) + ((size_t)f * a.J + a.ngs_star[g]) * a.nchunk;
+            for (int c = 0; c < a.nchunk; ++c) {
+                const float4 v = mo[c];
+                msum.x += v.x;
+                msum.y += v.y;
+                msum.z += v.z;
             }
         }
         __syncthreads();
@@ -183,6 +181,11 @@ __global__ __launch_bounds__(256) void out_kernel(OutArgs a) {
                 rows[p] = v.x * scale;
                 rows[M + p] = v.y * scale;
             });
+        }
+        if (MIXED && tid < NF * ng) {
+            const int fi = tid / ng, g = tid - fi * ng;
+            coef[fi * a.nb + 2 * g] = a.tt_b[0] * msum.x + a.tt_b[1] * msum.y + a.tt_b[2] * msum.z;
+            coef[fi * a.nb + 2 * g + 1] = a.tt_c[0] * msum.x + a.tt_c[1] * msum.y + a.tt_c[2] * msum.z;
         }
         __syncthreads();
 
