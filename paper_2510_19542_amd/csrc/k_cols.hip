@@ -140,20 +140,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
         // the first round's forward inputs; each later round's are requested after the previous
         // round's first pass, so at most two rounds of inputs are held at once
         if constexpr (FIX) load_fwd(f0, 0, xf[0]);
+        // tip/tilt plane sums of this iteration's frames, requested now and reduced after the forward transforms
+        const PlaneArgs pa{a.mom, a.J, a.nchunk, G, f0, fend, min(NF, fend - f0) * G};
+        auto star_of = [&](int g) { return gr.star[g]; };
+        constexpr int PMAX = 2;
+        float4 part[PMAX];
+        if (MODE != 0) plane_gather<PMAX>(pa, star_of, part);
         __syncthreads();                                        // previous inverse transforms done with the slots
-        // tip/tilt plane sums of this iteration's frames: requested now, used after the forward transforms
-        float4 msum = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (MODE != 0 && tid < NF * G) {
-            const int fl = tid / G, g = tid - fl * G;
-            const int f = min(f0 + fl, fend - 1);
-            const float4* mo = reinterpret_cast<const float4*>(a.mom) + ((size_t)f * a.J + gr.star[g]) * a.nchunk;
-            for (int q = 0; q < a.nchunk; ++q) {
-                const float4 v = mo[q];
-                msum.x += v.x;
-                msum.y += v.y;
-                msum.z += v.z;
-            }
-        }
         // 1. forward column transforms into the star slots
         const int frounds = FIX ? FR_MAX : (ftasks + NTEAM - 1) / NTEAM;
 #pragma unroll
@@ -180,10 +173,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
             __syncthreads();
             if (active) fft_pass2_regs<M, -1>(t, z, [&](int jj, float2 v) { sl[jj] = v; });
         }
-        if (MODE != 0 && tid < NF * G) {
-            coef[tid] = make_float2(a.tt_b[0] * msum.x + a.tt_b[1] * msum.y + a.tt_b[2] * msum.z,
-                                    a.tt_c[0] * msum.x + a.tt_c[1] * msum.y + a.tt_c[2] * msum.z);
-        }
+        // tip/tilt plane coefficients of this iteration's frames (used by the apply, after the barrier)
+        if (MODE != 0) plane_finish<PMAX>(pa, star_of, part, a.tt_b, a.tt_c, coef);
         __syncthreads();
 
         // 2. apply: b_l(j) = sum_g B[l][g][j] d_g(j) for the NF frames

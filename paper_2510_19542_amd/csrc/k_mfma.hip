@@ -98,18 +98,11 @@ __global__ __launch_bounds__(256) void cols_mfma_kernel(MfmaArgs a) {
 
     for (int i = tid; i < M; i += 256) tws[i] = a.tw[i];
     if (mode != 0) {
-        for (int e = tid; e < nf * G; e += 256) {
-            const int f = e / G, g = e % G;
-            const float* mo = a.mom + ((size_t)(fb + f) * a.J + gr.star[g]) * a.nchunk * 4;
-            float m0 = 0.f, m1 = 0.f, m2 = 0.f;
-            for (int c = 0; c < a.nchunk; ++c) {
-                m0 += mo[4 * c + 0];
-                m1 += mo[4 * c + 1];
-                m2 += mo[4 * c + 2];
-            }
-            coef[f * G + g] = make_float2(a.tt_b[0] * m0 + a.tt_b[1] * m1 + a.tt_b[2] * m2,
-                                          a.tt_c[0] * m0 + a.tt_c[1] * m1 + a.tt_c[2] * m2);
-        }
+        const PlaneArgs pa{a.mom, a.J, a.nchunk, G, fb, fb + nf, nf * G};   // nf = valid frames of the block
+        auto star_of = [&](int g) { return gr.star[g]; };
+        float4 part[2];
+        plane_gather<2>(pa, star_of, part);
+        plane_finish<2>(pa, star_of, part, a.tt_b, a.tt_c, coef);
     }
     __syncthreads();
 

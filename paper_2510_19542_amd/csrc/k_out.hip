@@ -128,24 +128,16 @@ __global__ __launch_bounds__(256) void out_kernel(OutArgs a) {
     if (tid < M) tws[tid] = twv;
     const float scale = 1.0f / ((float)M * (float)M);
 
+    auto star_of = [&](int g) { return a.ngs_star[g]; };
+    constexpr int PMAX = 1;                                 // rounds of natural-star plane sums held in registers
     for (int f0 = fbeg; f0 < fend; f0 += NF) {
         __syncthreads();                                    // previous epilogue done with the regions
         stash();
         if (f0 + NF < fend) issue(f0 + NF);
-        // tip/tilt plane sums of the natural stars: requested now, turned into coefficients after the transforms
-        float4 msum = make_float4(0.f, 0.f, 0.f, 0.f);
-        const int ng = a.nb / 2;
-        if (MIXED && tid < NF * ng) {
-            const int fi = tid / ng, g = tid - fi * ng;
-            const int f = min(f0 + fi, fend - 1);
-            const float4* mo = reinterpret_cast<const float4*>(a.mom) + ((size_t)f * a.J + a.ngs_star[g]) * a.nchunk;
-            for (int c = 0; c < a.nchunk; ++c) {
-                const float4 v = mo[c];
-                msum.x += v.x;
-                msum.y += v.y;
-                msum.z += v.z;
-            }
-        }
+        // natural stars' plane sums of this iteration's frames: requested now, reduced before the epilogue
+        const PlaneArgs pa{a.mom, a.J, a.nchunk, a.nb / 2, f0, fend, min(NF, fend - f0) * (a.nb / 2)};
+        float4 part[PMAX];
+        if constexpr (MIXED) plane_gather<PMAX>(pa, star_of, part);
         __syncthreads();
 
         // packed C2R: Z[q] = A[q] + i B[q] over the Hermitian extensions of the team's two rows
@@ -182,11 +174,8 @@ __global__ __launch_bounds__(256) void out_kernel(OutArgs a) {
                 rows[M + p] = v.y * scale;
             });
         }
-        if (MIXED && tid < NF * ng) {
-            const int fi = tid / ng, g = tid - fi * ng;
-            coef[fi * a.nb + 2 * g] = a.tt_b[0] * msum.x + a.tt_b[1] * msum.y + a.tt_b[2] * msum.z;
-            coef[fi * a.nb + 2 * g + 1] = a.tt_c[0] * msum.x + a.tt_c[1] * msum.y + a.tt_c[2] * msum.z;
-        }
+        // natural stars' plane coefficients (b_g, c_g) of this iteration's frames, [NF][ng] as float2
+        if constexpr (MIXED) plane_finish<PMAX>(pa, star_of, part, a.tt_b, a.tt_c, reinterpret_cast<float2*>(coef));
         __syncthreads();
 
         // epilogue: 4-pixel groups, coalesced stores

@@ -102,6 +102,77 @@ struct BasisArgs {
     float* P;                   // [L][2 G][M][M]
 };
 
+// Tip/tilt plane coefficients of `count` (frame, star) pairs from the row pass's partial moments
+// mom[f][star][chunk] = (sum v, sum x v, sum y v, 0); pair i = (frame f0 + i / per, star
+// star_of(i % per)); frames at or beyond fend use fend - 1.  A wavefront sums 64 / seg pairs at a
+// time, seg = 1 for at most 8 chunks, else the smallest power of two >= min(nchunk, 64): lane l
+// takes chunks l % seg,
+// l % seg + seg, ... of pair (round * waves + wave) * (64 / seg) + l / seg.  plane_gather requests
+// the first PMAX rounds into registers (early), plane_finish reduces each segment with a fixed
+// shuffle tree (deterministic order), does any further rounds, and the segment's first lane writes
+// (b, c) = rows 1 and 2 of the inverse normal matrix times the sums to out[i].  Every thread of the
+// block calls both with the same arguments.
+struct PlaneArgs {
+    const float* mom;
+    int J, nchunk, per, f0, fend, count;
+};
+
+__device__ inline int plane_seg(int nchunk) {
+    if (nchunk <= 8) return 1;                  // few chunks: one lane per pair, no shuffles
+    int seg = 1;
+    while (seg < nchunk && seg < 64) seg <<= 1;
+    return seg;
+}
+
+template <class StarOf>
+__device__ inline float4 plane_lane(const PlaneArgs& p, StarOf star_of, int round, int seg) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, waves = (blockDim.x + 63) >> 6;
+    const int i = (round * waves + wave) * (64 / seg) + lane / seg;
+    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (i < p.count) {
+        const int f = min(p.f0 + i / p.per, p.fend - 1), g = star_of(i % p.per);
+        const float4* mo = reinterpret_cast<const float4*>(p.mom) + ((size_t)f * p.J + g) * p.nchunk;
+        for (int q = lane % seg; q < p.nchunk; q += seg) {
+            const float4 v = mo[q];
+            s.x += v.x;
+            s.y += v.y;
+            s.z += v.z;
+        }
+    }
+    return s;
+}
+
+__device__ inline void plane_write(const PlaneArgs& p, float4 s, int round, int seg, const float* tt_b,
+                                   const float* tt_c, float2* out) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, waves = (blockDim.x + 63) >> 6;
+    for (int o = seg >> 1; o > 0; o >>= 1) {
+        s.x += __shfl_xor(s.x, o, 64);
+        s.y += __shfl_xor(s.y, o, 64);
+        s.z += __shfl_xor(s.z, o, 64);
+    }
+    const int i = (round * waves + wave) * (64 / seg) + lane / seg;
+    if (lane % seg == 0 && i < p.count)
+        out[i] = make_float2(tt_b[0] * s.x + tt_b[1] * s.y + tt_b[2] * s.z, tt_c[0] * s.x + tt_c[1] * s.y + tt_c[2] * s.z);
+}
+
+template <int PMAX, class StarOf>
+__device__ inline void plane_gather(const PlaneArgs& p, StarOf star_of, float4 (&part)[PMAX]) {
+    const int seg = plane_seg(p.nchunk);
+#pragma unroll
+    for (int u = 0; u < PMAX; ++u) part[u] = plane_lane(p, star_of, u, seg);
+}
+
+template <int PMAX, class StarOf>
+__device__ inline void plane_finish(const PlaneArgs& p, StarOf star_of, float4 (&part)[PMAX], const float* tt_b,
+                                    const float* tt_c, float2* out) {
+    const int seg = plane_seg(p.nchunk), waves = (blockDim.x + 63) >> 6;
+    const int rounds = (p.count + waves * (64 / seg) - 1) / (waves * (64 / seg));
+#pragma unroll
+    for (int u = 0; u < PMAX; ++u)
+        if (u < rounds) plane_write(p, part[u], u, seg, tt_b, tt_c, out);
+    for (int u = PMAX; u < rounds; ++u) plane_write(p, plane_lane(p, star_of, u, seg), u, seg, tt_b, tt_c, out);
+}
+
 // Lets a kernel use up to the full 160 KiB of LDS of a gfx950 compute unit (once per kernel).
 inline void allow_large_lds(const void* kernel) {
     static thread_local const void* done[64];
