@@ -15,8 +15,10 @@
 // and a barrier separates them from the stores that overwrite the region.  The
 // next iteration's spectra are loaded into registers while the current one is
 // transformed.  The epilogue is pixel-stationary (thread -> 4-pixel groups of
-// the block's rows), so the basis images of those pixels stay in registers for
-// all frames of the block.
+// the block's rows): a group's basis pixels are read once per iteration (from
+// L2: the blocks of one row tile are XCD-contiguous) and serve its NF frames.
+// The kernel targets three wavefronts per SIMD; holding the basis pixels in
+// registers for the whole block instead costs a third of the occupancy.
 //
 // C layout (row tiles of 8): C[f][l][p / 8][k][p % 8]; a block's rows of one
 // frame are one contiguous run.
@@ -56,7 +58,7 @@ struct OutShape {
 
 // NB: natural-star basis images held in registers (0: none; a.nb <= NB, the rest are re-read)
 template <int M, int RT, int NB>
-__global__ __launch_bounds__(256) void out_kernel(OutArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void out_kernel(OutArgs a) {
     constexpr bool MIXED = NB > 0;
     using S = FftShape<M>;
     using O = OutShape<M, RT>;
@@ -108,20 +110,6 @@ __global__ __launch_bounds__(256) void out_kernel(OutArgs a) {
             dst[Kh + k] = make_float2(ld[i].z, ld[i].w);
         }
     };
-
-    // natural-star basis images of this thread's pixels
-    float4 pb4[MIXED ? O::V4 : 1][MIXED ? NB : 1];
-    if constexpr (MIXED) {
-#pragma unroll
-        for (int v = 0; v < O::V4; ++v) {
-            const int e = 4 * (tid + 256 * v);
-            const int r = e / M, q = e % M;
-#pragma unroll
-            for (int i = 0; i < NB; ++i)
-                if (i < a.nb)
-                    pb4[v][i] = *reinterpret_cast<const float4*>(a.P + (((size_t)l * a.nb + i) * M + r0 + r) * M + q);
-        }
-    }
 
     const float2 twv = tid < M ? a.tw[tid] : make_float2(0.f, 0.f);
     issue(fbeg);
@@ -178,15 +166,28 @@ __global__ __launch_bounds__(256) void out_kernel(OutArgs a) {
         if constexpr (MIXED) plane_finish<PMAX>(pa, star_of, part, a.tt_b, a.tt_c, reinterpret_cast<float2*>(coef));
         __syncthreads();
 
-        // epilogue: 4-pixel groups, coalesced stores
+        // epilogue: 4-pixel groups, coalesced stores; a group's basis pixels are read (from L2) once per
+        // iteration and serve its NF frames
+#pragma unroll 1
+        for (int v = 0; v < O::V4; ++v) {
+            const int e = 4 * (tid + 256 * v);
+            const int r = e / M, q = e % M;
+            float4 pv[MIXED ? NB : 1];
+            if constexpr (MIXED) {
+                // an opaque zero keeps these loop-invariant loads inside the frame loop (hoisted, they would
+                // hold 4 NB registers through the transforms and halve the occupancy)
+                int zero;
+                asm volatile("s_mov_b32 %0, 0" : "=s"(zero));
+                const float* Pb = a.P + zero;
 #pragma unroll
-        for (int fi = 0; fi < NF; ++fi) {
-            const int f = f0 + fi;
-            if (f >= fend) break;
+                for (int i = 0; i < NB; ++i)
+                    if (i < a.nb)
+                        pv[i] = *reinterpret_cast<const float4*>(Pb + (((size_t)l * a.nb + i) * M + r0 + r) * M + q);
+            }
 #pragma unroll
-            for (int v = 0; v < O::V4; ++v) {
-                const int e = 4 * (tid + 256 * v);
-                const int r = e / M, q = e % M;
+            for (int fi = 0; fi < NF; ++fi) {
+                const int f = f0 + fi;
+                if (f >= fend) break;
                 const float* src = reinterpret_cast<const float*>(smem + M + (fi * TPF + r / 2) * RS) + (r & 1) * M + q;
                 float4 o = *reinterpret_cast<const float4*>(src);
                 if constexpr (MIXED) {
@@ -195,20 +196,20 @@ __global__ __launch_bounds__(256) void out_kernel(OutArgs a) {
                     for (int i = 0; i < NB; ++i) {
                         if (i < a.nb) {
                             const float c = cf[i];
-                            o.x += c * pb4[v][i].x;
-                            o.y += c * pb4[v][i].y;
-                            o.z += c * pb4[v][i].z;
-                            o.w += c * pb4[v][i].w;
+                            o.x += c * pv[i].x;
+                            o.y += c * pv[i].y;
+                            o.z += c * pv[i].z;
+                            o.w += c * pv[i].w;
                         }
                     }
                     for (int i = NB; i < a.nb; ++i) {
                         const float c = cf[i];
-                        const float4 pv =
+                        const float4 pw =
                             *reinterpret_cast<const float4*>(a.P + (((size_t)l * a.nb + i) * M + r0 + r) * M + q);
-                        o.x += c * pv.x;
-                        o.y += c * pv.y;
-                        o.z += c * pv.z;
-                        o.w += c * pv.w;
+                        o.x += c * pw.x;
+                        o.y += c * pw.y;
+                        o.z += c * pw.z;
+                        o.w += c * pw.w;
                     }
                 }
                 *reinterpret_cast<float4*>(a.out + (((size_t)f * L + l) * M + r0 + r) * M + q) = o;
