@@ -384,6 +384,38 @@ def test_mixed_asterism_is_sum_of_groups():
     assert np.max(np.abs(O.reconstruct(mixed, wf) - expect)) <= 1e-12
 
 
+def test_natural_star_layers_are_linear_in_the_plane_coefficients():
+    """Sec. 3.3 with keepTT: the natural stars see only b_g x + c_g y over the pupil, and Alg. 1 and the
+    resampling are linear, so the natural-star part of a mixed reconstruction equals
+    sum_g b_g P[2g] + c_g P[2g+1] with P the (resampled) reconstructions of the unit planes x * mask,
+    y * mask of one star at a time (the identity the GPU path's precomputed basis images rest on)."""
+    M, n = 16, 9
+    lgs = _stars(3, kind=O.LGS)
+    ngs = _stars(2, kind=O.NGS)
+    plan = O.precompute(n=n, M=M, pitch=1.0, stars=lgs + ngs, h_lgs=20e3, heights=[0.0, 4000.0, 9000.0],
+                        weights=[0.5, 0.3, 0.2], alpha=5e-3, alpha_tt=1e-3, beta=1.5)
+    pup = np.ones((n, n), dtype=np.uint8)
+    pup[0, 0] = pup[-1, -1] = 0
+    plan.pupil = pup.astype(bool)
+    lg, ng = plan.groups
+    wf = RNG.standard_normal((5, n, n))
+    laser = O.reconstruct_group(lg.B, O.zero_extend(np.stack([O.prepare(w, pup, 1) for w in wf[:3]]), M))
+    natural = O.reconstruct(plan, wf) - laser
+    x = np.arange(n) - (n - 1) / 2.0
+    X, Y = np.meshgrid(x, x, indexing="ij")
+    m = pup.astype(bool)
+    basis = np.stack([X[m], Y[m], np.ones(m.sum())], axis=1)
+    expect = np.zeros_like(natural)
+    for g in range(2):
+        coef, *_ = np.linalg.lstsq(basis, wf[3 + g][m], rcond=None)
+        for a, img in ((coef[0], X), (coef[1], Y)):
+            unit = np.zeros((2, n, n))
+            unit[g] = np.where(m, img, 0.0)
+            P = O.resample_onto_cone_grid(O.reconstruct_group(ng.B, O.zero_extend(unit, M)), lg.c)
+            expect += a * P
+    assert np.max(np.abs(natural - expect)) <= 1e-12 * np.max(np.abs(natural))
+
+
 def test_zero_extension_centres_pupil():
     M, n = 16, 5
     psi = np.arange(n * n, dtype=float).reshape(n, n)
