@@ -1,6 +1,6 @@
 """BF16 matrix-core apply with the split correction (batched path) against the FP64 oracle.
 
-Bound: relative L2 <= 1e-4 per frame (the benchmark spec's BF16 tolerance).  The
+Bound: relative L2 <= 1e-4 per frame (the BF16 tolerance of the batched path).  The
 split hi/lo products leave ~2^-16 relative error per product; the FP32 path on
 the same frames is also checked, and the two GPU paths must differ by no more
 than the BF16 bound.
