@@ -34,7 +34,10 @@ the design notes):
   1, x, y over the pupil pixels) subtracted; natural-star data is reduced to that
   plane; the natural-star layers (spacing = pitch) are resampled bilinearly
   (periodically) at the points of the laser-star layer grids (spacing c_l * pitch)
-  and added.
+  and added;
+* Alg. 3 (closed loop): the mirror commands are the reconstructed layers on their
+  output grids; POLC adds A(a) with A evaluated by periodic bilinear interpolation
+  along each star's line of sight, at the pupil pixels only.
 """
 from __future__ import annotations
 
@@ -272,6 +275,14 @@ class Plan:
     pupil: np.ndarray
     groups: List[Group]
     mixed: bool
+    stars: Optional[np.ndarray] = None      # (J, 3): alpha_x, alpha_y [rad], kind
+    heights: Optional[np.ndarray] = None    # (L,) layer heights [m]
+    h_lgs: float = 0.0
+
+    @property
+    def c_out(self) -> np.ndarray:
+        """Cone coefficients of the output layer grids: those of the first group (laser stars when mixed)."""
+        return self.groups[0].c
 
 
 def split_groups(kinds, alpha: float, alpha_tt: float):
@@ -331,7 +342,8 @@ def precompute(*, n: int, M: int, pitch: float, stars, h_lgs: float, heights, we
     if pupil is None:
         pupil = np.ones((n, n), dtype=np.uint8)
     return Plan(n=n, M=M, pitch=pitch, T=T, L=L, gamma=gamma,
-                pupil=np.asarray(pupil).astype(bool), groups=groups, mixed=mixed)
+                pupil=np.asarray(pupil).astype(bool), groups=groups, mixed=mixed,
+                stars=stars, heights=heights, h_lgs=float(h_lgs))
 
 
 def precompute_geometry(geo, **kw) -> Plan:
@@ -576,3 +588,83 @@ def forward_bilinear(layers: np.ndarray, shifts: np.ndarray) -> np.ndarray:
             rows = (1 - fu)[:, None] * X[a0, :] + fu[:, None] * X[a1, :]
             out[g] += (1 - fv)[None, :] * rows[:, b0] + fv[None, :] * rows[:, b1]
     return out
+
+
+# --------------------------------------------------------------------------------------
+# Alg. 3: three-step closed loop (the wavefront-reconstruction step excluded)
+# --------------------------------------------------------------------------------------
+
+def bilinear_periodic(X: np.ndarray, u: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """X sampled at fractional indices (u, v) by bilinear interpolation on the periodic grid."""
+    M0, M1 = X.shape
+    i0 = np.floor(u).astype(np.int64)
+    j0 = np.floor(v).astype(np.int64)
+    fu = u - i0
+    fv = v - j0
+    a0, a1 = i0 % M0, (i0 + 1) % M0
+    b0, b1 = j0 % M1, (j0 + 1) % M1
+    return ((1 - fu) * (1 - fv) * X[a0, b0] + fu * (1 - fv) * X[a1, b0]
+            + (1 - fu) * fv * X[a0, b1] + fu * fv * X[a1, b1])
+
+
+def line_of_sight_points(plan: Plan, directions=None, cones=None):
+    """Fractional indices (u, v) on each output layer grid seen from every pupil pixel.
+
+    Pupil pixel (i, j) sits at grid point p = p0 + i, q = p0 + j, i.e. at
+    r = ((p - M/2) pitch, (q - M/2) pitch).  A source in direction theta with cone
+    coefficient c^s_l (Sec. 2: 1 for a natural star, 1 - h_l / h_LGS for a laser star)
+    crosses layer l at c^s_l r + theta h_l, which on the layer's output grid (spacing
+    c_l pitch, centred at index M/2) is the index (c^s_l r + theta h_l) / (c_l pitch) + M/2.
+    ``directions`` (D, 2) and ``cones`` (D, L) default to the plan's guide stars.
+    Returns u, v of shape (D, L, n, n).
+    """
+    M, n, pitch = plan.M, plan.n, plan.pitch
+    if directions is None:
+        st = np.asarray(plan.stars, dtype=np.float64).reshape(-1, 3)
+        directions = st[:, :2]
+        cones = np.stack([cone_coefficients(plan.heights, int(k), plan.h_lgs) for k in st[:, 2]])
+    directions = np.asarray(directions, dtype=np.float64).reshape(-1, 2)
+    cones = np.asarray(cones, dtype=np.float64).reshape(len(directions), -1)
+    p0 = pupil_offset(M, n)
+    r = (p0 + np.arange(n) - M / 2.0) * pitch
+    X, Y = np.meshgrid(r, r, indexing="ij")
+    h = np.asarray(plan.heights, dtype=np.float64)
+    co = plan.c_out
+    D, L = len(directions), len(h)
+    u = np.empty((D, L, n, n))
+    v = np.empty((D, L, n, n))
+    for d in range(D):
+        for l in range(L):
+            u[d, l] = (cones[d, l] * X + directions[d, 0] * h[l]) / (co[l] * pitch) + M / 2.0
+            v[d, l] = (cones[d, l] * Y + directions[d, 1] * h[l]) / (co[l] * pitch) + M / 2.0
+    return u, v
+
+
+def forward_layers(plan: Plan, layers: np.ndarray, directions=None, cones=None) -> np.ndarray:
+    """(A a)_g on the pupil: sum over layers of a_l at the line-of-sight points, zero outside the pupil.
+
+    layers (L, M, M) on the output grids -> (D, n, n); D = J guide stars by default.
+    """
+    u, v = line_of_sight_points(plan, directions, cones)
+    out = np.zeros(u.shape[:1] + u.shape[2:])
+    for d in range(u.shape[0]):
+        for l in range(u.shape[1]):
+            out[d] += bilinear_periodic(np.asarray(layers[l], dtype=np.float64), u[d, l], v[d, l])
+    return np.where(plan.pupil[None], out, 0.0)
+
+
+def polc(plan: Plan, wavefronts: np.ndarray, layers: np.ndarray, weight: float = 1.0) -> np.ndarray:
+    """Pseudo-open-loop data Psi + weight * A(a) on the pupil pixels, zero outside (Alg. 3, POLC step)."""
+    wf = np.where(plan.pupil[None], np.asarray(wavefronts, dtype=np.float64), 0.0)
+    return wf + weight * forward_layers(plan, layers)
+
+
+def loop_step(plan: Plan, wavefronts: np.ndarray, a: np.ndarray, gain: float) -> np.ndarray:
+    """One time step of Alg. 3 from given closed-loop wavefronts.
+
+    POLC, tip/tilt removal of the laser stars and the two SAFR reconstructions
+    (both inside ``reconstruct``), then the integrator
+    a_next = (1 - gain) a + gain Phi.
+    """
+    phi = reconstruct(plan, polc(plan, wavefronts, a))
+    return (1.0 - gain) * np.asarray(a, dtype=np.float64) + gain * phi
