@@ -193,6 +193,39 @@ safr_status safr_time_stages(safr_plan* p, int frames, const float* wavefronts, 
 safr_status safr_autotune(safr_plan* p, int frames, const float* wavefronts, float* layers, int precision,
                           int iters, hipStream_t stream, int* choice);
 
+/* ---- Closed loop (Alg. 3 without its wavefront-reconstruction step) -------------------------
+ * The mirror commands are layers [L][M][M] on the plan's output grids: the layers are placed at
+ * the conjugation heights, so no fitting step is needed (Sec. 3.3, Alg. 3).  The tomography
+ * operator A of Sec. 2 maps them to each guide star's pupil: (A a)_g at pupil pixel (i, j) is the
+ * sum over layers of a_l sampled, by periodic bilinear interpolation, where star g's line of sight
+ * through that pixel crosses layer l.  The pixel sits at r = (p0 + i - M/2, p0 + j - M/2) pitch
+ * with p0 = (M - n + 1) / 2; the crossing point is c^s_l r + theta_g h_l (c^s_l = 1 - h_l / h_lgs
+ * for laser stars, 1 for natural stars), which on layer l's output grid (spacing c_l pitch,
+ * centred at index M/2) is the index (c^s_l r + theta_g h_l) / (c_l pitch) + M/2.  Sample
+ * positions are evaluated in FP32, values in FP32.
+ */
+
+/* POLC (Alg. 3, pseudo-open-loop data) of `frames` frames (1..65535):
+ * out[f][g] = pupil .* (wavefronts[f][g] + weight (A layers[f])_g), zero outside the pupil.
+ * wavefronts and out [frames][J][n][n], layers [frames][L][M][M], FP32 device memory.  out may
+ * be wavefronts (in place); layers must not overlap out.  weight = -1 turns open-loop wavefronts
+ * into the residuals a mirror with these commands leaves.  Asynchronous on `stream`.
+ * Errors: SAFR_ERR_ARG (NULL, frame count, non-finite weight), SAFR_ERR_DEVICE. */
+safr_status safr_polc(safr_plan* p, int frames, const float* wavefronts, const float* layers, float weight,
+                      float* out, hipStream_t stream);
+
+/* One time step of Alg. 3 for `frames` independent loops (1..65535), from given closed-loop
+ * wavefronts [frames][J][n][n] and the current commands a_in [frames][L][M][M]: POLC
+ * (Psi + A a_in), tip/tilt removal of the laser stars and the SAFR reconstruction(s) exactly as
+ * safr_reconstruct_batched in FP32, then the integrator a_out = (1 - gain) a_in + gain Phi, fused
+ * into the output pass.  a_out may be a_in (in place); neither may overlap wavefronts.  The POLC
+ * data lives in the workspace (safr_workspace_size covers it).  With SAFR_OPT_GRAPH the sequence
+ * is captured per (frames, pointers, gain, stream) and replayed.  Asynchronous on `stream`.
+ * Errors: SAFR_ERR_ARG (NULL, frame count, non-finite gain), SAFR_ERR_STATE (workspace too small),
+ * SAFR_ERR_DEVICE. */
+safr_status safr_loop_step(safr_plan* p, int frames, const float* wavefronts, const float* a_in, float gain,
+                           float* a_out, hipStream_t stream);
+
 /* ---- Mixed-size batches -------------------------------------------------------------------
  * A bundle of plans (different geometries and grid sizes), each with its own frame count.
  * safr_multi_execute reconstructs every entry's frames (wavefronts[i]: [frames[i]][J][n][n],

@@ -5,7 +5,9 @@
 //   - mixed asterisms: the natural-star layers, sum_g b_g P[l][2g] + c_g P[l][2g+1]
 //     with the frame's tip/tilt plane coefficients (b_g, c_g) from the row-pass
 //     moments and the precomputed basis images P (already resampled onto the
-//     laser layer grids), added to every output pixel.
+//     laser layer grids), added to every output pixel;
+//   - closed loop (Alg. 3): optionally the integrator, out = (1 - gain) prev + gain
+//     layer, with prev read at the pixel just before it is written (prev may be out).
 //
 // One block of 256 threads owns RT rows of one layer and loops over a run of
 // frames, NF frames per iteration so that every team of the block transforms
@@ -212,7 +214,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void o
                         o.w += c * pw.w;
                     }
                 }
-                *reinterpret_cast<float4*>(a.out + (((size_t)f * L + l) * M + r0 + r) * M + q) = o;
+                const size_t oi = (((size_t)f * L + l) * M + r0 + r) * M + q;
+                if (a.prev) {                   // integrator of the closed loop (Alg. 3)
+                    const float4 pr = *reinterpret_cast<const float4*>(a.prev + oi);
+                    const float keep = 1.f - a.gain;
+                    o.x = fmaf(a.gain, o.x, keep * pr.x);
+                    o.y = fmaf(a.gain, o.y, keep * pr.y);
+                    o.z = fmaf(a.gain, o.z, keep * pr.z);
+                    o.w = fmaf(a.gain, o.w, keep * pr.w);
+                }
+                *reinterpret_cast<float4*>(a.out + oi) = o;
             }
         }
     }

@@ -1,0 +1,52 @@
+// Pseudo-open-loop data for the closed loop (Alg. 3, POLC step).
+//
+// The mirror commands are layers on the output grids.  For every pupil pixel of
+// every guide star the kernel adds, over the layers, the command sampled by
+// periodic bilinear interpolation at the point where the star's line of sight
+// crosses the layer (the layered tomography operator of Sec. 2), scaled by a
+// weight, to the measured wavefront; pixels outside the pupil are written as 0.
+// One thread per pupil pixel; the layers (a few MB) are read through L2.
+#include "safr_internal.h"
+
+namespace safr {
+
+__global__ void __launch_bounds__(256) polc_kernel(PolcArgs a) {
+    const int n = a.n, M = a.M, L = a.L;
+    const int g = blockIdx.y, f = blockIdx.z;
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= n * n) return;
+    const size_t o = ((size_t)f * a.J + g) * (size_t)n * n + e;
+    float v = 0.f;
+    if (a.pupil[e]) {
+        const int i = e / n, j = e - (e / n) * n;
+        const int mask = M - 1;                          // M is a power of two: the periodic wrap
+        const float* lay = a.layers + (size_t)f * L * M * M;
+        const float4* tab = a.tab + (size_t)g * L;
+        float acc = 0.f;
+#pragma unroll 3
+        for (int l = 0; l < L; ++l) {
+            const float4 t = tab[l];
+            const float u = fmaf(t.x, (float)i, t.y);
+            const float w = fmaf(t.x, (float)j, t.z);
+            const float fu0 = floorf(u), fw0 = floorf(w);
+            const float fu = u - fu0, fw = w - fw0;
+            const int i0 = (int)fu0 & mask, j0 = (int)fw0 & mask;
+            const int i1 = (i0 + 1) & mask, j1 = (j0 + 1) & mask;
+            const float* X = lay + (size_t)l * M * M;
+            const float x00 = X[i0 * M + j0], x01 = X[i0 * M + j1];
+            const float x10 = X[i1 * M + j0], x11 = X[i1 * M + j1];
+            acc += (1.f - fu) * ((1.f - fw) * x00 + fw * x01) + fu * ((1.f - fw) * x10 + fw * x11);
+        }
+        v = fmaf(a.weight, acc, a.wf[o]);
+    }
+    a.out[o] = v;
+}
+
+hipError_t launch_polc(const PolcArgs& a, int frames, hipStream_t s) {
+    if (a.M < 2 || (a.M & (a.M - 1)) || a.n < 1 || a.n > a.M || frames < 1 || frames > 65535) return hipErrorInvalidValue;
+    const int blocks = (a.n * a.n + 255) / 256;
+    hipLaunchKernelGGL(polc_kernel, dim3(blocks, a.J, frames), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace safr

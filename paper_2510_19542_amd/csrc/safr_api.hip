@@ -79,6 +79,7 @@ struct safr_plan {
     int nb = 0;
     unsigned char* pupil = nullptr;
     int* tt_mode = nullptr;
+    float4* polc_tab = nullptr;     // [J][L] line-of-sight sampling of the output grids (closed loop)
     void* ws_own = nullptr;
     size_t ws_own_bytes = 0;
     void* ws_user = nullptr;
@@ -93,6 +94,15 @@ struct safr_plan {
     const float* g_wf = nullptr;
     float* g_out = nullptr;
     hipStream_t g_stream = nullptr;
+    // graph cache of the closed-loop step
+    hipGraphExec_t lexec = nullptr;
+    hipGraph_t lgraph = nullptr;
+    int l_frames = 0;
+    float l_gain = 0.f;
+    const float* l_wf = nullptr;
+    const float* l_ain = nullptr;
+    float* l_aout = nullptr;
+    hipStream_t l_stream = nullptr;
 };
 
 namespace {
@@ -105,12 +115,27 @@ size_t ws_c(const safr_plan* p, int frames) {
 size_t ws_m(const safr_plan* p, int frames) {
     return align256((size_t)frames * p->J * ((p->n + 1) / 2) * 4 * sizeof(float));
 }
-size_t ws_bytes(const safr_plan* p, int frames) { return ws_r(p, frames) + ws_c(p, frames) + ws_m(p, frames); }
+// pseudo-open-loop wavefronts of the closed-loop step
+size_t ws_w(const safr_plan* p, int frames) { return align256((size_t)frames * p->J * p->n * p->n * sizeof(float)); }
+size_t ws_bytes(const safr_plan* p, int frames) {
+    return ws_r(p, frames) + ws_c(p, frames) + ws_m(p, frames) + ws_w(p, frames);
+}
+
+// captured graphs hold launch shapes and pointers: dropped whenever a tuning option changes
+void drop_graphs(safr_plan* p) {
+    if (p->gexec) hipGraphExecDestroy(p->gexec);
+    if (p->graph) hipGraphDestroy(p->graph);
+    if (p->lexec) hipGraphExecDestroy(p->lexec);
+    if (p->lgraph) hipGraphDestroy(p->lgraph);
+    p->gexec = nullptr;
+    p->graph = nullptr;
+    p->lexec = nullptr;
+    p->lgraph = nullptr;
+}
 
 void free_plan(safr_plan* p) {
     if (!p) return;
-    if (p->gexec) hipGraphExecDestroy(p->gexec);
-    if (p->graph) hipGraphDestroy(p->graph);
+    drop_graphs(p);
     hipFree(p->B64);
     hipFree(p->B32);
     hipFree(p->Apack);
@@ -120,6 +145,7 @@ void free_plan(safr_plan* p) {
     hipFree(p->P);
     hipFree(p->pupil);
     hipFree(p->tt_mode);
+    hipFree(p->polc_tab);
     hipFree(p->ws_own);
     delete p;
 }
@@ -198,7 +224,33 @@ void tt_transforms(const std::vector<unsigned char>& pup, int n, int M, int p0, 
 }
 
 safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, int precision,
-                       void* ws, hipStream_t s, hipEvent_t* ev = nullptr);
+                       void* ws, hipStream_t s, hipEvent_t* ev = nullptr, const float* prev = nullptr,
+                       float gain = 1.f);
+
+PolcArgs polc_args(const safr_plan* p, const float* wf, const float* layers, float weight, float* out) {
+    PolcArgs a{};
+    a.wf = wf;
+    a.layers = layers;
+    a.out = out;
+    a.pupil = p->pupil;
+    a.tab = p->polc_tab;
+    a.weight = weight;
+    a.n = p->n;
+    a.M = p->M;
+    a.J = p->J;
+    a.L = p->L;
+    return a;
+}
+
+// Alg. 3 without its wavefront reconstruction: POLC into the workspace, the reconstruction with
+// the integrator fused into the output pass
+safr_status launch_loop(safr_plan* p, int frames, const float* wf, const float* a_in, float gain, float* a_out,
+                        void* ws, hipStream_t s) {
+    float* psi = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + ws_r(p, frames) + ws_c(p, frames) +
+                                          ws_m(p, frames));
+    HIP_TRY(launch_polc(polc_args(p, wf, a_in, 1.f, psi), frames, s));
+    return launch_all(p, frames, psi, a_out, SAFR_FP32, ws, s, nullptr, a_in, gain);
+}
 
 }  // namespace
 
@@ -386,6 +438,24 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
         PC_TRY(hipMemcpy(p->pupil, pup.data(), pup.size(), hipMemcpyHostToDevice));
         PC_TRY(hipMalloc(&p->tt_mode, J * sizeof(int)));
         PC_TRY(hipMemcpy(p->tt_mode, mode.data(), J * sizeof(int), hipMemcpyHostToDevice));
+        {
+            // closed loop: star g's line of sight through pupil pixel (i, j) crosses output layer l at
+            // c^s_l r + theta_g h_l, r = (p0 + i - M/2, p0 + j - M/2) pitch; on the layer grid (spacing
+            // c_l pitch, centred at M/2) that is (u0 + m i, v0 + m j) with m = c^s_l / c_l
+            std::vector<float4> tab((size_t)J * L);
+            for (int g = 0; g < J; ++g)
+                for (int l = 0; l < L; ++l) {
+                    const safr_star& st = geo->stars[g];
+                    const double cs = st.kind == SAFR_LGS ? 1.0 - heights[l] / geo->h_lgs : 1.0;
+                    const double co = p->c_out[l];
+                    const double m = cs / co, base = m * (p->p0 - 0.5 * M) + 0.5 * M;
+                    const double sx = st.ax * heights[l] / (co * geo->pitch);
+                    const double sy = st.ay * heights[l] / (co * geo->pitch);
+                    tab[(size_t)g * L + l] = make_float4((float)m, (float)(base + sx), (float)(base + sy), 0.f);
+                }
+            PC_TRY(hipMalloc(&p->polc_tab, tab.size() * sizeof(float4)));
+            PC_TRY(hipMemcpy(p->polc_tab, tab.data(), tab.size() * sizeof(float4), hipMemcpyHostToDevice));
+        }
         PC_TRY(hipMalloc(&dbad, sizeof(int)));
         PC_TRY(hipMemsetAsync(dbad, 0, sizeof(int), stream));
         const int H = p->Kh * M;
@@ -618,6 +688,58 @@ safr_status safr_reconstruct(safr_plan* p, const float* wf, float* out, hipStrea
     return safr_reconstruct_batched(p, 1, wf, out, SAFR_FP32, s);
 }
 
+safr_status safr_polc(safr_plan* p, int frames, const float* wf, const float* layers, float weight, float* out,
+                      hipStream_t s) {
+    if (!p || !wf || !layers || !out) return fail(SAFR_ERR_ARG, "NULL argument");
+    if (frames < 1 || frames > 65535) return fail(SAFR_ERR_ARG, "frames must be in 1..65535");
+    if (!std::isfinite(weight)) return fail(SAFR_ERR_ARG, "weight must be finite");
+    HIP_TRY(launch_polc(polc_args(p, wf, layers, weight, out), frames, s));
+    return SAFR_OK;
+}
+
+safr_status safr_loop_step(safr_plan* p, int frames, const float* wf, const float* a_in, float gain, float* a_out,
+                           hipStream_t s) {
+    if (!p || !wf || !a_in || !a_out) return fail(SAFR_ERR_ARG, "NULL argument");
+    if (frames < 1 || frames > 65535) return fail(SAFR_ERR_ARG, "frames must be in 1..65535");
+    if (!std::isfinite(gain)) return fail(SAFR_ERR_ARG, "gain must be finite");
+    const size_t need = ws_bytes(p, frames);
+    void* ws = nullptr;
+    if (p->ws_user && p->ws_user_bytes >= need) ws = p->ws_user;
+    else if (p->ws_own_bytes >= need) ws = p->ws_own;
+    else return fail(SAFR_ERR_STATE, "workspace of %zu bytes needed for %d frames", need, frames);
+
+    if (p->use_graph && s != nullptr) {
+        const bool hit = p->lexec && p->l_frames == frames && p->l_gain == gain && p->l_wf == wf &&
+                         p->l_ain == a_in && p->l_aout == a_out && p->l_stream == s;
+        if (!hit) {
+            if (p->lexec) hipGraphExecDestroy(p->lexec);
+            if (p->lgraph) hipGraphDestroy(p->lgraph);
+            p->lexec = nullptr;
+            p->lgraph = nullptr;
+            HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            safr_status st = launch_loop(p, frames, wf, a_in, gain, a_out, ws, s);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(s, &g);
+            if (st != SAFR_OK) {
+                if (g) hipGraphDestroy(g);
+                return st;
+            }
+            if (e != hipSuccess) return fail(SAFR_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+            p->lgraph = g;
+            HIP_TRY(hipGraphInstantiate(&p->lexec, g, nullptr, nullptr, 0));
+            p->l_frames = frames;
+            p->l_gain = gain;
+            p->l_wf = wf;
+            p->l_ain = a_in;
+            p->l_aout = a_out;
+            p->l_stream = s;
+        }
+        HIP_TRY(hipGraphLaunch(p->lexec, s));
+        return SAFR_OK;
+    }
+    return launch_loop(p, frames, wf, a_in, gain, a_out, ws, s);
+}
+
 safr_status safr_time_stages(safr_plan* p, int frames, const float* wf, float* out, int precision, int iters,
                              hipStream_t s, double* ms) {
     if (!p || !wf || !out || !ms || iters < 1) return fail(SAFR_ERR_ARG, "bad argument");
@@ -749,12 +871,7 @@ safr_status safr_autotune(safr_plan* p, int frames, const float* wf, float* out,
         p->col_nf = bestn;
     }
     for (auto& e : ev) hipEventDestroy(e);
-    if (p->gexec) {                      // a captured graph holds the old launch shapes
-        hipGraphExecDestroy(p->gexec);
-        hipGraphDestroy(p->graph);
-        p->gexec = nullptr;
-        p->graph = nullptr;
-    }
+    drop_graphs(p);
     if (choice) {
         choice[0] = p->row_teams;
         choice[1] = p->out_rows;
@@ -917,12 +1034,7 @@ void safr_multi_destroy(safr_multi* m) { free_multi(m); }
 
 safr_status safr_set_option(safr_plan* p, int option, int value) {
     if (!p) return fail(SAFR_ERR_ARG, "plan is NULL");
-    if (p->gexec) {                      // a captured graph holds the old launch shapes
-        hipGraphExecDestroy(p->gexec);
-        hipGraphDestroy(p->graph);
-        p->gexec = nullptr;
-        p->graph = nullptr;
-    }
+    drop_graphs(p);
     switch (option) {
         case 0: p->use_graph = value != 0; return SAFR_OK;
         case 1:
@@ -970,7 +1082,7 @@ safr_status safr_set_option(safr_plan* p, int option, int value) {
 namespace {
 
 safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, int precision, void* ws,
-                       hipStream_t s, hipEvent_t* ev) {
+                       hipStream_t s, hipEvent_t* ev, const float* prev, float gain) {
     if (ev) HIP_TRY(hipEventRecord(ev[0], s));
     char* base = reinterpret_cast<char*>(ws);
     float2* R = reinterpret_cast<float2*>(base);
@@ -1065,6 +1177,8 @@ safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, in
     oa.nchunk = nchunk;
     oa.frames = frames;
     oa.frames_per_block = std::max(1, p->out_frames);
+    oa.prev = prev;
+    oa.gain = gain;
     HIP_TRY(launch_out(p->M, oa, p->out_rows, frames, s));
     if (ev) HIP_TRY(hipEventRecord(ev[3], s));
     return SAFR_OK;

@@ -70,7 +70,23 @@ struct OutArgs {
     int ngs_star[kMaxG];        // star index of natural star g
     int nb;                     // 2 x natural stars (0: no natural-star part)
     int L, J, nchunk, frames, frames_per_block;
+    const float* prev;          // integrator (Alg. 3): out = (1 - gain) prev + gain layers; nullptr = plain
+    float gain;
 };
+
+// Pseudo-open-loop data (Alg. 3): out = pupil .* (wf + weight * A(layers)), A sampled bilinearly along
+// each star's line of sight.  tab[g][l] = (m, u0, v0, 0): pupil pixel (i, j) of star g crosses output
+// layer l at the fractional grid index (u0 + m i, v0 + m j).
+struct PolcArgs {
+    const float* wf;            // [F][J][n][n]
+    const float* layers;        // [F][L][M][M]
+    float* out;                 // [F][J][n][n]
+    const unsigned char* pupil; // [n][n]
+    const float4* tab;          // [J][L]
+    float weight;
+    int n, M, J, L;
+};
+hipError_t launch_polc(const PolcArgs& a, int frames, hipStream_t s);
 
 // BF16 hi/lo split apply on matrix cores (batched path).
 struct MfmaArgs {

@@ -32,6 +32,7 @@ EXPORTED = [
     "safr_set_workspace", "safr_plan_info", "safr_export_B", "safr_set_option", "safr_time_stages",
     "safr_autotune", "safr_destroy", "safr_last_error",
     "safr_multi_create", "safr_multi_execute", "safr_multi_autotune", "safr_multi_destroy",
+    "safr_polc", "safr_loop_step",
     # learned filter (bound in learn.py)
     "safr_trainer_create", "safr_trainer_add_frames", "safr_trainer_set_params", "safr_trainer_get_params",
     "safr_trainer_step", "safr_trainer_gradient", "safr_trainer_frames", "safr_trainer_destroy", "safr_mlp_infer",
@@ -105,7 +106,9 @@ def lib() -> ctypes.CDLL:
     L.safr_multi_autotune.argtypes = [vp, pp, pp, i, vp]
     L.safr_multi_destroy.argtypes = [vp]
     L.safr_multi_destroy.restype = None
-    for name in EXPORTED[:17]:
+    L.safr_polc.argtypes = [vp, i, vp, vp, ctypes.c_float, vp, vp]
+    L.safr_loop_step.argtypes = [vp, i, vp, vp, ctypes.c_float, vp, vp]
+    for name in EXPORTED[:EXPORTED.index("safr_trainer_create")]:
         if name not in ("safr_destroy", "safr_last_error", "safr_multi_destroy"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -241,6 +244,18 @@ def safr_autotune(plan: Plan, frames: int, wavefronts, layers, precision: int = 
     _check(lib().safr_autotune(plan._as_parameter_, int(frames), _ptr(wavefronts), _ptr(layers), int(precision),
                                int(iters), _stream(stream), ch))
     return tuple(int(x) for x in ch)
+
+
+def safr_polc(plan: Plan, frames: int, wavefronts, layers, weight: float, out, stream=None):
+    """Pseudo-open-loop data: out = pupil * (wavefronts + weight * A(layers)) for each frame."""
+    _check(lib().safr_polc(plan._as_parameter_, int(frames), _ptr(wavefronts), _ptr(layers), float(weight),
+                           _ptr(out), _stream(stream)))
+
+
+def safr_loop_step(plan: Plan, frames: int, wavefronts, a_in, gain: float, a_out, stream=None):
+    """One closed-loop step: a_out = (1 - gain) a_in + gain * SAFR(POLC(wavefronts, a_in))."""
+    _check(lib().safr_loop_step(plan._as_parameter_, int(frames), _ptr(wavefronts), _ptr(a_in), float(gain),
+                                _ptr(a_out), _stream(stream)))
 
 
 def safr_plan_info(plan: Plan) -> safr_plan_desc:
