@@ -221,12 +221,28 @@ def learned_cutoff(sigma: np.ndarray) -> np.ndarray:
     return np.sqrt(EPS) * sigma[..., :1]
 
 
-def tikhonov_filter(sigma: np.ndarray, alpha: float, G: int, L: int) -> np.ndarray:
-    """g(s) = s / (s^2 + alpha) (Sec. 3.1); alpha = 0 gives 1/s above the rank tolerance."""
-    if alpha > 0.0:
-        return sigma / (sigma ** 2 + alpha)
+def tikhonov_filter(sigma: np.ndarray, alpha, G: int, L: int) -> np.ndarray:
+    """g(s) = s / (s^2 + alpha) (Sec. 3.1); alpha = 0 gives 1/s above the rank tolerance.
+
+    alpha is a scalar or an array broadcastable against sigma (one value per frequency,
+    Sec. 3.1 allows a different parameter for each A_jk).
+    """
+    alpha = np.broadcast_to(np.asarray(alpha, dtype=np.float64), sigma.shape)
     tol = rank_tolerance(sigma, G, L)
     keep = sigma > tol
+    pinv = np.where(keep, 1.0 / np.where(keep, sigma, 1.0), 0.0)
+    tik = sigma / (sigma ** 2 + np.where(alpha > 0.0, alpha, 1.0))
+    return np.where(alpha > 0.0, tik, pinv)
+
+
+def tsvd_filter(sigma: np.ndarray, alpha, G: int, L: int) -> np.ndarray:
+    """Truncated SVD (Sec. 3.1 admits truncation): g(s) = 1/s for s^2 > alpha, else 0.
+
+    The cut sits where Tikhonov's filter factor s^2 / (s^2 + alpha) equals 1/2, so
+    alpha plays the same role in both filters; alpha = 0 is the pseudo-inverse.
+    """
+    alpha = np.broadcast_to(np.asarray(alpha, dtype=np.float64), sigma.shape)
+    keep = (sigma > rank_tolerance(sigma, G, L)) & (sigma ** 2 > alpha)
     return np.where(keep, 1.0 / np.where(keep, sigma, 1.0), 0.0)
 
 
@@ -298,14 +314,18 @@ def split_groups(kinds, alpha: float, alpha_tt: float):
 def precompute(*, n: int, M: int, pitch: float, stars, h_lgs: float, heights, weights,
                alpha: float, alpha_tt: float, beta: float, pupil=None, mlp_params=None,
                eta: float = 0.01, mlp_bf16: bool = False, phi_fn=None,
-               keep_svd: bool = False) -> Plan:
+               keep_svd: bool = False, filter: str = "tikhonov", alpha_weight=None) -> Plan:
     """Alg. 2 for every frequency of the M x M grid and every group.
 
     For each array index pair (j, k): n = (n(j), n(k)); A_n per Sec. 3.1; SVD;
     filter; b_{n,lg} = scale_l(n) * sum_r g(sigma_r) conj(U[g, r]) V[l, r].
     With ``mlp_params`` the filter is g_r = phi_r / sigma_r, phi = MLP(features);
     ``phi_fn`` (features (N, 4) -> phi (N,)) replaces the network by any other map.
+    ``filter`` = "tikhonov" or "tsvd"; ``alpha_weight`` (M, M), indexed by the array
+    indices (j, k) like B, scales the group's alpha per frequency.
     """
+    if filter not in ("tikhonov", "tsvd"):
+        raise ValueError(f"unknown filter {filter}")
     if mlp_params is not None and phi_fn is None:
         def phi_fn(F):
             return _mlp.forward(mlp_params, F, bf16=mlp_bf16)
@@ -324,8 +344,9 @@ def precompute(*, n: int, M: int, pitch: float, stars, h_lgs: float, heights, we
         A = tomography_matrix(NX, NY, stars[idx, :2], heights, c, gamma, T, beta)  # (M,M,G,L)
         U, sig, V = jacobi_svd(A)
         G = len(idx)
+        a_n = a if alpha_weight is None else a * np.asarray(alpha_weight, dtype=np.float64)[..., None]
         if phi_fn is None:
-            g = tikhonov_filter(sig, a, G, L)
+            g = (tikhonov_filter if filter == "tikhonov" else tsvd_filter)(sig, a_n, G, L)
         else:
             feats = mlp_features(NX, NY, T, sig, V, gamma, eta)
             phi = np.asarray(phi_fn(feats.reshape(-1, 4))).reshape(sig.shape)
