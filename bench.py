@@ -134,6 +134,38 @@ def run_c3(S, torch, stream):
     return res
 
 
+def run_loop(S, torch, plan, geo, pool, calls):
+    """One closed loop of the MORFEO-like geometry: POLC, reconstruction and integrator per time step.
+
+    The measurement and command buffers stay fixed, as in a real-time loop, so the captured graph
+    of the step is replayed on every call.
+    """
+    L, M = geo.L, geo.M
+    wf = pool[0].clone()
+    a = torch.zeros((L, M, M), dtype=torch.float32, device="cuda")
+    gain = 0.5
+    res = {"workload": "MORFEO-like geometry (J=9, L=9, n=69, M=256), one loop, gain 0.5, "
+                       "fixed measurement and command buffers",
+           "loop_rate_requirement_hz": [500, 1000]}
+    cur = torch.cuda.current_stream()
+    for name, graph in (("eager", 0), ("graph", 1)):
+        S.safr_set_option(plan, S.SAFR_OPT_GRAPH, graph)
+        s = torch.cuda.Stream() if graph else cur
+        torch.cuda.synchronize()
+        for _ in range(100):
+            S.safr_loop_step(plan, 1, wf, a, gain, a, s)
+        ms = _timed(lambda: S.safr_loop_step(plan, 1, wf, a, gain, a, s), calls, s, torch)
+        res[f"us_per_step_{name}"] = round(ms * 1000.0, 3)
+    S.safr_set_option(plan, S.SAFR_OPT_GRAPH, 0)
+    out = torch.empty_like(wf)
+    ms = _timed(lambda: S.safr_polc(plan, 1, wf, a, 1.0, out, cur), calls, cur, torch)
+    res["us_per_polc_call"] = round(ms * 1000.0, 3)
+    best = min(res["us_per_step_eager"], res["us_per_step_graph"])
+    res["steps_per_s"] = round(1e6 / best, 1)
+    res["fraction_of_1khz_budget"] = round(best / 1000.0, 4)
+    return res
+
+
 _WS = {}
 
 
@@ -398,6 +430,8 @@ def main():
     stage1_ms = S.safr_time_stages(plan1, 1, pool[0], out[0], S.SAFR_FP32, 50, stream)
     result["single_frame"] = {"us_per_frame": round(us_single, 3), "frames_per_s": round(1e6 / us_single, 1),
                               "stage_ms": {k: round(v, 6) for k, v in zip(names, stage1_ms)}}
+    print("bench: closed-loop step (Alg. 3)", file=sys.stderr, flush=True)
+    result["closed_loop"] = run_loop(S, torch, plan1, geo, pool, args.single_calls)
     if not args.no_extras:
         print("bench: 1024-frame batches (C1 geometry)", file=sys.stderr, flush=True)
         result["c3_batched_1024"] = run_c3(S, torch, stream)

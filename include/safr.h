@@ -57,7 +57,12 @@ typedef enum {
 } safr_status;
 
 enum { SAFR_NGS = 0, SAFR_LGS = 1 };
-enum { SAFR_FILTER_TIKHONOV = 0, SAFR_FILTER_MLP = 1 };
+/* Filters of the regularised inverse (Sec. 3.1):
+ *   TIKHONOV  g(s) = s / (s^2 + alpha); alpha = 0: pseudo-inverse (rank tolerance max(G,L) eps s_1);
+ *   MLP       learned filter factors (see the learned-filter section below);
+ *   TSVD      truncation, g(s) = 1/s for s^2 > alpha (and above the rank tolerance), else 0: the cut
+ *             sits where Tikhonov's filter factor s^2 / (s^2 + alpha) is 1/2. */
+enum { SAFR_FILTER_TIKHONOV = 0, SAFR_FILTER_MLP = 1, SAFR_FILTER_TSVD = 2 };
 enum { SAFR_FP32 = 0, SAFR_BF16X3 = 1 };
 
 #define SAFR_MAX_STARS_PER_GROUP 16
@@ -82,9 +87,15 @@ typedef struct {
     const unsigned char* pupil;     /* n*n mask, row-major, nonzero = inside; NULL = all inside */
     double beta;                    /* Sobolev smoothness, >= 0 */
     double alpha_tt;                /* Tikhonov parameter of the natural-star group when mixed */
-    int filter;                     /* SAFR_FILTER_TIKHONOV or SAFR_FILTER_MLP */
+    int filter;                     /* SAFR_FILTER_TIKHONOV, SAFR_FILTER_MLP or SAFR_FILTER_TSVD */
     const float* mlp;               /* SAFR_MLP_PARAMS network parameters (learned filter only) */
     double noise;                   /* relative noise level, a network input (learned filter only) */
+    /* NULL, or [M][M] multipliers w >= 0 of the regularisation parameter per frequency (Sec. 3.1
+     * allows one per A_jk): frequency (j, k) uses alpha w[j][k] (alpha_tt w[j][k] for the natural
+     * stars of a mixed asterism); j, k are the DFT indices along the first and second grid axis.
+     * Must be point-symmetric, w[j][k] = w[(M-j)%M][(M-k)%M], so that B stays Hermitian.
+     * Tikhonov and TSVD filters only. */
+    const double* alpha_weight;
 } safr_geometry;
 
 typedef struct safr_plan safr_plan;

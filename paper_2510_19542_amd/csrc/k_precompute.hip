@@ -154,12 +154,16 @@ __global__ void assemble_kernel(PrecompArgs a) {
     double smax = 0.0;
     for (int c = 0; c < C; ++c) smax = fmax(smax, sg[c]);
     const double tol = (double)(G > L ? G : L) * 2.220446049250313e-16 * smax;
+    // regularisation parameter of this frequency (the weight map is point-symmetric, so the mirrored
+    // frequency's value is the same)
+    const double an = a.aw ? a.alpha * a.aw[(size_t)js * M + k] : a.alpha;
     double hv[kMaxL];
     for (int c = 0; c < C; ++c) {
         const double s = sg[c];
         double v;
         if (a.phi) v = s > kSqrtEps * smax ? (double)a.phi[(size_t)hs * C + c] / (s * s) : 0.0;
-        else if (a.alpha > 0.0) v = 1.0 / (s * s + a.alpha);
+        else if (a.tsvd) v = (s > tol && s * s > an) ? 1.0 / (s * s) : 0.0;
+        else if (an > 0.0) v = 1.0 / (s * s + an);
         else v = s > tol ? 1.0 / (s * s) : 0.0;
         hv[c] = v;
     }

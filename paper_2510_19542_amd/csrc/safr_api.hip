@@ -275,8 +275,19 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
     if (!(geo->beta >= 0.0) || !std::isfinite(geo->beta)) return fail(SAFR_ERR_ARG, "beta must be >= 0");
     if (!(geo->alpha_tt >= 0.0) || !std::isfinite(geo->alpha_tt))
         return fail(SAFR_ERR_ARG, "alpha_tt must be >= 0");
-    if (geo->filter != SAFR_FILTER_TIKHONOV && geo->filter != SAFR_FILTER_MLP)
+    if (geo->filter != SAFR_FILTER_TIKHONOV && geo->filter != SAFR_FILTER_MLP && geo->filter != SAFR_FILTER_TSVD)
         return fail(SAFR_ERR_ARG, "unknown filter %d", geo->filter);
+    if (geo->alpha_weight) {
+        if (geo->filter == SAFR_FILTER_MLP) return fail(SAFR_ERR_ARG, "alpha_weight needs the Tikhonov or TSVD filter");
+        for (int j = 0; j < M; ++j)
+            for (int k = 0; k < M; ++k) {
+                const double w = geo->alpha_weight[(size_t)j * M + k];
+                if (!(w >= 0.0) || !std::isfinite(w))
+                    return fail(SAFR_ERR_ARG, "alpha_weight[%d][%d] must be finite and >= 0", j, k);
+                if (w != geo->alpha_weight[(size_t)((M - j) % M) * M + (M - k) % M])
+                    return fail(SAFR_ERR_ARG, "alpha_weight must be point-symmetric (w[j][k] = w[-j][-k])");
+            }
+    }
     if (geo->filter == SAFR_FILTER_MLP && (!geo->mlp || !(geo->noise > 0.0)))
         return fail(SAFR_ERR_ARG, "learned filter needs parameters and noise > 0");
     int nl = 0, nn = 0;
@@ -385,6 +396,7 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
     float* feats = nullptr;
     float* phi = nullptr;
     float* mlp_dev = nullptr;
+    double* aw_dev = nullptr;
     int* dbad = nullptr;
     double2* X64 = nullptr;
     double2* Y64 = nullptr;
@@ -470,6 +482,10 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
             PC_TRY(hipMalloc(&mlp_dev, SAFR_MLP_PARAMS * sizeof(float)));
             PC_TRY(hipMemcpy(mlp_dev, geo->mlp, SAFR_MLP_PARAMS * sizeof(float), hipMemcpyHostToDevice));
         }
+        if (geo->alpha_weight) {
+            PC_TRY(hipMalloc(&aw_dev, (size_t)M * M * sizeof(double)));
+            PC_TRY(hipMemcpy(aw_dev, geo->alpha_weight, (size_t)M * M * sizeof(double), hipMemcpyHostToDevice));
+        }
         for (int gi = 0; gi < p->ngroups && st == SAFR_OK; ++gi) {
             PrecompArgs a{};
             a.M = M;
@@ -497,6 +513,8 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
             a.B32 = p->B32 + p->boff32[gi];
             a.log10_noise = geo->filter == SAFR_FILTER_MLP ? std::log10(geo->noise) : 0.0;
             a.bad = dbad;
+            a.tsvd = geo->filter == SAFR_FILTER_TSVD;
+            a.aw = aw_dev;
             PC_TRY(launch_svd(a, stream));
             if (geo->filter == SAFR_FILTER_MLP) {
                 const int C = std::min(a.G, L);
@@ -568,6 +586,7 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
     hipFree(feats);
     hipFree(phi);
     hipFree(mlp_dev);
+    hipFree(aw_dev);
     hipFree(dbad);
     hipFree(X64);
     hipFree(Y64);

@@ -229,6 +229,8 @@ struct PrecompArgs {
     float2* B32;
     double log10_noise;
     int* bad;         // set to 1 if a non-finite value appears
+    int tsvd;         // 1 = truncated SVD instead of Tikhonov (no learned filter)
+    const double* aw; // [M][M] per-frequency multipliers of alpha, or nullptr
 };
 hipError_t launch_svd(const PrecompArgs& a, hipStream_t s);
 hipError_t launch_assemble(const PrecompArgs& a, hipStream_t s);

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libsafr.so")
 SAFR_OK, SAFR_ERR_ARG, SAFR_ERR_GEOMETRY, SAFR_ERR_DOMAIN = 0, -1, -2, -3
 SAFR_ERR_UNSUPPORTED, SAFR_ERR_NUMERIC, SAFR_ERR_DEVICE, SAFR_ERR_STATE = -4, -5, -6, -7
 SAFR_NGS, SAFR_LGS = 0, 1
-SAFR_FILTER_TIKHONOV, SAFR_FILTER_MLP = 0, 1
+SAFR_FILTER_TIKHONOV, SAFR_FILTER_MLP, SAFR_FILTER_TSVD = 0, 1, 2
 SAFR_FP32, SAFR_BF16X3 = 0, 1
 SAFR_OPT_GRAPH, SAFR_OPT_ROW_TEAMS, SAFR_OPT_OUT_ROWS, SAFR_OPT_MFMA_FRAMES, SAFR_OPT_COL_FRAMES = 0, 1, 2, 3, 4
 SAFR_OPT_COL_PREFETCH, SAFR_OPT_OUT_FRAMES, SAFR_OPT_COL_TOGETHER = 5, 6, 7
@@ -56,6 +56,7 @@ class safr_geometry(ctypes.Structure):
         ("h_lgs", ctypes.c_double), ("pupil", ctypes.POINTER(ctypes.c_ubyte)),
         ("beta", ctypes.c_double), ("alpha_tt", ctypes.c_double), ("filter", ctypes.c_int),
         ("mlp", ctypes.POINTER(ctypes.c_float)), ("noise", ctypes.c_double),
+        ("alpha_weight", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -166,8 +167,9 @@ class Plan:
 
 def safr_precompute(*, n: int, M: int, pitch: float, stars: Sequence, h_lgs: float, heights, weights,
                     alpha: float, alpha_tt: float, beta: float, pupil=None, filter: int = SAFR_FILTER_TIKHONOV,
-                    mlp=None, noise: float = 0.0, stream=None) -> Plan:
-    """Alg. 2 on the GPU (see safr.h); returns a Plan."""
+                    mlp=None, noise: float = 0.0, alpha_weight=None, stream=None) -> Plan:
+    """Alg. 2 on the GPU (see safr.h); returns a Plan.  alpha_weight: optional (M, M) per-frequency
+    multipliers of alpha (point-symmetric)."""
     L = lib()
     st = np.asarray(stars, dtype=np.float64).reshape(-1, 3)
     arr = (safr_star * len(st))(*[safr_star(float(a), float(b), int(k)) for a, b, k in st])
@@ -185,6 +187,10 @@ def safr_precompute(*, n: int, M: int, pitch: float, stars: Sequence, h_lgs: flo
         mb = np.ascontiguousarray(np.asarray(mlp, dtype=np.float32).ravel())
         keep.append(mb)
         g.mlp = mb.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    if alpha_weight is not None:
+        aw = np.ascontiguousarray(np.asarray(alpha_weight, dtype=np.float64).reshape(M, M))
+        keep.append(aw)
+        g.alpha_weight = aw.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     h = np.ascontiguousarray(np.asarray(heights, dtype=np.float64))
     w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
     out = ctypes.c_void_p()

@@ -1,0 +1,156 @@
+"""Truncated SVD and per-frequency alpha (Sec. 3.1) through the C ABI, against the oracle.
+
+B from the GPU's FP64 precomputation must match the oracle's within 1e-12
+(relative to the largest entry), as for the Tikhonov filter.  Truncation decides
+per singular value, so alpha is chosen with every s^2 at least 1e-8 alpha away
+from it (both sides' singular values agree to about 1e-15), and both take the
+decision in FP64.  Reconstructions with these operators: relative L2 within 1e-5.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import safr as O
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _lib():
+    from paper_2510_19542_amd import safr as S
+    S.lib()
+    return S
+
+
+def _small(M, n, kinds, L, seed, pitch=0.5):
+    rng = np.random.default_rng(500 + seed)
+    T = M * pitch / 2
+    half = (n - 1) * pitch / 2
+    h = np.sort(rng.uniform(0, 12000, L))
+    h[0] = 0.0
+    h = np.maximum.accumulate(h + np.arange(L) * 10.0)
+    amax = abs(0.8 * (0.7 * T - half) / max(h.max(), 1.0))
+    stars = [(float(rng.uniform(-amax, amax)), float(rng.uniform(-amax, amax)), int(k)) for k in kinds]
+    return synth.Geometry(name=f"filt{seed}", n=n, M=M, pitch=pitch, diameter=(n - 1) * pitch,
+                          obstruction=0.0, stars=stars, h_lgs=90e3, heights=h,
+                          weights=rng.uniform(0.2, 1.0, L), alpha=1e-3, alpha_tt=1e-3, beta=1.5,
+                          truth_heights=h, truth_fracs=np.ones(L) / L, r0=0.15, L0=25.0, eta=0.01,
+                          config_id=290 + seed)
+
+
+CASES = {
+    "C1": lambda: synth.preset("C1"),
+    "C2": lambda: synth.preset("C2"),
+    "m32-mixed": lambda: _small(32, 19, (1, 1, 1, 0, 0), 3, 1),
+    "m64-lgs-L5": lambda: _small(64, 31, (1, 1, 1, 1), 5, 2),
+}
+
+
+def _clear_alpha(sig):
+    """Median of s^2, moved until no singular value is within 1e-8 of the cut."""
+    s2 = sig[sig > 0] ** 2
+    a = float(np.median(s2))
+    while np.min(np.abs(s2 - a)) <= 1e-8 * a:
+        a *= 1.01
+    return a
+
+
+_SVD = {}
+
+
+def _svd(geo):
+    """Singular values of each group (independent of alpha), from the oracle, cached per geometry."""
+    if geo.name not in _SVD:
+        _SVD[geo.name] = [g.sigma for g in O.precompute_geometry(geo, keep_svd=True).groups]
+    return _SVD[geo.name]
+
+
+def _tsvd_geometry(geo):
+    """alpha (and alpha_tt) at the median squared singular value of each group."""
+    a = [_clear_alpha(sig) for sig in _svd(geo)]
+    return geo.replace(alpha=a[0], alpha_tt=a[1] if len(a) > 1 else geo.alpha_tt)
+
+
+def _symmetric_weights(M, seed):
+    rng = np.random.default_rng(seed)
+    w = rng.uniform(0.05, 20.0, (M, M))
+    return 0.5 * (w + np.roll(w[::-1, ::-1], (1, 1), axis=(0, 1)))
+
+
+def _compare_B(S, plan, ref, M):
+    for gi, grp in enumerate(ref.groups):
+        got = S.safr_export_B(plan, gi)
+        want = np.transpose(grp.B[:, : M // 2 + 1], (1, 0, 2, 3))
+        err = np.max(np.abs(got - want)) / np.max(np.abs(want))
+        assert err <= 1e-12, (gi, err)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_tsvd_B_matches_oracle(case):
+    S = _lib()
+    geo = _tsvd_geometry(CASES[case]())
+    ref = O.precompute_geometry(geo, filter="tsvd", keep_svd=True)
+    for g in ref.groups:                     # the truncation is partial somewhere
+        kept = np.sum(g.sigma ** 2 > g.alpha, axis=-1)
+        assert np.any((kept > 0) & (kept < g.sigma.shape[-1]))
+    plan = S.precompute_geometry(geo, filter=S.SAFR_FILTER_TSVD)
+    _compare_B(S, plan, ref, geo.M)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("filt", ["tikhonov", "tsvd"])
+def test_per_frequency_alpha_B_matches_oracle(case, filt):
+    S = _lib()
+    geo = CASES[case]()
+    if filt == "tsvd":
+        geo = _tsvd_geometry(geo)
+    w = _symmetric_weights(geo.M, 7)
+    if filt == "tsvd":                       # keep the weighted cuts clear of every singular value
+        for sig, alpha in zip(_svd(geo), (geo.alpha, geo.alpha_tt)):
+            s2 = sig ** 2
+            an = alpha * w[..., None]
+            assert np.min(np.abs(s2 - an)[s2 > 0] / an.repeat(s2.shape[-1], -1)[s2 > 0]) > 1e-8
+    ref = O.precompute_geometry(geo, filter=filt, alpha_weight=w)
+    code = S.SAFR_FILTER_TSVD if filt == "tsvd" else S.SAFR_FILTER_TIKHONOV
+    plan = S.precompute_geometry(geo, filter=code, alpha_weight=w)
+    _compare_B(S, plan, ref, geo.M)
+
+
+@pytest.mark.parametrize("case", ["C1", "m32-mixed"])
+def test_tsvd_and_weighted_reconstruction(case):
+    torch = _torch()
+    S = _lib()
+    geo = _tsvd_geometry(CASES[case]())
+    w = _symmetric_weights(geo.M, 8)
+    wf = synth.frames(geo, 2, first=1)
+    x = torch.from_numpy(wf).cuda()
+    for filt, kw, okw in (("tsvd", {"filter": S.SAFR_FILTER_TSVD}, {"filter": "tsvd"}),
+                          ("weighted", {"alpha_weight": w}, {"alpha_weight": w})):
+        plan = S.precompute_geometry(geo, **kw)
+        ref = O.precompute_geometry(geo, **okw)
+        out = S.reconstruct(plan, x)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        for f in range(2):
+            want = O.reconstruct(ref, wf[f])
+            err = float(np.linalg.norm(got[f] - want) / np.linalg.norm(want))
+            assert err <= 1e-5, (case, filt, f, err)
+
+
+def test_filter_argument_errors():
+    S = _lib()
+    geo = CASES["C1"]()
+    M = geo.M
+    bad = _symmetric_weights(M, 9)
+    bad[1, 2] += 1.0                          # breaks point symmetry
+    for kw in ({"alpha_weight": bad}, {"alpha_weight": -np.ones((M, M))}, {"filter": 3},
+               {"alpha_weight": np.ones((M, M)), "filter": S.SAFR_FILTER_MLP,
+                "mlp": np.zeros(S.SAFR_MLP_PARAMS, np.float32), "noise": 0.01}):
+        with pytest.raises(S.SafrError) as e:
+            S.precompute_geometry(geo, **kw)
+        assert e.value.status == S.SAFR_ERR_ARG, kw
