@@ -689,3 +689,37 @@ def loop_step(plan: Plan, wavefronts: np.ndarray, a: np.ndarray, gain: float) ->
     """
     phi = reconstruct(plan, polc(plan, wavefronts, a))
     return (1.0 - gain) * np.asarray(a, dtype=np.float64) + gain * phi
+
+
+# --------------------------------------------------------------------------------------
+# Sec. 4: Strehl ratio by the Marechal approximation
+# --------------------------------------------------------------------------------------
+
+def residual_phase(plan: Plan, open_loop: np.ndarray, layers: np.ndarray, directions) -> np.ndarray:
+    """Phase left in science directions after the correction: open_loop - A_theta(a), on the pupil.
+
+    Science objects are at infinity (cone coefficient 1 on every layer).  open_loop (D, n, n).
+    """
+    directions = np.asarray(directions, dtype=np.float64).reshape(-1, 2)
+    cones = np.ones((len(directions), plan.L))
+    corr = forward_layers(plan, layers, directions, cones)
+    return np.where(plan.pupil[None], np.asarray(open_loop, dtype=np.float64), 0.0) - corr
+
+
+def pupil_variance(phase: np.ndarray, pupil: np.ndarray) -> np.ndarray:
+    """Variance over the pupil pixels (piston removed) of each (n, n) map in ``phase``."""
+    m = pupil.astype(bool)
+    vals = phase[..., m]
+    return np.mean((vals - vals.mean(axis=-1, keepdims=True)) ** 2, axis=-1)
+
+
+def marechal_strehl(variance_rad2) -> np.ndarray:
+    """Strehl ratio exp(-sigma^2) from the residual phase variance in rad^2 (Marechal)."""
+    return np.exp(-np.asarray(variance_rad2, dtype=np.float64))
+
+
+def strehl(plan: Plan, open_loop: np.ndarray, layers: np.ndarray, directions, scale: float = 1.0):
+    """(Strehl ratios, variances in rad^2) of the residual in each direction; ``scale`` converts the
+    data's phase unit to radians at the science wavelength."""
+    var = scale ** 2 * pupil_variance(residual_phase(plan, open_loop, layers, directions), plan.pupil)
+    return marechal_strehl(var), var
