@@ -140,6 +140,7 @@ def run_loop(S, torch, plan, geo, pool, calls):
     The measurement and command buffers stay fixed, as in a real-time loop, so the captured graph
     of the step is replayed on every call.
     """
+    import numpy as np
     L, M = geo.L, geo.M
     wf = pool[0].clone()
     a = torch.zeros((L, M, M), dtype=torch.float32, device="cuda")
@@ -160,6 +161,13 @@ def run_loop(S, torch, plan, geo, pool, calls):
     out = torch.empty_like(wf)
     ms = _timed(lambda: S.safr_polc(plan, 1, wf, a, 1.0, out, cur), calls, cur, torch)
     res["us_per_polc_call"] = round(ms * 1000.0, 3)
+    # Strehl estimate in a 3 x 3 grid of science directions over the central arcminute
+    t = np.linspace(-30.0, 30.0, 3) * np.pi / (180.0 * 3600.0)
+    dirs = np.array([(x, y) for x in t for y in t])
+    ol = torch.zeros((1, len(dirs), geo.n, geo.n), dtype=torch.float32, device="cuda")
+    sr = torch.empty((1, len(dirs)), dtype=torch.float32, device="cuda")
+    ms = _timed(lambda: S.safr_strehl(plan, 1, dirs, ol, a, 0.5 / 2.2, sr, None, cur), calls, cur, torch)
+    res["us_per_strehl_call_9_directions"] = round(ms * 1000.0, 3)
     best = min(res["us_per_step_eager"], res["us_per_step_graph"])
     res["steps_per_s"] = round(1e6 / best, 1)
     res["fraction_of_1khz_budget"] = round(best / 1000.0, 4)

@@ -237,6 +237,21 @@ safr_status safr_polc(safr_plan* p, int frames, const float* wavefronts, const f
 safr_status safr_loop_step(safr_plan* p, int frames, const float* wavefronts, const float* a_in, float gain,
                            float* a_out, hipStream_t stream);
 
+/* Strehl estimate in science directions (Sec. 4: Marechal approximation).  For `frames` frames
+ * (1..65535) and D directions (1..32; dirs: host [D][2] in rad): the residual phase
+ * open_loop[f][d] - A_d(layers[f]) over the pupil, with A_d the operator above for a source at
+ * infinity (cone coefficient 1 on every layer), its variance over the pupil pixels after piston
+ * removal, times scale^2 (scale converts the data's phase unit to rad at the science wavelength;
+ * an empty pupil gives 0), and sr = exp(-variance).  open_loop [frames][D][n][n], layers
+ * [frames][L][M][M], sr and var [frames][D], FP32 device memory; var may be NULL.  Directions and
+ * sample positions are taken in FP32, the variance is accumulated in FP32 (per 256-pixel chunk,
+ * then pairwise merges in a fixed order).  The plan keeps a small buffer of per-chunk moments that
+ * grows on demand (the first call with more frames or directions synchronises the stream and
+ * allocates); calls on one plan must not overlap.  Otherwise asynchronous on `stream`.
+ * Errors: SAFR_ERR_ARG (NULL, counts, non-finite scale or direction), SAFR_ERR_DEVICE. */
+safr_status safr_strehl(safr_plan* p, int frames, int D, const double* dirs, const float* open_loop,
+                        const float* layers, float scale, float* sr, float* var, hipStream_t stream);
+
 /* ---- Mixed-size batches -------------------------------------------------------------------
  * A bundle of plans (different geometries and grid sizes), each with its own frame count.
  * safr_multi_execute reconstructs every entry's frames (wavefronts[i]: [frames[i]][J][n][n],

@@ -1,0 +1,107 @@
+// Strehl ratio by the Marechal approximation (Sec. 4) in science directions.
+//
+// For each frame and direction theta the residual phase at every pupil pixel is
+// the open-loop phase minus the commands sampled along theta (science objects at
+// infinity: cone coefficient 1, so on output grid l the pixel (i, j) maps to
+// (base_l + m_l i + theta_x hs_l, base_l + m_l j + theta_y hs_l), periodic bilinear
+// interpolation).  Its piston-removed variance over the pupil gives the Strehl
+// ratio exp(-variance).
+//
+// Two launches: the partial pass gives every pupil chunk of 256 pixels its own
+// block (one pixel per thread, so the chunks of all directions and frames fill
+// the chip) and writes the chunk's (count, mean, M2); the merge pass combines a
+// (frame, direction)'s chunks in chunk order with Chan's pairwise formula.  The
+// result does not depend on scheduling.
+#include "safr_internal.h"
+
+namespace safr {
+
+namespace {
+
+struct Moments {
+    float n, mean, m2;
+};
+
+__device__ inline Moments merge(Moments a, Moments b) {
+    const float n = a.n + b.n;
+    if (n == 0.f) return a;
+    const float d = b.mean - a.mean;
+    const float fb = b.n / n;
+    return {n, fmaf(d, fb, a.mean), a.m2 + b.m2 + d * d * a.n * fb};
+}
+
+}  // namespace
+
+int strehl_chunks(int n) { return (n * n + 255) / 256; }
+
+__global__ void __launch_bounds__(256) strehl_part_kernel(StrehlArgs a) {
+    __shared__ float red[3 * 4];
+    const int n = a.n, M = a.M, L = a.L;
+    const int c = blockIdx.x, d = blockIdx.y, f = blockIdx.z;
+    const int mask = M - 1;
+    const int e = c * 256 + threadIdx.x;
+    Moments acc = {0.f, 0.f, 0.f};
+    if (e < n * n && a.pupil[e]) {
+        const float* lay = a.layers + (size_t)f * L * M * M;
+        const float tx = a.dx[d], ty = a.dy[d];
+        const int i = e / n, j = e - (e / n) * n;
+        float corr = 0.f;
+#pragma unroll 3
+        for (int l = 0; l < L; ++l) {
+            const float u = fmaf(a.m[l], (float)i, fmaf(tx, a.hs[l], a.base[l]));
+            const float w = fmaf(a.m[l], (float)j, fmaf(ty, a.hs[l], a.base[l]));
+            const float fu0 = floorf(u), fw0 = floorf(w);
+            const float fu = u - fu0, fw = w - fw0;
+            const int i0 = (int)fu0 & mask, j0 = (int)fw0 & mask;
+            const int i1 = (i0 + 1) & mask, j1 = (j0 + 1) & mask;
+            const float* X = lay + (size_t)l * M * M;
+            const float x00 = X[i0 * M + j0], x01 = X[i0 * M + j1];
+            const float x10 = X[i1 * M + j0], x11 = X[i1 * M + j1];
+            corr += (1.f - fu) * ((1.f - fw) * x00 + fw * x01) + fu * ((1.f - fw) * x10 + fw * x11);
+        }
+        acc = {1.f, a.open_loop[((size_t)f * a.D + d) * (size_t)n * n + e] - corr, 0.f};
+    }
+    for (int o = 1; o < 64; o <<= 1) {
+        const Moments b = {__shfl_xor(acc.n, o, 64), __shfl_xor(acc.mean, o, 64), __shfl_xor(acc.m2, o, 64)};
+        acc = (threadIdx.x & o) ? merge(b, acc) : merge(acc, b);       // both lanes: merge(lower, upper)
+    }
+    const int wave = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0) {
+        red[3 * wave + 0] = acc.n;
+        red[3 * wave + 1] = acc.mean;
+        red[3 * wave + 2] = acc.m2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Moments t = {red[0], red[1], red[2]};
+        for (int w = 1; w < 4; ++w) t = merge(t, Moments{red[3 * w], red[3 * w + 1], red[3 * w + 2]});
+        float* o = a.part + (((size_t)f * a.D + d) * gridDim.x + c) * 3;
+        o[0] = t.n;
+        o[1] = t.mean;
+        o[2] = t.m2;
+    }
+}
+
+__global__ void __launch_bounds__(64) strehl_merge_kernel(StrehlArgs a, int chunks, int count) {
+    const int q = blockIdx.x * 64 + threadIdx.x;       // q = f * D + d
+    if (q >= count) return;
+    const float* p = a.part + (size_t)q * chunks * 3;
+    Moments t = {p[0], p[1], p[2]};
+    for (int c = 1; c < chunks; ++c) t = merge(t, Moments{p[3 * c], p[3 * c + 1], p[3 * c + 2]});
+    const float var = t.n > 0.f ? a.scale2 * (t.m2 / t.n) : 0.f;
+    a.sr[q] = expf(-var);
+    if (a.var) a.var[q] = var;
+}
+
+hipError_t launch_strehl(const StrehlArgs& a, int frames, hipStream_t s) {
+    if (a.M < 2 || (a.M & (a.M - 1)) || a.n < 1 || a.n > a.M || a.D < 1 || a.D > kMaxDirs || frames < 1 ||
+        frames > 65535 || a.L < 1 || a.L > kMaxL || !a.part)
+        return hipErrorInvalidValue;
+    const int chunks = strehl_chunks(a.n);
+    hipLaunchKernelGGL(strehl_part_kernel, dim3(chunks, a.D, frames), dim3(256), 0, s, a);
+    const int count = frames * a.D;
+    hipLaunchKernelGGL(strehl_merge_kernel, dim3((count + 63) / 64), dim3(64), 0, s, a, chunks, count);
+    return hipGetLastError();
+}
+
+}  // namespace safr

@@ -61,6 +61,7 @@ struct safr_plan {
     int gstar[2][kMaxG] = {};
     double galpha[2] = {0.0, 0.0};
     double c_out[kMaxL] = {};
+    double heights[kMaxL] = {};
     size_t bcount[2] = {0, 0};      // complex entries per group (FP64 export layout)
     size_t boff[2] = {0, 0};        // group offsets in B64
     size_t boff32[2] = {0, 0};      // group offsets in B32 (column-block layout, zero padded)
@@ -80,6 +81,8 @@ struct safr_plan {
     unsigned char* pupil = nullptr;
     int* tt_mode = nullptr;
     float4* polc_tab = nullptr;     // [J][L] line-of-sight sampling of the output grids (closed loop)
+    float* strehl_part = nullptr;   // per-chunk moments of the Strehl estimate (grown on demand)
+    size_t strehl_part_floats = 0;
     void* ws_own = nullptr;
     size_t ws_own_bytes = 0;
     void* ws_user = nullptr;
@@ -146,6 +149,7 @@ void free_plan(safr_plan* p) {
     hipFree(p->pupil);
     hipFree(p->tt_mode);
     hipFree(p->polc_tab);
+    hipFree(p->strehl_part);
     hipFree(p->ws_own);
     delete p;
 }
@@ -343,7 +347,10 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
     for (int gi = 0; gi < p->ngroups; ++gi)
         for (int l = 0; l < L; ++l)
             cgrp[gi][l] = p->gkind[gi] == SAFR_LGS ? 1.0 - heights[l] / geo->h_lgs : 1.0;
-    for (int l = 0; l < L; ++l) p->c_out[l] = cgrp[0][l];
+    for (int l = 0; l < L; ++l) {
+        p->c_out[l] = cgrp[0][l];
+        p->heights[l] = heights[l];
+    }
 
     // domain condition c_l Omega_A + alpha_g h_l in c_l Omega_T (Sec. 2); skipped when the
     // data covers the whole periodic grid (n == M)
@@ -713,6 +720,49 @@ safr_status safr_polc(safr_plan* p, int frames, const float* wf, const float* la
     if (frames < 1 || frames > 65535) return fail(SAFR_ERR_ARG, "frames must be in 1..65535");
     if (!std::isfinite(weight)) return fail(SAFR_ERR_ARG, "weight must be finite");
     HIP_TRY(launch_polc(polc_args(p, wf, layers, weight, out), frames, s));
+    return SAFR_OK;
+}
+
+safr_status safr_strehl(safr_plan* p, int frames, int D, const double* dirs, const float* open_loop,
+                        const float* layers, float scale, float* sr, float* var, hipStream_t s) {
+    if (!p || !dirs || !open_loop || !layers || !sr) return fail(SAFR_ERR_ARG, "NULL argument");
+    if (frames < 1 || frames > 65535) return fail(SAFR_ERR_ARG, "frames must be in 1..65535");
+    if (D < 1 || D > kMaxDirs) return fail(SAFR_ERR_ARG, "directions must be in 1..%d", kMaxDirs);
+    if (!std::isfinite(scale)) return fail(SAFR_ERR_ARG, "scale must be finite");
+    StrehlArgs a{};
+    for (int d = 0; d < D; ++d) {
+        if (!std::isfinite(dirs[2 * d]) || !std::isfinite(dirs[2 * d + 1]))
+            return fail(SAFR_ERR_ARG, "direction %d is not finite", d);
+        a.dx[d] = (float)dirs[2 * d];
+        a.dy[d] = (float)dirs[2 * d + 1];
+    }
+    for (int l = 0; l < p->L; ++l) {
+        const double m = 1.0 / p->c_out[l];
+        a.m[l] = (float)m;
+        a.base[l] = (float)(m * (p->p0 - 0.5 * p->M) + 0.5 * p->M);
+        a.hs[l] = (float)(p->heights[l] / (p->c_out[l] * p->pitch));
+    }
+    a.open_loop = open_loop;
+    a.layers = layers;
+    a.sr = sr;
+    a.var = var;
+    a.pupil = p->pupil;
+    a.scale2 = scale * scale;
+    a.n = p->n;
+    a.M = p->M;
+    a.L = p->L;
+    a.D = D;
+    const size_t need = (size_t)frames * D * strehl_chunks(p->n) * 3;
+    if (p->strehl_part_floats < need) {          // grown on demand (synchronises the device once)
+        HIP_TRY(hipStreamSynchronize(s));
+        hipFree(p->strehl_part);
+        p->strehl_part = nullptr;
+        p->strehl_part_floats = 0;
+        HIP_TRY(hipMalloc(&p->strehl_part, need * sizeof(float)));
+        p->strehl_part_floats = need;
+    }
+    a.part = p->strehl_part;
+    HIP_TRY(launch_strehl(a, frames, s));
     return SAFR_OK;
 }
 

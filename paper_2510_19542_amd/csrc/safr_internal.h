@@ -88,6 +88,26 @@ struct PolcArgs {
 };
 hipError_t launch_polc(const PolcArgs& a, int frames, hipStream_t s);
 
+// Strehl estimate (Marechal): residual phase open_loop - A_theta(layers) over the pupil for science
+// directions theta (cone coefficient 1), its piston-removed variance, exp(-variance).
+constexpr int kMaxDirs = 32;
+struct StrehlArgs {
+    const float* open_loop;     // [F][D][n][n]
+    const float* layers;        // [F][L][M][M]
+    float* sr;                  // [F][D]
+    float* var;                 // [F][D] or nullptr
+    const unsigned char* pupil; // [n][n]
+    float dx[kMaxDirs], dy[kMaxDirs];
+    float m[kMaxL];             // 1 / c_l: science lines of sight on the output grids
+    float base[kMaxL];          // m_l (p0 - M/2) + M/2
+    float hs[kMaxL];            // h_l / (c_l pitch): layer pixels per radian of direction
+    float scale2;               // (phase unit -> rad)^2
+    float* part;                // [F][D][chunks][3] per-chunk (count, mean, M2) of the residual
+    int n, M, L, D;
+};
+int strehl_chunks(int n);       // pupil chunks (256 pixels each) per frame and direction
+hipError_t launch_strehl(const StrehlArgs& a, int frames, hipStream_t s);
+
 // BF16 hi/lo split apply on matrix cores (batched path).
 struct MfmaArgs {
     const float2* R;

@@ -32,7 +32,7 @@ EXPORTED = [
     "safr_set_workspace", "safr_plan_info", "safr_export_B", "safr_set_option", "safr_time_stages",
     "safr_autotune", "safr_destroy", "safr_last_error",
     "safr_multi_create", "safr_multi_execute", "safr_multi_autotune", "safr_multi_destroy",
-    "safr_polc", "safr_loop_step",
+    "safr_polc", "safr_loop_step", "safr_strehl",
     # learned filter (bound in learn.py)
     "safr_trainer_create", "safr_trainer_add_frames", "safr_trainer_set_params", "safr_trainer_get_params",
     "safr_trainer_step", "safr_trainer_gradient", "safr_trainer_frames", "safr_trainer_destroy", "safr_mlp_infer",
@@ -109,6 +109,7 @@ def lib() -> ctypes.CDLL:
     L.safr_multi_destroy.restype = None
     L.safr_polc.argtypes = [vp, i, vp, vp, ctypes.c_float, vp, vp]
     L.safr_loop_step.argtypes = [vp, i, vp, vp, ctypes.c_float, vp, vp]
+    L.safr_strehl.argtypes = [vp, i, i, ctypes.POINTER(d), vp, vp, ctypes.c_float, vp, vp, vp]
     for name in EXPORTED[:EXPORTED.index("safr_trainer_create")]:
         if name not in ("safr_destroy", "safr_last_error", "safr_multi_destroy"):
             getattr(L, name).restype = ctypes.c_int
@@ -262,6 +263,14 @@ def safr_loop_step(plan: Plan, frames: int, wavefronts, a_in, gain: float, a_out
     """One closed-loop step: a_out = (1 - gain) a_in + gain * SAFR(POLC(wavefronts, a_in))."""
     _check(lib().safr_loop_step(plan._as_parameter_, int(frames), _ptr(wavefronts), _ptr(a_in), float(gain),
                                 _ptr(a_out), _stream(stream)))
+
+
+def safr_strehl(plan: Plan, frames: int, directions, open_loop, layers, scale: float, sr, var=None, stream=None):
+    """Marechal Strehl ratios sr[f][d] (and residual variances var[f][d], rad^2) in science directions."""
+    dirs = np.ascontiguousarray(np.asarray(directions, dtype=np.float64).reshape(-1, 2))
+    _check(lib().safr_strehl(plan._as_parameter_, int(frames), len(dirs),
+                             dirs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(open_loop), _ptr(layers),
+                             float(scale), _ptr(sr), _ptr(var), _stream(stream)))
 
 
 def safr_plan_info(plan: Plan) -> safr_plan_desc:

@@ -113,3 +113,27 @@ def test_loop_gain_limits():
     assert np.array_equal(O.loop_step(plan, psi, a, 0.0), a)
     full = O.loop_step(plan, psi, a, 1.0)
     assert np.max(np.abs(full - O.reconstruct(plan, O.polc(plan, psi, a)))) <= 1e-13 * np.max(np.abs(full))
+
+
+def test_oracle_closed_loop_raises_the_strehl():
+    # frozen-flow synthetic atmosphere, natural stars; the command computed from the measurement of step t
+    # (taken with the mirror a_t) is applied at step t + 1.  A property of the whole loop, not a pin.
+    import synth
+    geo = synth.preset("C1")
+    plan = O.precompute_geometry(geo)
+    t = np.linspace(-20.0, 20.0, 3) * synth.ARCSEC
+    dirs = np.array([(x, y) for x in t for y in t])
+    sci = geo.replace(stars=[(float(x), float(y), synth.NGS) for x, y in dirs])
+    screens = synth.truth_screens(geo, 0)
+    a = np.zeros((geo.L, geo.M, geo.M))
+    late, open_ = [], []
+    for step in range(25):
+        wf = synth.simulate_wavefronts(geo, screens, step, frozen_flow=True)
+        ol = synth.simulate_wavefronts(sci, screens, step, frozen_flow=True, noise=False)
+        sr, _ = O.strehl(plan, ol, a, dirs, 0.5 / 2.2)
+        sr0, _ = O.strehl(plan, ol, np.zeros_like(a), dirs, 0.5 / 2.2)
+        a = O.loop_step(plan, O.polc(plan, wf, a, -1.0), a, 0.5)
+        if step >= 15:
+            late.append(sr)
+            open_.append(sr0)
+    assert np.mean(late) > 0.3 and np.mean(late) > 10.0 * np.mean(open_)
