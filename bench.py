@@ -174,6 +174,31 @@ def run_loop(S, torch, plan, geo, pool, calls):
     return res
 
 
+def run_recompute(S, torch, reps=3):
+    """Soft-real-time refresh: wall time of the whole precomputation (Alg. 2) when alpha, the layer
+    weights or the asterism change, against the loop period."""
+    import numpy as np
+    import synth
+    res = {"what": "safr_precompute wall time (A_n, FP64 Jacobi SVD per frequency, filter, B in FP64/FP32, "
+                   "natural-star basis images, BF16 tiles); every change of alpha, gamma or the asterism "
+                   "takes one", "loop_period_ms_at_1khz": 1.0}
+    for name in ("C2", "C1", "C5-Mid"):
+        geo = synth.preset(name)
+        variants = [geo, geo.replace(alpha=geo.alpha * 2.0), geo.replace(weights=np.roll(geo.weights, 1))]
+        ms = []
+        for r in range(reps):
+            g = variants[r % len(variants)]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan = S.precompute_geometry(g)
+            torch.cuda.synchronize()
+            ms.append((time.perf_counter() - t0) * 1e3)
+            plan.close()
+        res[name] = {"ms": [round(v, 2) for v in ms], "median_ms": round(float(np.median(ms)), 2),
+                     "loop_periods_at_1khz": round(float(np.median(ms)) / 1.0, 1)}
+    return res
+
+
 _WS = {}
 
 
@@ -440,6 +465,8 @@ def main():
                               "stage_ms": {k: round(v, 6) for k, v in zip(names, stage1_ms)}}
     print("bench: closed-loop step (Alg. 3)", file=sys.stderr, flush=True)
     result["closed_loop"] = run_loop(S, torch, plan1, geo, pool, args.single_calls)
+    print("bench: precompute refresh", file=sys.stderr, flush=True)
+    result["recompute"] = run_recompute(S, torch)
     if not args.no_extras:
         print("bench: 1024-frame batches (C1 geometry)", file=sys.stderr, flush=True)
         result["c3_batched_1024"] = run_c3(S, torch, stream)

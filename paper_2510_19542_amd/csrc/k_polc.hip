@@ -10,8 +10,10 @@
 
 namespace safr {
 
+// L layers as a compile-time count: the 4 L samples of a pixel are all issued before any is used
+template <int L>
 __global__ void __launch_bounds__(256) polc_kernel(PolcArgs a) {
-    const int n = a.n, M = a.M, L = a.L;
+    const int n = a.n, M = a.M;
     const int g = blockIdx.y, f = blockIdx.z;
     const int e = blockIdx.x * 256 + threadIdx.x;
     if (e >= n * n) return;
@@ -23,7 +25,7 @@ __global__ void __launch_bounds__(256) polc_kernel(PolcArgs a) {
         const float* lay = a.layers + (size_t)f * L * M * M;
         const float4* tab = a.tab + (size_t)g * L;
         float acc = 0.f;
-#pragma unroll 3
+#pragma unroll
         for (int l = 0; l < L; ++l) {
             const float4 t = tab[l];
             const float u = fmaf(t.x, (float)i, t.y);
@@ -42,11 +44,28 @@ __global__ void __launch_bounds__(256) polc_kernel(PolcArgs a) {
     a.out[o] = v;
 }
 
-hipError_t launch_polc(const PolcArgs& a, int frames, hipStream_t s) {
-    if (a.M < 2 || (a.M & (a.M - 1)) || a.n < 1 || a.n > a.M || frames < 1 || frames > 65535) return hipErrorInvalidValue;
+namespace {
+
+template <int L>
+hipError_t launch_polc_l(const PolcArgs& a, int frames, hipStream_t s) {
+    if (a.L != L) return launch_polc_l<L - 1>(a, frames, s);
     const int blocks = (a.n * a.n + 255) / 256;
-    hipLaunchKernelGGL(polc_kernel, dim3(blocks, a.J, frames), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(polc_kernel<L>, dim3(blocks, a.J, frames), dim3(256), 0, s, a);
     return hipGetLastError();
+}
+
+template <>
+hipError_t launch_polc_l<0>(const PolcArgs&, int, hipStream_t) {
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_polc(const PolcArgs& a, int frames, hipStream_t s) {
+    if (a.M < 2 || (a.M & (a.M - 1)) || a.n < 1 || a.n > a.M || frames < 1 || frames > 65535 || a.L < 1 ||
+        a.L > kMaxL)
+        return hipErrorInvalidValue;
+    return launch_polc_l<kMaxL>(a, frames, s);
 }
 
 }  // namespace safr

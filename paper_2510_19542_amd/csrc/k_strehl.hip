@@ -10,8 +10,8 @@
 // Two launches: the partial pass gives every pupil chunk of 256 pixels its own
 // block (one pixel per thread, so the chunks of all directions and frames fill
 // the chip) and writes the chunk's (count, mean, M2); the merge pass combines a
-// (frame, direction)'s chunks in chunk order with Chan's pairwise formula.  The
-// result does not depend on scheduling.
+// (frame, direction)'s chunks with Chan's pairwise formula in an order fixed by the
+// chunk count, so the result does not depend on scheduling.
 #include "safr_internal.h"
 
 namespace safr {
@@ -34,9 +34,10 @@ __device__ inline Moments merge(Moments a, Moments b) {
 
 int strehl_chunks(int n) { return (n * n + 255) / 256; }
 
+template <int L>
 __global__ void __launch_bounds__(256) strehl_part_kernel(StrehlArgs a) {
     __shared__ float red[3 * 4];
-    const int n = a.n, M = a.M, L = a.L;
+    const int n = a.n, M = a.M;
     const int c = blockIdx.x, d = blockIdx.y, f = blockIdx.z;
     const int mask = M - 1;
     const int e = c * 256 + threadIdx.x;
@@ -46,7 +47,7 @@ __global__ void __launch_bounds__(256) strehl_part_kernel(StrehlArgs a) {
         const float tx = a.dx[d], ty = a.dy[d];
         const int i = e / n, j = e - (e / n) * n;
         float corr = 0.f;
-#pragma unroll 3
+#pragma unroll
         for (int l = 0; l < L; ++l) {
             const float u = fmaf(a.m[l], (float)i, fmaf(tx, a.hs[l], a.base[l]));
             const float w = fmaf(a.m[l], (float)j, fmaf(ty, a.hs[l], a.base[l]));
@@ -82,25 +83,49 @@ __global__ void __launch_bounds__(256) strehl_part_kernel(StrehlArgs a) {
     }
 }
 
-__global__ void __launch_bounds__(64) strehl_merge_kernel(StrehlArgs a, int chunks, int count) {
-    const int q = blockIdx.x * 64 + threadIdx.x;       // q = f * D + d
-    if (q >= count) return;
+// one wave per (frame, direction): lane t merges chunks t, t + 64, ... in order, then the lanes merge
+// pairwise (lower lane first), so the result is fixed by the chunk count alone
+__global__ void __launch_bounds__(64) strehl_merge_kernel(StrehlArgs a, int chunks) {
+    const int q = blockIdx.x;                          // q = f * D + d
+    const int t = threadIdx.x;
     const float* p = a.part + (size_t)q * chunks * 3;
-    Moments t = {p[0], p[1], p[2]};
-    for (int c = 1; c < chunks; ++c) t = merge(t, Moments{p[3 * c], p[3 * c + 1], p[3 * c + 2]});
-    const float var = t.n > 0.f ? a.scale2 * (t.m2 / t.n) : 0.f;
-    a.sr[q] = expf(-var);
-    if (a.var) a.var[q] = var;
+    Moments acc = {0.f, 0.f, 0.f};
+    for (int c = t; c < chunks; c += 64) acc = merge(acc, Moments{p[3 * c], p[3 * c + 1], p[3 * c + 2]});
+    for (int o = 1; o < 64; o <<= 1) {
+        const Moments b = {__shfl_xor(acc.n, o, 64), __shfl_xor(acc.mean, o, 64), __shfl_xor(acc.m2, o, 64)};
+        acc = (t & o) ? merge(b, acc) : merge(acc, b);
+    }
+    if (t == 0) {
+        const float var = acc.n > 0.f ? a.scale2 * (acc.m2 / acc.n) : 0.f;
+        a.sr[q] = expf(-var);
+        if (a.var) a.var[q] = var;
+    }
 }
+
+namespace {
+
+template <int L>
+hipError_t launch_part_l(const StrehlArgs& a, int chunks, int frames, hipStream_t s) {
+    if (a.L != L) return launch_part_l<L - 1>(a, chunks, frames, s);
+    hipLaunchKernelGGL(strehl_part_kernel<L>, dim3(chunks, a.D, frames), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <>
+hipError_t launch_part_l<0>(const StrehlArgs&, int, int, hipStream_t) {
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
 
 hipError_t launch_strehl(const StrehlArgs& a, int frames, hipStream_t s) {
     if (a.M < 2 || (a.M & (a.M - 1)) || a.n < 1 || a.n > a.M || a.D < 1 || a.D > kMaxDirs || frames < 1 ||
         frames > 65535 || a.L < 1 || a.L > kMaxL || !a.part)
         return hipErrorInvalidValue;
     const int chunks = strehl_chunks(a.n);
-    hipLaunchKernelGGL(strehl_part_kernel, dim3(chunks, a.D, frames), dim3(256), 0, s, a);
-    const int count = frames * a.D;
-    hipLaunchKernelGGL(strehl_merge_kernel, dim3((count + 63) / 64), dim3(64), 0, s, a, chunks, count);
+    const hipError_t e = launch_part_l<kMaxL>(a, chunks, frames, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(strehl_merge_kernel, dim3(frames * a.D), dim3(64), 0, s, a, chunks);
     return hipGetLastError();
 }
 

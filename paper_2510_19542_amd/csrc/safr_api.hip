@@ -185,10 +185,13 @@ void tt_transforms(const std::vector<unsigned char>& pup, int n, int M, int p0, 
                    std::vector<double2>& Y) {
     const int Kh = M / 2 + 1;
     const double half = 0.5 * (n - 1);
-    auto w = [M](long e) {
-        const double ang = -2.0 * M_PI * (double)(e % M) / M;
-        return std::make_pair(std::cos(ang), std::sin(ang));
-    };
+    // exp(-2 pi i e / M) for e = 0..M-1, indexed by the exponent reduced mod M
+    std::vector<std::pair<double, double>> tw(M);
+    for (int e = 0; e < M; ++e) {
+        const double ang = -2.0 * M_PI * (double)e / M;
+        tw[e] = std::make_pair(std::cos(ang), std::sin(ang));
+    }
+    auto w = [M, &tw](long e) { return tw[e % M]; };
     // row sums at each k: rx = sum_q mask e^{-2 pi i k (p0+q)/M}, ry = sum_q (q - half) mask e^{...}
     std::vector<double> rxr((size_t)n * Kh), rxi((size_t)n * Kh), ryr((size_t)n * Kh), ryi((size_t)n * Kh);
     for (int p = 0; p < n; ++p)
