@@ -180,10 +180,17 @@ safr_status safr_export_B(const safr_plan* p, int group, double* host, size_t co
  *   SAFR_OPT_COL_TOGETHER frames the FP32 column pass transforms together (1, 2 or 4; B is
  *                        read once for them; compile-time shapes only, others use 1);
  *   SAFR_OPT_COL_PREFETCH 1 = the column pass uses its compile-time kernel when the shape
- *                        has one (default), 0 = always the generic kernel. */
+ *                        has one (default), 0 = always the generic kernel;
+ *   SAFR_OPT_CHECK_FINITE 1 = debug mode: safr_reconstruct(_batched) and safr_loop_step first scan
+ *                        their inputs (wavefronts at pupil pixels, the loop's commands everywhere)
+ *                        for non-finite values, synchronise the stream, and return SAFR_ERR_NUMERIC
+ *                        naming the first such frame without launching the reconstruction; no graph
+ *                        is used meanwhile.  Default: 1 if the environment variable SAFR_CHECK_FINITE
+ *                        is "1" when the plan is made, else 0 (non-finite inputs then propagate
+ *                        within their own frame only). */
 enum { SAFR_OPT_GRAPH = 0, SAFR_OPT_ROW_TEAMS = 1, SAFR_OPT_OUT_ROWS = 2, SAFR_OPT_MFMA_FRAMES = 3,
        SAFR_OPT_COL_FRAMES = 4, SAFR_OPT_COL_PREFETCH = 5, SAFR_OPT_OUT_FRAMES = 6,
-       SAFR_OPT_COL_TOGETHER = 7 };
+       SAFR_OPT_COL_TOGETHER = 7, SAFR_OPT_CHECK_FINITE = 8 };
 safr_status safr_set_option(safr_plan* p, int option, int value);
 
 /* Measures the three kernels of the hard-real-time step (row pass, column pass

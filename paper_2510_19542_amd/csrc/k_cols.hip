@@ -74,7 +74,7 @@ __device__ __forceinline__ bool xcd_work(int nwork, int& w) {
 
 }  // namespace
 
-template <int M, int NF, int GC, int LC, int MODE>
+template <int M, int NF, int GC, int LC, int MODE, int LSPLIT = 1>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 2 : 3))) void cols_kernel(ColArgs a) {
     using S = FftShape<M>;
     constexpr int T = S::T, N1 = S::N1, NTEAM = 256 / T, TL = team_lds<M>() + 2;   // slot stride, 4 banks apart
@@ -94,7 +94,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
     const int kblocks = (Kh + CPW - 1) / CPW;
     const int runs = (a.frames + a.frames_per_block - 1) / a.frames_per_block;
     int w;
-    if (!xcd_work(kblocks * runs, w)) return;                  // the whole block leaves before any barrier
+    if (!xcd_work(kblocks * runs * LSPLIT, w)) return;         // the whole block leaves before any barrier
+    // layer split (launches with fewer blocks than CUs): the LSPLIT blocks of a column each transform all
+    // stars and apply and invert LB of the layers, starting at l0
+    constexpr int LB = FIX ? (LC + LSPLIT - 1) / LSPLIT : 1;
+    const int ls = w % LSPLIT;
+    w /= LSPLIT;
+    const int l0 = ls * LB;
+    const int nl = FIX ? min(LB, LC - l0) : L;                 // layers of this block
     const int kb = w / runs, run = w - kb * runs;
     const int fbeg = run * a.frames_per_block;
     const int fend = min(a.frames, fbeg + a.frames_per_block);
@@ -191,14 +198,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
                 // B of layer l + 1 is requested before the products of layer l
                 float2 bv[GC], bn[GC];
 #pragma unroll
-                for (int g = 0; g < GC; ++g) bn[g] = load_b(Brs, tid * 8, g);
+                for (int g = 0; g < GC; ++g) bn[g] = load_b(Brs, tid * 8, l0 * GC + g);
 #pragma unroll
-                for (int l = 0; l < LC; ++l) {
+                for (int l = 0; l < LB; ++l) {
+                    if (LSPLIT > 1 && l >= nl) break;
 #pragma unroll
                     for (int g = 0; g < GC; ++g) bv[g] = bn[g];
-                    if (l + 1 < LC) {
+                    if (l + 1 < LB && (LSPLIT == 1 || l + 1 < nl)) {
 #pragma unroll
-                        for (int g = 0; g < GC; ++g) bn[g] = load_b(Brs, tid * 8, (l + 1) * GC + g);
+                        for (int g = 0; g < GC; ++g) bn[g] = load_b(Brs, tid * 8, (l0 + l + 1) * GC + g);
                     }
 #pragma unroll
                     for (int fl = 0; fl < NF; ++fl) {
@@ -228,11 +236,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
         __syncthreads();
 
         // 3. inverse column transforms of the layer slots, in place, written to C
-        const int itasks = CPW * NF * L;
+        const int itasks = CPW * NF * nl;
         for (int base = 0; base < itasks; base += NTEAM) {
             const int task = base + team;
-            const int cc = task / (NF * L), rem = task - cc * (NF * L);
-            const int fl = rem / L, l = rem - fl * L;
+            const int cc = task / (NF * nl), rem = task - cc * (NF * nl);
+            const int fl = rem / nl, l = rem - fl * nl;
             const int kk = kb * CPW + cc, f = f0 + fl;
             const bool active = task < itasks;
             float2* sl = active ? slot(cc, fl, LS + l) : slots;
@@ -248,7 +256,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
                 const int nfr = min(NF, fend - f0);
                 const size_t cfr = (size_t)L * Kh * M;        // float2 per frame of C
                 const __amdgpu_buffer_rsrc_t cr = block_rsrc(a.C + c_index(f0, 0, L, M, 0, 0), (unsigned)(nfr * cfr * 8));
-                const int base = (int)(c_index(fl, l, L, M, kk, 0));
+                const int base = (int)(c_index(fl, l0 + l, L, M, kk, 0));
                 fft_pass2<M, +1>(t, sl, [&](int p, float2 v) {
                     store_f2(cr, (base + (p >> 3) * (Kh * 8) + (p & 7)) * 8, v);
                 });
@@ -267,12 +275,13 @@ size_t cols_lds_bytes(int M, int G, int L, int nf, bool fixed) {
 namespace {
 
 template <class K>
-hipError_t launch_cols_kernel(K kernel, int M, int nf, bool fixed, const ColArgs& a, int frames, hipStream_t s) {
+hipError_t launch_cols_kernel(K kernel, int M, int nf, bool fixed, const ColArgs& a, int frames, hipStream_t s,
+                              int lsplit = 1) {
     const int CPW = 256 / M, Kh = M / 2 + 1;
     const size_t lds = cols_lds_bytes(M, a.grp.G, a.L, nf, fixed);
     const int kblocks = (Kh + CPW - 1) / CPW;
     const int runs = (frames + a.frames_per_block - 1) / a.frames_per_block;
-    const int nblk = (kblocks * runs + 7) / 8 * 8;
+    const int nblk = (kblocks * runs * lsplit + 7) / 8 * 8;
     allow_large_lds(reinterpret_cast<const void*>(kernel));
     hipLaunchKernelGGL(kernel, dim3(nblk), dim3(256), lds, s, a);
     return hipGetLastError();
@@ -286,8 +295,15 @@ hipError_t launch_cols_kernel(K kernel, int M, int nf, bool fixed, const ColArgs
     X(64, 2, 4, 0)           \
     X(64, 3, 4, 0)
 
+// fewer column blocks than CUs (one-frame calls at M = 256): split the layers of each column over two blocks
+constexpr int kCUs = 256;
+
 template <int M, int G, int L, int MODE>
 hipError_t launch_fixed(const ColArgs& a, int nf, int frames, hipStream_t s) {
+    const int CPW = 256 / M, kblocks = (M / 2 + 1 + CPW - 1) / CPW;
+    const int runs = (frames + a.frames_per_block - 1) / a.frames_per_block;
+    if (nf == 1 && L >= 2 && kblocks * runs * 2 <= kCUs + kCUs / 8)
+        return launch_cols_kernel(&cols_kernel<M, 1, G, L, MODE, 2>, M, 1, true, a, frames, s, 2);
     switch (nf) {
         case 1: return launch_cols_kernel(&cols_kernel<M, 1, G, L, MODE>, M, 1, true, a, frames, s);
         case 2: return launch_cols_kernel(&cols_kernel<M, 2, G, L, MODE>, M, 2, true, a, frames, s);

@@ -4,9 +4,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -90,6 +92,8 @@ struct safr_plan {
     // tuning
     int row_teams = 0, out_rows = 0, out_frames = 1, mfma_frames = 16, col_frames = 1, col_nf = 1, col_prefetch = 1;
     int use_graph = 0;
+    int check_finite = 0;           // debug: scan inputs for non-finite values first (synchronises)
+    int* dfirst = nullptr;          // first non-finite frame found by the check
     // graph cache
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
@@ -150,6 +154,7 @@ void free_plan(safr_plan* p) {
     hipFree(p->tt_mode);
     hipFree(p->polc_tab);
     hipFree(p->strehl_part);
+    hipFree(p->dfirst);
     hipFree(p->ws_own);
     delete p;
 }
@@ -247,6 +252,21 @@ PolcArgs polc_args(const safr_plan* p, const float* wf, const float* layers, flo
     a.J = p->J;
     a.L = p->L;
     return a;
+}
+
+// Debug input check (SAFR_OPT_CHECK_FINITE): wavefronts at pupil pixels and, when given, layer-shaped
+// inputs everywhere; synchronises the stream and names the first frame with a non-finite value.
+safr_status check_inputs(safr_plan* p, int frames, const float* wf, const float* layers, hipStream_t s) {
+    const int none = INT_MAX;
+    HIP_TRY(hipMemcpyAsync(p->dfirst, &none, sizeof(int), hipMemcpyHostToDevice, s));
+    const int pix = p->n * p->n;
+    HIP_TRY(launch_finite_check(wf, p->pupil, pix, p->J * pix, frames, p->dfirst, s));
+    if (layers) HIP_TRY(launch_finite_check(layers, nullptr, 1, p->L * p->M * p->M, frames, p->dfirst, s));
+    int first = none;
+    HIP_TRY(hipMemcpyAsync(&first, p->dfirst, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (first != none) return fail(SAFR_ERR_NUMERIC, "non-finite input in frame %d", first);
+    return SAFR_OK;
 }
 
 // Alg. 3 without its wavefront reconstruction: POLC into the workspace, the reconstruction with
@@ -587,6 +607,11 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
         }
         p->ws_own_bytes = ws_bytes(p, 1);
         PC_TRY(hipMalloc(&p->ws_own, p->ws_own_bytes));
+        PC_TRY(hipMalloc(&p->dfirst, sizeof(int)));
+        {
+            const char* env = std::getenv("SAFR_CHECK_FINITE");
+            p->check_finite = env && env[0] == '1';
+        }
         PC_TRY(hipStreamSynchronize(stream));
 #undef PC_TRY
     } while (0);
@@ -681,6 +706,11 @@ safr_status safr_reconstruct_batched(safr_plan* p, int frames, const float* wf, 
     if (p->ws_user && p->ws_user_bytes >= need) ws = p->ws_user;
     else if (p->ws_own_bytes >= need) ws = p->ws_own;
     else return fail(SAFR_ERR_STATE, "workspace of %zu bytes needed for %d frames", need, frames);
+    if (p->check_finite) {
+        const safr_status cs = check_inputs(p, frames, wf, nullptr, s);
+        if (cs != SAFR_OK) return cs;
+        return launch_all(p, frames, wf, out, precision, ws, s);
+    }
 
     if (p->use_graph && s != nullptr) {
         const bool hit = p->gexec && p->g_frames == frames && p->g_prec == precision && p->g_wf == wf &&
@@ -779,6 +809,11 @@ safr_status safr_loop_step(safr_plan* p, int frames, const float* wf, const floa
     if (p->ws_user && p->ws_user_bytes >= need) ws = p->ws_user;
     else if (p->ws_own_bytes >= need) ws = p->ws_own;
     else return fail(SAFR_ERR_STATE, "workspace of %zu bytes needed for %d frames", need, frames);
+    if (p->check_finite) {
+        const safr_status cs = check_inputs(p, frames, wf, a_in, s);
+        if (cs != SAFR_OK) return cs;
+        return launch_loop(p, frames, wf, a_in, gain, a_out, ws, s);
+    }
 
     if (p->use_graph && s != nullptr) {
         const bool hit = p->lexec && p->l_frames == frames && p->l_gain == gain && p->l_wf == wf &&
@@ -1145,6 +1180,7 @@ safr_status safr_set_option(safr_plan* p, int option, int value) {
                 return fail(SAFR_ERR_ARG, "%d frames together need more than 160 KiB of LDS", value);
             p->col_nf = value;
             return SAFR_OK;
+        case 8: p->check_finite = value != 0; return SAFR_OK;
         default: return fail(SAFR_ERR_ARG, "unknown option %d", option);
     }
 }

@@ -105,7 +105,12 @@ struct StrehlArgs {
     float* part;                // [F][D][chunks][3] per-chunk (count, mean, M2) of the residual
     int n, M, L, D;
 };
-int strehl_chunks(int n);       // pupil chunks (256 pixels each) per frame and direction
+int strehl_chunks(int n);
+
+// Debug input check: *first = min(*first, frame) for every frame with a non-finite value (pupil != nullptr:
+// only where pupil[e % pix] is set; per_frame a multiple of pix).
+hipError_t launch_finite_check(const float* x, const unsigned char* pupil, int pix, int per_frame, int frames,
+                               int* first, hipStream_t s);       // pupil chunks (256 pixels each) per frame and direction
 hipError_t launch_strehl(const StrehlArgs& a, int frames, hipStream_t s);
 
 // BF16 hi/lo split apply on matrix cores (batched path).

@@ -174,6 +174,52 @@ def test_nan_frame_stays_in_its_frame():
         assert torch.equal(dirty[i], clean[i])
 
 
+def test_check_finite_option_names_the_frame():
+    torch = _torch()
+    S = _lib()
+    geo = _small(32, 17, (1, 1, 0, 0), L=2, seed=12)
+    plan = S.precompute_geometry(geo)
+    wf = torch.from_numpy(synth.random_wavefronts(geo, 4)).cuda()
+    clean = S.reconstruct(plan, wf)
+    torch.cuda.synchronize()
+    pup = geo.pupil().astype(bool)
+    outside = np.argwhere(~pup)
+    S.safr_set_option(plan, S.SAFR_OPT_CHECK_FINITE, 1)
+    try:
+        # a non-finite value outside the pupil is ignored like any value there
+        wf2 = wf.clone()
+        wf2[1, 0, int(outside[0][0]), int(outside[0][1])] = float("inf")
+        assert torch.equal(S.reconstruct(plan, wf2), clean)
+        wf2[3, 2, 8, 8] = float("nan")
+        wf2[2, 1, 8, 9] = float("-inf")
+        out = torch.full((4, geo.L, geo.M, geo.M), 7.0, device="cuda")
+        ws = torch.empty(S.safr_workspace_size(plan, 4) + 256, dtype=torch.uint8, device="cuda")
+        S.safr_set_workspace(plan, (ws.data_ptr() + 255) & ~255, S.safr_workspace_size(plan, 4))
+        with pytest.raises(S.SafrError) as e:
+            S.safr_reconstruct_batched(plan, 4, wf2, out)
+        assert e.value.status == S.SAFR_ERR_NUMERIC and "frame 2" in str(e.value)
+        assert bool((out == 7.0).all())                     # nothing was launched
+        # the loop step also checks its commands
+        a = torch.zeros((4, geo.L, geo.M, geo.M), device="cuda")
+        a[3, 1, 0, 0] = float("nan")
+        with pytest.raises(S.SafrError) as e:
+            S.safr_loop_step(plan, 4, wf, a, 0.5, a)
+        assert e.value.status == S.SAFR_ERR_NUMERIC and "frame 3" in str(e.value)
+        S.safr_set_workspace(plan, 0, 0)
+    finally:
+        S.safr_set_option(plan, S.SAFR_OPT_CHECK_FINITE, 0)
+    # the environment variable sets the default of new plans
+    import os
+    os.environ["SAFR_CHECK_FINITE"] = "1"
+    try:
+        plan2 = S.precompute_geometry(geo)
+    finally:
+        del os.environ["SAFR_CHECK_FINITE"]
+    with pytest.raises(S.SafrError) as e:
+        S.reconstruct(plan2, wf2[3])
+    assert e.value.status == S.SAFR_ERR_NUMERIC
+
+
 def test_deterministic():
     torch = _torch()
     S = _lib()
