@@ -11,6 +11,9 @@
 // c DFT2(y mask), with the two transforms precomputed in FP64 per plan.  The
 // natural stars are added in the output pass.
 //
+// Only the columns k < M/2 are processed: B vanishes on the Nyquist column, whose
+// layer spectra the output pass takes as zero.
+//
 // One block of 256 threads owns CPW = 256 / M columns and a run of frames,
 // transformed NF frames at a time.  LDS holds one slot of team_lds<M>() float2
 // per (column, frame, star-or-layer); a slot is in turn a transform's exchange
@@ -91,7 +94,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
     float2* slots = smem + M;                                  // [CPW][NF][SPF][TL]
     float2* coef = slots + (size_t)CPW * NF * SPF * TL;        // [NF][G]
 
-    const int kblocks = (Kh + CPW - 1) / CPW;
+    // columns k < M/2 only: B vanishes on the Nyquist column k = M/2, so its layer spectra are zero and
+    // the output pass takes them as such without reading C there
+    constexpr int KC = M / 2;
+    const int kblocks = KC / CPW;
     const int runs = (a.frames + a.frames_per_block - 1) / a.frames_per_block;
     int w;
     if (!xcd_work(kblocks * runs * LSPLIT, w)) return;         // the whole block leaves before any barrier
@@ -108,7 +114,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
     const int tid = threadIdx.x, team = tid / T, t = tid % T;
     const int c = tid / M, j = tid % M;                        // apply: column in block, frequency
     const int k = kb * CPW + c;
-    const bool kvalid = k < Kh;
+    const bool kvalid = k < KC;
     const GroupArgs& gr = a.grp;
     auto slot = [&](int cc, int f, int s) { return slots + ((size_t)(cc * NF + f) * SPF + s) * TL; };
 
@@ -123,7 +129,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
         const int cc = task / (NF * G), rem = task - cc * (NF * G);
         const int fl = rem / G, g = rem - fl * G;
         const int kk = kb * CPW + cc, f = f0 + fl;
-        const bool ok = task < ftasks && kk < Kh && f < fend;
+        const bool ok = task < ftasks && kk < KC && f < fend;
         const int nfr = min(NF, fend - f0);
         const __amdgpu_buffer_rsrc_t rr = block_rsrc(a.R + (size_t)f0 * fstride, (unsigned)(nfr * fstride * 8));
         const int colb = ((fl * a.J + gr.star[g]) * Kh + kk) * a.n;
@@ -180,6 +186,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
             __syncthreads();
             if (active) fft_pass2_regs<M, -1>(t, z, [&](int jj, float2 v) { sl[jj] = v; });
         }
+        // B of the block's first two layers, requested before the barrier; later layers two ahead of use
+        constexpr int BD = 3;                                   // B buffers in flight (prefetch distance 2)
+        float2 bq[BD][FIX ? GC : 1];
+        if constexpr (FIX) {
+            if (kvalid) {
+#pragma unroll
+                for (int q = 0; q < BD - 1; ++q) {
+                    if (q < LB && (LSPLIT == 1 || q < nl)) {
+#pragma unroll
+                        for (int g = 0; g < GC; ++g) bq[q][g] = load_b(Brs, tid * 8, (l0 + q) * GC + g);
+                    }
+                }
+            }
+        }
         // tip/tilt plane coefficients of this iteration's frames (used by the apply, after the barrier)
         if (MODE != 0) plane_finish<PMAX>(pa, star_of, part, a.tt_b, a.tt_c, coef);
         __syncthreads();
@@ -195,18 +215,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
                         const float2 d = slot(c, fl, g)[j];
                         dv[fl][g] = MODE != 0 ? csub(d, plane_value(coef[fl * GC + g], xh, yh)) : d;
                     }
-                // B of layer l + 1 is requested before the products of layer l
-                float2 bv[GC], bn[GC];
-#pragma unroll
-                for (int g = 0; g < GC; ++g) bn[g] = load_b(Brs, tid * 8, l0 * GC + g);
+                // B of layer l + 2 is requested before the products of layer l
 #pragma unroll
                 for (int l = 0; l < LB; ++l) {
                     if (LSPLIT > 1 && l >= nl) break;
+                    const float2* bv = bq[l % BD];
+                    if (l + BD - 1 < LB && (LSPLIT == 1 || l + BD - 1 < nl)) {
 #pragma unroll
-                    for (int g = 0; g < GC; ++g) bv[g] = bn[g];
-                    if (l + 1 < LB && (LSPLIT == 1 || l + 1 < nl)) {
-#pragma unroll
-                        for (int g = 0; g < GC; ++g) bn[g] = load_b(Brs, tid * 8, (l0 + l + 1) * GC + g);
+                        for (int g = 0; g < GC; ++g) bq[(l + BD - 1) % BD][g] = load_b(Brs, tid * 8, (l0 + l + BD - 1) * GC + g);
                     }
 #pragma unroll
                     for (int fl = 0; fl < NF; ++fl) {
@@ -252,7 +268,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
             __syncthreads();
             if (active) fft_pass1_regs<M, +1>(t, sl, tws, x);
             __syncthreads();
-            if (active && kk < Kh && f < fend) {
+            if (active && kk < KC && f < fend) {
                 const int nfr = min(NF, fend - f0);
                 const size_t cfr = (size_t)L * Kh * M;        // float2 per frame of C
                 const __amdgpu_buffer_rsrc_t cr = block_rsrc(a.C + c_index(f0, 0, L, M, 0, 0), (unsigned)(nfr * cfr * 8));
@@ -277,9 +293,9 @@ namespace {
 template <class K>
 hipError_t launch_cols_kernel(K kernel, int M, int nf, bool fixed, const ColArgs& a, int frames, hipStream_t s,
                               int lsplit = 1) {
-    const int CPW = 256 / M, Kh = M / 2 + 1;
+    const int CPW = 256 / M;
     const size_t lds = cols_lds_bytes(M, a.grp.G, a.L, nf, fixed);
-    const int kblocks = (Kh + CPW - 1) / CPW;
+    const int kblocks = (M / 2) / CPW;                       // the Nyquist column is not transformed
     const int runs = (frames + a.frames_per_block - 1) / a.frames_per_block;
     const int nblk = (kblocks * runs * lsplit + 7) / 8 * 8;
     allow_large_lds(reinterpret_cast<const void*>(kernel));
@@ -300,7 +316,7 @@ constexpr int kCUs = 256;
 
 template <int M, int G, int L, int MODE>
 hipError_t launch_fixed(const ColArgs& a, int nf, int frames, hipStream_t s) {
-    const int CPW = 256 / M, kblocks = (M / 2 + 1 + CPW - 1) / CPW;
+    const int CPW = 256 / M, kblocks = (M / 2) / CPW;
     const int runs = (frames + a.frames_per_block - 1) / a.frames_per_block;
     if (nf == 1 && L >= 2 && kblocks * runs * 2 <= kCUs + kCUs / 8)
         return launch_cols_kernel(&cols_kernel<M, 1, G, L, MODE, 2>, M, 1, true, a, frames, s, 2);

@@ -207,7 +207,7 @@ template <int M, int NF>
 hipError_t launch_mfma_t(const MfmaArgs& a, int frames, hipStream_t s) {
     const size_t lds = mfma_lds_bytes(M, NF, a.grp.G, a.L);
     allow_large_lds(reinterpret_cast<const void*>(&cols_mfma_kernel<M, NF>));
-    const dim3 grid(M / 2 + 1, 1, (frames + NF - 1) / NF);
+    const dim3 grid(M / 2, 1, (frames + NF - 1) / NF);     // the Nyquist column (B = 0) is left out
     hipLaunchKernelGGL((cols_mfma_kernel<M, NF>), grid, dim3(256), lds, s, a);
     return hipGetLastError();
 }

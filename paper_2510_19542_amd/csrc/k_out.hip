@@ -139,7 +139,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void o
             for (int n1 = 0; n1 < S::N1; ++n1) {
                 const int q = S::N2 * n1 + t;
                 float2 z;
-                if (q == 0 || q == M / 2) {
+                if (q == M / 2) {
+                    z = make_float2(0.f, 0.f);      // Nyquist column: B = 0 there, C is not written
+                } else if (q == 0) {
                     z = make_float2(A[q].x, B[q].x);
                 } else if (q < M / 2) {
                     const float2 u = A[q], w = B[q];
