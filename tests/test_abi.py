@@ -68,3 +68,36 @@ def test_validation_errors(kw, code):
         _pre(S, **kw)
     assert e.value.status == code
     assert len(S.safr_last_error()) > 0
+
+
+def _c_layout(tmp_path, structs):
+    """sizeof and offsetof of every field, as the C compiler lays out the header's structs."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "safr.h"', "int main(void) {"]
+    for name, fields in structs.items():
+        lines.append(f'    printf("{name} %zu\\n", sizeof({name}));')
+        for f in fields:
+            lines.append(f'    printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    r = subprocess.run([gcc, "-std=c99", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+                        "-I", "/opt/rocm/include", str(src), "-o", str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    return {k: int(v) for k, v in (line.split() for line in out.splitlines())}
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    from paper_2510_19542_amd import safr as S
+    structs = {"safr_star": S.safr_star, "safr_geometry": S.safr_geometry, "safr_plan_desc": S.safr_plan_desc}
+    c = _c_layout(tmp_path, {n: [f for f, _ in t._fields_] for n, t in structs.items()})
+    for name, t in structs.items():
+        assert ctypes.sizeof(t) == c[name], name
+        for f, _ in t._fields_:
+            assert getattr(t, f).offset == c[f"{name}.{f}"], (name, f)
