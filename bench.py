@@ -180,8 +180,9 @@ def run_recompute(S, torch, reps=3):
     import numpy as np
     import synth
     res = {"what": "safr_precompute wall time (A_n, FP64 Jacobi SVD per frequency, filter, B in FP64/FP32, "
-                   "natural-star basis images, BF16 tiles); every change of alpha, gamma or the asterism "
-                   "takes one", "loop_period_ms_at_1khz": 1.0}
+                   "natural-star basis images, BF16 tiles), needed when gamma or the asterism changes; "
+                   "safr_update_alpha wall time (filter and B from the kept SVDs) when only the "
+                   "regularisation changes", "loop_period_ms_at_1khz": 1.0}
     for name in ("C2", "C1", "C5-Mid"):
         geo = synth.preset(name)
         variants = [geo, geo.replace(alpha=geo.alpha * 2.0), geo.replace(weights=np.roll(geo.weights, 1))]
@@ -196,6 +197,18 @@ def run_recompute(S, torch, reps=3):
             plan.close()
         res[name] = {"ms": [round(v, 2) for v in ms], "median_ms": round(float(np.median(ms)), 2),
                      "loop_periods_at_1khz": round(float(np.median(ms)) / 1.0, 1)}
+        # refresh of the filter from the kept SVDs (safr_update_alpha): alpha alone, then both alphas
+        plan = S.precompute_geometry(geo)
+        for what, f_tt in (("alpha_only", 1.0), ("alpha_and_alpha_tt", 2.0)):
+            ms = []
+            for r in range(reps):
+                scale = 1.5 + r
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                S.safr_update_alpha(plan, geo.alpha * scale, geo.alpha_tt * (f_tt ** (r + 1)))
+                ms.append((time.perf_counter() - t0) * 1e3)
+            res[name]["update_" + what + "_ms"] = round(float(np.median(ms)), 3)
+        plan.close()
     return res
 
 

@@ -127,6 +127,23 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
                             hipStream_t stream);
 
 /*
+ * Soft-real-time refresh of the filter (Alg. 2 after its SVD): rebuilds B for new regularisation
+ * parameters from the per-frequency SVDs the plan keeps, without recomputing A_n or its SVD.
+ * alpha and alpha_tt (natural stars of a mixed asterism; ignored otherwise) >= 0; filter
+ * SAFR_FILTER_TIKHONOV or SAFR_FILTER_TSVD (a learned filter is made by safr_precompute);
+ * alpha_weight: NULL or host [M][M] multipliers as in safr_geometry.  The natural group and its
+ * basis images are rebuilt only when alpha_tt, the filter or a weight map changes, so a change of
+ * alpha alone touches only the laser (or only) group.  B, its FP32 copy, the basis images and the
+ * BF16 tiles are rewritten in place (pointers, captured graphs and workspaces stay valid): work
+ * on `stream` issued before the call uses the old operator, after it the new one; reconstructions
+ * on other streams must not run meanwhile.  Synchronises `stream`.  Errors: SAFR_ERR_ARG (bad
+ * parameters or map), SAFR_ERR_DEVICE; SAFR_ERR_NUMERIC if a non-finite value appears, after
+ * which the plan's operator is undefined (destroy the plan).
+ */
+safr_status safr_update_alpha(safr_plan* p, double alpha, double alpha_tt, int filter, const double* alpha_weight,
+                              hipStream_t stream);
+
+/*
  * Hard-real-time reconstruction of one frame (Alg. 1): wavefronts [J][n][n]
  * FP32 device (values outside the pupil are ignored) -> layers [L][M][M] FP32
  * device, layer l on its own grid.  Uses the plan's internal workspace.

@@ -80,6 +80,13 @@ struct safr_plan {
     float2* Yh = nullptr;
     float* P = nullptr;             // natural-star basis images [L][nb][M][M] (mixed asterisms)
     int nb = 0;
+    // kept for refreshes of the filter (safr_update_alpha): per group the geometry of A_n and its SVD
+    // (W, Q, sigma owned by the plan), the FP64 transforms of x * pupil and y * pupil, the filter in use
+    PrecompArgs pre[2] = {};
+    double2* X64 = nullptr;
+    double2* Y64 = nullptr;
+    int filter = SAFR_FILTER_TIKHONOV;
+    int weighted = 0;               // B was made with a per-frequency alpha map
     unsigned char* pupil = nullptr;
     int* tt_mode = nullptr;
     float4* polc_tab = nullptr;     // [J][L] line-of-sight sampling of the output grids (closed loop)
@@ -154,6 +161,13 @@ void free_plan(safr_plan* p) {
     hipFree(p->tt_mode);
     hipFree(p->polc_tab);
     hipFree(p->strehl_part);
+    for (int gi = 0; gi < 2; ++gi) {
+        hipFree(p->pre[gi].W);
+        hipFree(p->pre[gi].Q);
+        hipFree(p->pre[gi].sigma);
+    }
+    hipFree(p->X64);
+    hipFree(p->Y64);
     hipFree(p->dfirst);
     hipFree(p->ws_own);
     delete p;
@@ -239,6 +253,91 @@ safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, in
                        void* ws, hipStream_t s, hipEvent_t* ev = nullptr, const float* prev = nullptr,
                        float gain = 1.f);
 
+// per-frequency alpha multipliers: finite, >= 0 and point-symmetric (B must stay Hermitian)
+safr_status check_alpha_weight(int M, const double* w) {
+    for (int j = 0; j < M; ++j)
+        for (int k = 0; k < M; ++k) {
+            const double v = w[(size_t)j * M + k];
+            if (!(v >= 0.0) || !std::isfinite(v))
+                return fail(SAFR_ERR_ARG, "alpha_weight[%d][%d] must be finite and >= 0", j, k);
+            if (v != w[(size_t)((M - j) % M) * M + (M - k) % M])
+                return fail(SAFR_ERR_ARG, "alpha_weight must be point-symmetric (w[j][k] = w[-j][-k])");
+        }
+    return SAFR_OK;
+}
+
+#define BT_TRY(expr)                                                                                \
+    {                                                                                               \
+        hipError_t _e = (expr);                                                                     \
+        if (_e != hipSuccess) {                                                                     \
+            st = fail(SAFR_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(_e));            \
+            break;                                                                                  \
+        }                                                                                           \
+    }
+
+// natural-star basis images of a mixed asterism from the natural group's FP64 B (the natural stars enter
+// the output pass through them); synchronises `s`
+safr_status build_basis(safr_plan* p, hipStream_t s) {
+    const int M = p->M, L = p->L, Gn = p->gsize[1];
+    p->nb = 2 * Gn;
+    safr_status st = SAFR_OK;
+    double2* tw64 = nullptr;
+    double2* Tb = nullptr;
+    double* Eb = nullptr;
+    do {
+        std::vector<double2> t64(M);
+        for (int e = 0; e < M; ++e) t64[e] = make_double2(std::cos(2.0 * M_PI * e / M), std::sin(2.0 * M_PI * e / M));
+        BT_TRY(hipMalloc(&tw64, M * sizeof(double2)));
+        BT_TRY(hipMemcpy(tw64, t64.data(), M * sizeof(double2), hipMemcpyHostToDevice));
+        BT_TRY(hipMalloc(&Tb, (size_t)L * p->nb * p->Kh * M * sizeof(double2)));
+        BT_TRY(hipMalloc(&Eb, (size_t)L * p->nb * M * M * sizeof(double)));
+        if (!p->P) BT_TRY(hipMalloc(&p->P, (size_t)L * p->nb * M * M * sizeof(float)));
+        BasisArgs ba{};
+        ba.M = M;
+        ba.L = L;
+        ba.G = Gn;
+        for (int l = 0; l < L; ++l) ba.c[l] = p->c_out[l];
+        ba.B64 = p->B64 + p->boff[1];
+        ba.X = p->X64;
+        ba.Y = p->Y64;
+        ba.tw64 = tw64;
+        ba.T = Tb;
+        ba.E = Eb;
+        ba.P = p->P;
+        BT_TRY(launch_ngs_basis(ba, s));
+        BT_TRY(hipStreamSynchronize(s));
+    } while (0);
+    hipFree(tw64);
+    hipFree(Tb);
+    hipFree(Eb);
+    return st;
+}
+
+// BF16 hi/lo tiles of the real-split B for the matrix-core apply (M <= 128), column group only
+safr_status build_pack(safr_plan* p, hipStream_t s) {
+    const int M = p->M, L = p->L, G = p->gsize[0];
+    if (M > 128) return SAFR_OK;
+    int nf = 0;
+    for (int cand : {16, 8, 4})
+        if (!nf && mfma_lds_bytes(M, cand, G, L) <= 160 * 1024) nf = cand;
+    if (!nf) return SAFR_OK;
+    safr_status st = SAFR_OK;
+    do {
+        if (!p->Apack) p->mfma_frames = nf;
+        const int lt = std::min(L, 8), ntile = (L + lt - 1) / lt;
+        int ppm = std::max(1, std::min(16 / (2 * lt), 32 / (2 * G)));
+        while (ppm & (ppm - 1)) --ppm;                 // a power of two, so it divides M
+        p->mf_lt[0] = lt;
+        p->mf_ntile[0] = ntile;
+        p->mf_ppm[0] = ppm;
+        const size_t tot = (size_t)p->Kh * (M / ppm) * ntile * 2 * 64 * 8;
+        if (!p->Apack) BT_TRY(hipMalloc(&p->Apack, tot * sizeof(uint16_t)));
+        BT_TRY(launch_pack_bf16(M, L, G, p->B32 + p->boff32[0], p->Apack, lt, ntile, ppm, s));
+    } while (0);
+    return st;
+}
+
+
 PolcArgs polc_args(const safr_plan* p, const float* wf, const float* layers, float weight, float* out) {
     PolcArgs a{};
     a.wf = wf;
@@ -306,14 +405,8 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
         return fail(SAFR_ERR_ARG, "unknown filter %d", geo->filter);
     if (geo->alpha_weight) {
         if (geo->filter == SAFR_FILTER_MLP) return fail(SAFR_ERR_ARG, "alpha_weight needs the Tikhonov or TSVD filter");
-        for (int j = 0; j < M; ++j)
-            for (int k = 0; k < M; ++k) {
-                const double w = geo->alpha_weight[(size_t)j * M + k];
-                if (!(w >= 0.0) || !std::isfinite(w))
-                    return fail(SAFR_ERR_ARG, "alpha_weight[%d][%d] must be finite and >= 0", j, k);
-                if (w != geo->alpha_weight[(size_t)((M - j) % M) * M + (M - k) % M])
-                    return fail(SAFR_ERR_ARG, "alpha_weight must be point-symmetric (w[j][k] = w[-j][-k])");
-            }
+        const safr_status ws = check_alpha_weight(M, geo->alpha_weight);
+        if (ws != SAFR_OK) return ws;
     }
     if (geo->filter == SAFR_FILTER_MLP && (!geo->mlp || !(geo->noise > 0.0)))
         return fail(SAFR_ERR_ARG, "learned filter needs parameters and noise > 0");
@@ -420,19 +513,11 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
     p->col_frames = p->col_nf;
 
     safr_status st = SAFR_OK;
-    double2* W = nullptr;
-    double2* Qd = nullptr;
-    double* sig = nullptr;
     float* feats = nullptr;
     float* phi = nullptr;
     float* mlp_dev = nullptr;
     double* aw_dev = nullptr;
     int* dbad = nullptr;
-    double2* X64 = nullptr;
-    double2* Y64 = nullptr;
-    double2* tw64 = nullptr;
-    double2* Tb = nullptr;
-    double* Eb = nullptr;
     do {
         size_t total = 0, total32 = 0;
         const int cpw = 256 / M, kblocks = (p->Kh + cpw - 1) / cpw;
@@ -466,10 +551,10 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
             PC_TRY(hipMalloc(&p->Yh, Yf.size() * sizeof(float2)));
             PC_TRY(hipMemcpy(p->Xh, Xf.data(), Xf.size() * sizeof(float2), hipMemcpyHostToDevice));
             PC_TRY(hipMemcpy(p->Yh, Yf.data(), Yf.size() * sizeof(float2), hipMemcpyHostToDevice));
-            PC_TRY(hipMalloc(&X64, X.size() * sizeof(double2)));
-            PC_TRY(hipMalloc(&Y64, Y.size() * sizeof(double2)));
-            PC_TRY(hipMemcpy(X64, X.data(), X.size() * sizeof(double2), hipMemcpyHostToDevice));
-            PC_TRY(hipMemcpy(Y64, Y.data(), Y.size() * sizeof(double2), hipMemcpyHostToDevice));
+            PC_TRY(hipMalloc(&p->X64, X.size() * sizeof(double2)));
+            PC_TRY(hipMalloc(&p->Y64, Y.size() * sizeof(double2)));
+            PC_TRY(hipMemcpy(p->X64, X.data(), X.size() * sizeof(double2), hipMemcpyHostToDevice));
+            PC_TRY(hipMemcpy(p->Y64, Y.data(), Y.size() * sizeof(double2), hipMemcpyHostToDevice));
         }
         std::vector<float2> tw(M);
         for (int e = 0; e < M; ++e)
@@ -502,10 +587,7 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
         PC_TRY(hipMemsetAsync(dbad, 0, sizeof(int), stream));
         const int H = p->Kh * M;
         int gmax = std::max(p->gsize[0], p->gsize[1]);
-        const int Rm = std::max(gmax, L), Cm = std::min(gmax, L);
-        PC_TRY(hipMalloc(&W, (size_t)H * Rm * Cm * sizeof(double2)));
-        PC_TRY(hipMalloc(&Qd, (size_t)H * Cm * Cm * sizeof(double2)));
-        PC_TRY(hipMalloc(&sig, (size_t)H * Cm * sizeof(double)));
+        const int Cm = std::min(gmax, L);
         if (geo->filter == SAFR_FILTER_MLP) {
             PC_TRY(hipMalloc(&feats, (size_t)H * Cm * 4 * sizeof(float)));
             PC_TRY(hipMalloc(&phi, (size_t)H * Cm * sizeof(float)));
@@ -534,9 +616,15 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
                 a.gamma[l] = weights[l] / wsum;
                 a.sqrt_gamma[l] = std::sqrt(weights[l] / wsum);
             }
-            a.W = W;
-            a.Q = Qd;
-            a.sigma = sig;
+            {
+                const int R = std::max(a.G, L), C = std::min(a.G, L);
+                PC_TRY(hipMalloc(&a.W, (size_t)H * R * C * sizeof(double2)));
+                PC_TRY(hipMalloc(&a.Q, (size_t)H * C * C * sizeof(double2)));
+                PC_TRY(hipMalloc(&a.sigma, (size_t)H * C * sizeof(double)));
+                p->pre[gi].W = a.W;                      // owned by the plan from here on
+                p->pre[gi].Q = a.Q;
+                p->pre[gi].sigma = a.sigma;
+            }
             a.feats = feats;
             a.phi = phi;
             a.B64 = p->B64 + p->boff[gi];
@@ -551,8 +639,15 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
                 PC_TRY(launch_mlp_infer(mlp_dev, feats, phi, H * C, (float)a.log10_noise, stream));
             }
             PC_TRY(launch_assemble(a, stream));
+            p->pre[gi] = a;                              // geometry and SVD; temporaries cleared below
+            p->pre[gi].feats = nullptr;
+            p->pre[gi].phi = nullptr;
+            p->pre[gi].bad = nullptr;
+            p->pre[gi].aw = nullptr;
         }
         if (st != SAFR_OK) break;
+        p->filter = geo->filter;
+        p->weighted = geo->alpha_weight != nullptr;
         int hbad = 0;
         PC_TRY(hipMemcpyAsync(&hbad, dbad, sizeof(int), hipMemcpyDeviceToHost, stream));
         PC_TRY(hipStreamSynchronize(stream));
@@ -560,51 +655,12 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
             st = fail(SAFR_ERR_NUMERIC, "non-finite value in the precomputed operator");
             break;
         }
-        // natural-star basis images of a mixed asterism (group 1 enters the output pass through them)
         if (p->mixed) {
-            const int Gn = p->gsize[1];
-            p->nb = 2 * Gn;
-            std::vector<double2> t64(M);
-            for (int e = 0; e < M; ++e)
-                t64[e] = make_double2(std::cos(2.0 * M_PI * e / M), std::sin(2.0 * M_PI * e / M));
-            PC_TRY(hipMalloc(&tw64, M * sizeof(double2)));
-            PC_TRY(hipMemcpy(tw64, t64.data(), M * sizeof(double2), hipMemcpyHostToDevice));
-            PC_TRY(hipMalloc(&Tb, (size_t)L * p->nb * p->Kh * M * sizeof(double2)));
-            PC_TRY(hipMalloc(&Eb, (size_t)L * p->nb * M * M * sizeof(double)));
-            PC_TRY(hipMalloc(&p->P, (size_t)L * p->nb * M * M * sizeof(float)));
-            BasisArgs ba{};
-            ba.M = M;
-            ba.L = L;
-            ba.G = Gn;
-            for (int l = 0; l < L; ++l) ba.c[l] = cgrp[0][l];
-            ba.B64 = p->B64 + p->boff[1];
-            ba.X = X64;
-            ba.Y = Y64;
-            ba.tw64 = tw64;
-            ba.T = Tb;
-            ba.E = Eb;
-            ba.P = p->P;
-            PC_TRY(launch_ngs_basis(ba, stream));
+            st = build_basis(p, stream);
+            if (st != SAFR_OK) break;
         }
-        // BF16 hi/lo tiles of the real-split B for the matrix-core apply (M <= 128), column group only
-        if (M <= 128) {
-            const int G = p->gsize[0];
-            int nf = 0;
-            for (int cand : {16, 8, 4})
-                if (!nf && mfma_lds_bytes(M, cand, G, L) <= 160 * 1024) nf = cand;
-            if (nf) {
-                p->mfma_frames = nf;
-                const int lt = std::min(L, 8), ntile = (L + lt - 1) / lt;
-                int ppm = std::max(1, std::min(16 / (2 * lt), 32 / (2 * G)));
-                while (ppm & (ppm - 1)) --ppm;                 // a power of two, so it divides M
-                p->mf_lt[0] = lt;
-                p->mf_ntile[0] = ntile;
-                p->mf_ppm[0] = ppm;
-                const size_t tot = (size_t)p->Kh * (M / ppm) * ntile * 2 * 64 * 8;
-                PC_TRY(hipMalloc(&p->Apack, tot * sizeof(uint16_t)));
-                PC_TRY(launch_pack_bf16(M, L, G, p->B32 + p->boff32[0], p->Apack, lt, ntile, ppm, stream));
-            }
-        }
+        st = build_pack(p, stream);
+        if (st != SAFR_OK) break;
         p->ws_own_bytes = ws_bytes(p, 1);
         PC_TRY(hipMalloc(&p->ws_own, p->ws_own_bytes));
         PC_TRY(hipMalloc(&p->dfirst, sizeof(int)));
@@ -615,19 +671,11 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
         PC_TRY(hipStreamSynchronize(stream));
 #undef PC_TRY
     } while (0);
-    hipFree(W);
-    hipFree(Qd);
-    hipFree(sig);
     hipFree(feats);
     hipFree(phi);
     hipFree(mlp_dev);
     hipFree(aw_dev);
     hipFree(dbad);
-    hipFree(X64);
-    hipFree(Y64);
-    hipFree(tw64);
-    hipFree(Tb);
-    hipFree(Eb);
     if (st != SAFR_OK) {
         free_plan(p);
         return st;
@@ -692,6 +740,69 @@ safr_status safr_export_B(const safr_plan* p, int group, double* host, size_t co
                     host[2 * o + 1] = v.y;
                 }
     return SAFR_OK;
+}
+
+safr_status safr_update_alpha(safr_plan* p, double alpha, double alpha_tt, int filter, const double* alpha_weight,
+                              hipStream_t s) {
+    if (!p) return fail(SAFR_ERR_ARG, "plan is NULL");
+    if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(SAFR_ERR_ARG, "alpha must be >= 0");
+    if (!(alpha_tt >= 0.0) || !std::isfinite(alpha_tt)) return fail(SAFR_ERR_ARG, "alpha_tt must be >= 0");
+    if (filter != SAFR_FILTER_TIKHONOV && filter != SAFR_FILTER_TSVD)
+        return fail(SAFR_ERR_ARG, "a refresh takes the Tikhonov or TSVD filter");
+    if (alpha_weight) {
+        const safr_status ws = check_alpha_weight(p->M, alpha_weight);
+        if (ws != SAFR_OK) return ws;
+    }
+    const int M = p->M;
+    const double galpha[2] = {alpha, p->mixed ? alpha_tt : 0.0};
+    // the natural group (and its basis images) changes only with alpha_tt, the filter or a weight map
+    const bool redo1 = p->mixed && (alpha_tt != p->galpha[1] || filter != p->filter || alpha_weight || p->weighted);
+    safr_status st = SAFR_OK;
+    double* aw_dev = nullptr;
+    int* dbad = nullptr;
+    do {
+        const int clear = 0;
+        BT_TRY(hipMalloc(&dbad, sizeof(int)));
+        BT_TRY(hipMemcpyAsync(dbad, &clear, sizeof(int), hipMemcpyHostToDevice, s));
+        if (alpha_weight) {
+            BT_TRY(hipMalloc(&aw_dev, (size_t)M * M * sizeof(double)));
+            BT_TRY(hipMemcpy(aw_dev, alpha_weight, (size_t)M * M * sizeof(double), hipMemcpyHostToDevice));
+        }
+        for (int gi = 0; gi < p->ngroups; ++gi) {
+            if (gi == 1 && !redo1) continue;
+            PrecompArgs a = p->pre[gi];
+            a.alpha = galpha[gi];
+            a.tsvd = filter == SAFR_FILTER_TSVD;
+            a.aw = aw_dev;
+            a.phi = nullptr;
+            a.bad = dbad;
+            BT_TRY(launch_assemble(a, s));
+        }
+        if (st != SAFR_OK) break;
+        int hbad = 0;
+        BT_TRY(hipMemcpyAsync(&hbad, dbad, sizeof(int), hipMemcpyDeviceToHost, s));
+        BT_TRY(hipStreamSynchronize(s));
+        if (hbad) {
+            st = fail(SAFR_ERR_NUMERIC, "non-finite value in the refreshed operator");
+            break;
+        }
+        if (redo1) {
+            st = build_basis(p, s);
+            if (st != SAFR_OK) break;
+        }
+        if (p->Apack) {
+            st = build_pack(p, s);
+            if (st != SAFR_OK) break;
+        }
+        BT_TRY(hipStreamSynchronize(s));
+        p->galpha[0] = galpha[0];
+        p->galpha[1] = galpha[1];
+        p->filter = filter;
+        p->weighted = alpha_weight != nullptr;
+    } while (0);
+    hipFree(aw_dev);
+    hipFree(dbad);
+    return st;
 }
 
 safr_status safr_reconstruct_batched(safr_plan* p, int frames, const float* wf, float* out, int precision,

@@ -32,7 +32,7 @@ EXPORTED = [
     "safr_set_workspace", "safr_plan_info", "safr_export_B", "safr_set_option", "safr_time_stages",
     "safr_autotune", "safr_destroy", "safr_last_error",
     "safr_multi_create", "safr_multi_execute", "safr_multi_autotune", "safr_multi_destroy",
-    "safr_polc", "safr_loop_step", "safr_strehl",
+    "safr_polc", "safr_loop_step", "safr_strehl", "safr_update_alpha",
     # learned filter (bound in learn.py)
     "safr_trainer_create", "safr_trainer_add_frames", "safr_trainer_set_params", "safr_trainer_get_params",
     "safr_trainer_step", "safr_trainer_gradient", "safr_trainer_frames", "safr_trainer_destroy", "safr_mlp_infer",
@@ -110,6 +110,7 @@ def lib() -> ctypes.CDLL:
     L.safr_polc.argtypes = [vp, i, vp, vp, ctypes.c_float, vp, vp]
     L.safr_loop_step.argtypes = [vp, i, vp, vp, ctypes.c_float, vp, vp]
     L.safr_strehl.argtypes = [vp, i, i, ctypes.POINTER(d), vp, vp, ctypes.c_float, vp, vp, vp]
+    L.safr_update_alpha.argtypes = [vp, d, d, i, ctypes.POINTER(d), vp]
     for name in EXPORTED[:EXPORTED.index("safr_trainer_create")]:
         if name not in ("safr_destroy", "safr_last_error", "safr_multi_destroy"):
             getattr(L, name).restype = ctypes.c_int
@@ -251,6 +252,18 @@ def safr_autotune(plan: Plan, frames: int, wavefronts, layers, precision: int = 
     _check(lib().safr_autotune(plan._as_parameter_, int(frames), _ptr(wavefronts), _ptr(layers), int(precision),
                                int(iters), _stream(stream), ch))
     return tuple(int(x) for x in ch)
+
+
+def safr_update_alpha(plan: Plan, alpha: float, alpha_tt: float = 0.0, filter: int = SAFR_FILTER_TIKHONOV,
+                      alpha_weight=None, stream=None):
+    """Rebuild B for new regularisation parameters from the plan's kept SVDs (synchronises)."""
+    M = plan.desc.M
+    aw = None
+    if alpha_weight is not None:
+        aw = np.ascontiguousarray(np.asarray(alpha_weight, dtype=np.float64).reshape(M, M))
+    _check(lib().safr_update_alpha(plan._as_parameter_, float(alpha), float(alpha_tt), int(filter),
+                                   None if aw is None else aw.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   _stream(stream)))
 
 
 def safr_polc(plan: Plan, frames: int, wavefronts, layers, weight: float, out, stream=None):

@@ -154,3 +154,73 @@ def test_filter_argument_errors():
         with pytest.raises(S.SafrError) as e:
             S.precompute_geometry(geo, **kw)
         assert e.value.status == S.SAFR_ERR_ARG, kw
+
+
+def _recon(S, torch, plan, x, precision=None):
+    F = x.shape[0]
+    prec = S.SAFR_FP32 if precision is None else precision
+    return S.reconstruct(plan, x, precision=prec).cpu().numpy()
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_update_alpha_equals_a_fresh_plan(case):
+    # the refresh rebuilds B from the kept SVDs: the same arithmetic as a new precompute, bit for bit
+    torch = _torch()
+    S = _lib()
+    geo = CASES[case]()
+    plan = S.precompute_geometry(geo)
+    x = torch.from_numpy(synth.frames(geo, 3, first=2)).cuda()
+    M = geo.M
+    w = _symmetric_weights(M, 11)
+    tg = _tsvd_geometry(geo)
+    steps = [
+        (dict(alpha=geo.alpha * 3.0, alpha_tt=geo.alpha_tt), {}),                    # alpha only
+        (dict(alpha=geo.alpha * 3.0, alpha_tt=geo.alpha_tt * 0.5), {}),              # both groups
+        (dict(alpha=tg.alpha, alpha_tt=tg.alpha_tt, filter=S.SAFR_FILTER_TSVD), {"filter": S.SAFR_FILTER_TSVD}),
+        (dict(alpha=geo.alpha, alpha_tt=geo.alpha_tt, alpha_weight=w), {"alpha_weight": w}),
+        (dict(alpha=geo.alpha, alpha_tt=geo.alpha_tt), {}),                          # back to no map
+    ]
+    for upd, extra in steps:
+        S.safr_update_alpha(plan, **upd)
+        fresh = S.precompute_geometry(geo.replace(alpha=upd["alpha"], alpha_tt=upd["alpha_tt"]), **extra)
+        for gi in range(plan.desc.groups):
+            assert np.array_equal(S.safr_export_B(plan, gi), S.safr_export_B(fresh, gi)), (case, upd, gi)
+        assert np.array_equal(_recon(S, torch, plan, x), _recon(S, torch, fresh, x)), (case, upd)
+        if M <= 128:
+            assert np.array_equal(_recon(S, torch, plan, x, S.SAFR_BF16X3),
+                                  _recon(S, torch, fresh, x, S.SAFR_BF16X3)), (case, upd)
+        fresh.close()
+
+
+def test_update_alpha_keeps_captured_graphs_valid():
+    torch = _torch()
+    S = _lib()
+    geo = CASES["m32-mixed"]()
+    plan = S.precompute_geometry(geo)
+    x = torch.from_numpy(synth.frames(geo, 1)[0]).cuda()
+    out = torch.empty((geo.L, geo.M, geo.M), device="cuda")
+    s = torch.cuda.Stream()
+    S.safr_set_option(plan, S.SAFR_OPT_GRAPH, 1)
+    torch.cuda.synchronize()
+    S.safr_reconstruct(plan, x, out, stream=s)                    # captures the graph
+    s.synchronize()
+    S.safr_update_alpha(plan, geo.alpha * 10.0, geo.alpha_tt * 10.0, stream=s)
+    S.safr_reconstruct(plan, x, out, stream=s)                    # replays it with the new operator
+    s.synchronize()
+    fresh = S.precompute_geometry(geo.replace(alpha=geo.alpha * 10.0, alpha_tt=geo.alpha_tt * 10.0))
+    want = S.reconstruct(fresh, x)
+    torch.cuda.synchronize()
+    assert torch.equal(out, want)
+
+
+def test_update_alpha_errors():
+    S = _lib()
+    geo = CASES["C1"]()
+    plan = S.precompute_geometry(geo)
+    bad = _symmetric_weights(geo.M, 12)
+    bad[2, 3] += 1.0
+    for kw in ({"alpha": -1.0}, {"alpha": 1e-3, "filter": S.SAFR_FILTER_MLP}, {"alpha": float("nan")},
+               {"alpha": 1e-3, "alpha_weight": bad}):
+        with pytest.raises(S.SafrError) as e:
+            S.safr_update_alpha(plan, **kw)
+        assert e.value.status == S.SAFR_ERR_ARG, kw
