@@ -44,8 +44,19 @@ namespace safr {
 
 namespace {
 
-__device__ __forceinline__ float2 plane_value(float2 cf, float2 xh, float2 yh) {
-    return make_float2(cf.x * xh.x + cf.y * yh.x, cf.x * xh.y + cf.y * yh.y);
+// d - (b X + c Y) with (b, c) = cf: two FMAs per part
+__device__ __forceinline__ float2 remove_plane(float2 d, float2 cf, float2 xh, float2 yh) {
+    return make_float2(fmaf(-cf.y, yh.x, fmaf(-cf.x, xh.x, d.x)), fmaf(-cf.y, yh.y, fmaf(-cf.x, xh.y, d.y)));
+}
+
+// acc + b d as four FMAs (written as one expression, the product difference would be formed first and
+// cost a multiply, an FMA and an add per part)
+__device__ __forceinline__ float2 cmac(float2 acc, float2 b, float2 d) {
+    acc.x = fmaf(b.x, d.x, acc.x);
+    acc.x = fmaf(-b.y, d.y, acc.x);
+    acc.y = fmaf(b.x, d.y, acc.y);
+    acc.y = fmaf(b.y, d.x, acc.y);
+    return acc;
 }
 
 // Raw buffer access to the block's B slice: the descriptor is uniform (scalar registers) and each
@@ -213,7 +224,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
 #pragma unroll
                     for (int g = 0; g < GC; ++g) {
                         const float2 d = slot(c, fl, g)[j];
-                        dv[fl][g] = MODE != 0 ? csub(d, plane_value(coef[fl * GC + g], xh, yh)) : d;
+                        dv[fl][g] = MODE != 0 ? remove_plane(d, coef[fl * GC + g], xh, yh) : d;
                     }
                 // B of layer l + 2 is requested before the products of layer l
 #pragma unroll
@@ -228,10 +239,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
                     for (int fl = 0; fl < NF; ++fl) {
                         float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
-                        for (int g = 0; g < GC; ++g) {
-                            acc.x += bv[g].x * dv[fl][g].x - bv[g].y * dv[fl][g].y;
-                            acc.y += bv[g].x * dv[fl][g].y + bv[g].y * dv[fl][g].x;
-                        }
+                        for (int g = 0; g < GC; ++g) acc = cmac(acc, bv[g], dv[fl][g]);
                         slot(c, fl, l)[j] = acc;
                     }
                 }
@@ -240,10 +248,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
                     float2 acc = make_float2(0.f, 0.f);
                     for (int g = 0; g < G; ++g) {
                         float2 d = slot(c, 0, g)[j];
-                        if (MODE != 0) d = csub(d, plane_value(coef[g], xh, yh));
+                        if (MODE != 0) d = remove_plane(d, coef[g], xh, yh);
                         const float2 bv = load_b(Brs, tid * 8, l * G + g);
-                        acc.x += bv.x * d.x - bv.y * d.y;
-                        acc.y += bv.x * d.y + bv.y * d.x;
+                        acc = cmac(acc, bv, d);
                     }
                     slot(c, 0, LS + l)[j] = acc;
                 }

@@ -1,7 +1,7 @@
 // Output pass of SAFR's hard-real-time step (Alg. 1, last loop), fused with the
 // split-tomography sum (Sec. 3.3):
 //   - C2R row transforms of the layer spectra (two real rows packed into one
-//     complex inverse FFT), scaled by 1/M^2 (IDFT2 of Sec. 3.2);
+//     complex inverse FFT); the 1/M^2 of IDFT2 (Sec. 3.2) is already in the FP32 B;
 //   - mixed asterisms: the natural-star layers, sum_g b_g P[l][2g] + c_g P[l][2g+1]
 //     with the frame's tip/tilt plane coefficients (b_g, c_g) from the row-pass
 //     moments and the precomputed basis images P (already resampled onto the
@@ -116,7 +116,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void o
     const float2 twv = tid < M ? a.tw[tid] : make_float2(0.f, 0.f);
     issue(fbeg);
     if (tid < M) tws[tid] = twv;
-    const float scale = 1.0f / ((float)M * (float)M);
 
     auto star_of = [&](int g) { return a.ngs_star[g]; };
     constexpr int PMAX = 1;                                 // rounds of natural-star plane sums held in registers
@@ -162,8 +161,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void o
         {
             float* rows = reinterpret_cast<float*>(reg);    // [2][M]
             fft_pass2_regs<M, +1>(t, z, [&](int p, float2 v) {
-                rows[p] = v.x * scale;
-                rows[M + p] = v.y * scale;
+                rows[p] = v.x;
+                rows[M + p] = v.y;
             });
         }
         // natural stars' plane coefficients (b_g, c_g) of this iteration's frames, [NF][ng] as float2

@@ -191,10 +191,12 @@ __global__ void assemble_kernel(PrecompArgs a) {
             if (!isfinite(b.x) || !isfinite(b.y)) bad = true;
             const size_t o = (((size_t)k * L + l) * G + g) * M + j;
             a.B64[o] = make_double2(b.x, b.y);
-            // FP32 copy in the column-pass layout: [k / CPW][l][g][k % CPW][j], CPW = 256 / M
+            // FP32 copy in the column-pass layout: [k / CPW][l][g][k % CPW][j], CPW = 256 / M, with the
+            // 1/M^2 of IDFT2 folded in (M^2 is a power of two, so the scaling is exact)
             const int cpw = 256 / M;
             const size_t o32 = ((((size_t)(k / cpw) * L + l) * G + g) * cpw + (k % cpw)) * M + j;
-            a.B32[o32] = make_float2((float)b.x, (float)b.y);
+            const double inv_m2 = 1.0 / ((double)M * (double)M);
+            a.B32[o32] = make_float2((float)(b.x * inv_m2), (float)(b.y * inv_m2));
         }
     }
     if (bad) atomicOr(a.bad, 1);
