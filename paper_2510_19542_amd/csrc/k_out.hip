@@ -224,7 +224,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void o
                     o.z = fmaf(a.gain, o.z, keep * pr.z);
                     o.w = fmaf(a.gain, o.w, keep * pr.w);
                 }
-                *reinterpret_cast<float4*>(a.out + oi) = o;
+                // the layers are not read again by the step: streamed past the caches that hold C and the basis
+                typedef float f32x4 __attribute__((ext_vector_type(4)));
+                const f32x4 ov = {o.x, o.y, o.z, o.w};
+                __builtin_nontemporal_store(ov, reinterpret_cast<f32x4*>(a.out + oi));
             }
         }
     }
