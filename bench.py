@@ -337,6 +337,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--frames", type=int, default=64, help="independent frames per step (one batched call)")
+    ap.add_argument("--batches", type=int, default=8,
+                    help="distinct input batches cycled through (each is re-read only every this many steps)")
     ap.add_argument("--single-calls", type=int, default=2000, help="one-frame calls timed for the latency figure")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -382,15 +384,19 @@ def main():
         apply_shape(S, plan1, tuned1)
 
     # batched throughput: each step reconstructs F frames in one call
+    # distinct input buffers (the two synthetic batches, then sign-flipped copies in their own memory), so
+    # that a step's inputs were last read several steps earlier
     batches = [pool[:F], pool[F:]]
+    while len(batches) < args.batches:
+        batches.append(-batches[len(batches) % 2])
     for i in range(args.warmup):
-        S.safr_reconstruct_batched(plan, F, batches[i % 2], out, S.SAFR_FP32, stream)
+        S.safr_reconstruct_batched(plan, F, batches[i % len(batches)], out, S.SAFR_FP32, stream)
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     t0.record(stream)
     for i in range(args.steps):
-        S.safr_reconstruct_batched(plan, F, batches[i % 2], out, S.SAFR_FP32, stream)
+        S.safr_reconstruct_batched(plan, F, batches[i % len(batches)], out, S.SAFR_FP32, stream)
     t1.record(stream)
     torch.cuda.synchronize()
     ms_step = t0.elapsed_time(t1) / args.steps
@@ -451,7 +457,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"MORFEO-like frames: J=9 (6 LGS + 3 NGS, split tomography), L=9, n=69, "
                                f"M=256, FP32; {F} independent frames per step in one batched call",
-                   "frames_per_step": F, "J": geo.J, "L": geo.L, "M": geo.M, "n": geo.n,
+                   "frames_per_step": F, "input_batches_cycled": len(batches), "J": geo.J, "L": geo.L, "M": geo.M,
+                   "n": geo.n,
                    "launch_shapes": {"batched": list(tuned), "single": list(tuned1), "autotuned_now": args.autotune}},
         "roofline": roof,
         "stage_ms": {k: round(v, 6) for k, v in zip(names, stage_ms)},
