@@ -31,7 +31,7 @@ FP32_PEAK_TFLOPS = 157.3          # MI355X FP32 vector peak (published)
 
 # launch shapes of the MORFEO-like plans, chosen by safr_autotune on an MI355X
 # (row teams, output rows, column frames per block, output frames per block, column frames together)
-TUNED_BATCHED = (16, 8, 4, 8, 4)
+TUNED_BATCHED = (16, 8, 16, 8, 4)
 TUNED_SINGLE = (1, 8, 1, 4, 1)
 
 

@@ -193,7 +193,8 @@ safr_status safr_export_B(const safr_plan* p, int group, double* host, size_t co
  *                        block's natural-star basis pixels in registers across them);
  *   SAFR_OPT_MFMA_FRAMES frames per block of the BF16 apply (4, 8 or 16; default: the
  *                        largest that fits in LDS);
- *   SAFR_OPT_COL_FRAMES  frames per block of the FP32 column pass (>= 1);
+ *   SAFR_OPT_COL_FRAMES  frames per block of the FP32 column pass (>= 1; until set or autotuned it is
+ *                        chosen per launch for about two column blocks per CU);
  *   SAFR_OPT_COL_TOGETHER frames the FP32 column pass transforms together (1, 2 or 4; B is
  *                        read once for them; compile-time shapes only, others use 1);
  *   SAFR_OPT_COL_PREFETCH 1 = the column pass uses its compile-time kernel when the shape

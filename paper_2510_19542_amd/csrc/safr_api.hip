@@ -98,6 +98,7 @@ struct safr_plan {
     size_t ws_user_bytes = 0;
     // tuning
     int row_teams = 0, out_rows = 0, out_frames = 1, mfma_frames = 16, col_frames = 1, col_nf = 1, col_prefetch = 1;
+    int col_frames_auto = 1;        // column frames per block chosen per launch (until set or autotuned)
     int use_graph = 0;
     int check_finite = 0;           // debug: scan inputs for non-finite values first (synchronises)
     int* dfirst = nullptr;          // first non-finite frame found by the check
@@ -1067,6 +1068,7 @@ safr_status safr_autotune(safr_plan* p, int frames, const float* wf, float* out,
         int best = p->col_frames, bestn = p->col_nf;
         double bt = 1e30;
         const bool fixed = p->col_prefetch && cols_fixed_shape(p->M, p->L, p->gsize[0], p->mixed ? 1 : 0);
+        p->col_frames_auto = 0;                           // the candidates below are timed as set
         for (int nf : {1, 2, 4}) {
             if (nf > 1 && (!fixed || nf > frames)) break;
             if (cols_lds_bytes(p->M, p->gsize[0], p->L, nf, fixed) > kMaxLds) break;
@@ -1087,6 +1089,7 @@ safr_status safr_autotune(safr_plan* p, int frames, const float* wf, float* out,
         }
         p->col_frames = best;
         p->col_nf = bestn;
+        p->col_frames_auto = 0;
     }
     for (auto& e : ev) hipEventDestroy(e);
     drop_graphs(p);
@@ -1278,6 +1281,7 @@ safr_status safr_set_option(safr_plan* p, int option, int value) {
         case 4:
             if (value < 1 || value > 4096) return fail(SAFR_ERR_ARG, "bad frames per column block");
             p->col_frames = value;
+            p->col_frames_auto = 0;
             return SAFR_OK;
         case 5: p->col_prefetch = value != 0; return SAFR_OK;
         case 6:
@@ -1348,7 +1352,14 @@ safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, in
         const bool fixed = p->col_prefetch && cols_fixed_shape(p->M, p->L, grp.G, grp.mode);
         int nf = fixed ? p->col_nf : 1;
         while (nf > 1 && nf > frames) nf /= 2;
-        ca.frames_per_block = std::max(1, std::min(p->col_frames, frames));
+        int fpb = p->col_frames;
+        if (p->col_frames_auto) {
+            // about two column blocks per CU, each looping over a multiple of the frames transformed together
+            const int kblocks = (p->M / 2) / (256 / p->M);
+            const int per = std::max(1, frames * kblocks / 512);
+            fpb = std::max(nf, per / nf * nf);
+        }
+        ca.frames_per_block = std::max(1, std::min(fpb, frames));
         ca.nchunk = nchunk;
         ca.prefetch = p->col_prefetch;
         HIP_TRY(launch_cols(p->M, ca, nf, frames, s));
