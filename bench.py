@@ -59,21 +59,28 @@ def algorithmic_flops(desc, frames=1):
 def algorithmic_bytes(desc, n, frames=1):
     """Algorithmic bytes of one launch sequence: wavefronts in + layers out per frame, B read once.
 
-    Also the bytes each kernel moves including the intermediate spectra (R: row
-    spectra of the pupil rows, C: layer half-spectra), which are implementation
-    overhead of the two-pass transforms and not part of the algorithmic figure.
+    Per kernel: what the kernel itself must move of that (rows: the wavefronts; cols: the
+    B it applies, read once; out: the layers and, for mixed asterisms, the natural-star
+    basis images read once), and the bytes it moves including the intermediate spectra
+    (R: row spectra of the transformed stars' pupil rows, C: layer half-spectra of the
+    transformed group), which are implementation overhead of the two-pass transforms.
     """
     M, J, L, G = desc.M, desc.J, desc.L, desc.groups
     Kh = M // 2 + 1
+    Gt = int(desc.group_size[0])                 # stars transformed in the hot path (laser group when mixed)
+    nb = 2 * int(desc.group_size[1]) if G == 2 else 0
     wf = J * n * n * 4
-    R = J * Kh * n * 8
+    R = Gt * Kh * n * 8
     B = sum(int(desc.B_complex_per_group[g]) for g in range(G)) * 8
-    C = G * L * Kh * M * 8
+    B0 = int(desc.B_complex_per_group[0]) * 8
+    C = L * Kh * M * 8
     out = L * M * M * 4
+    basis = L * nb * M * M * 4
     return {
         "step": frames * (wf + out) + B,
-        "with_intermediates": {"rows": frames * (wf + R), "cols": frames * (R + C) + B,
-                               "out": frames * (C + out)},
+        "per_kernel": {"rows": frames * wf, "cols": B0, "out": frames * out + basis},
+        "with_intermediates": {"rows": frames * (wf + R), "cols": frames * (R + C) + B0,
+                               "out": frames * (C + out) + basis},
     }
 
 
@@ -432,14 +439,23 @@ def main():
                  "frac": round(tfl / FP32_PEAK_TFLOPS, 4)}
     dom = int(np.argmax(stage_ms))
     dk = names[dom]
-    dom_tfl = af["per_kernel"][dk] / (stage_ms[dom] * 1e-3) / 1e12
+    dsec = stage_ms[dom] * 1e-3
+    dom_tfl = af["per_kernel"][dk] / dsec / 1e12
+    dom_gbs = ab["per_kernel"][dk] / dsec / 1e9
+    dom_hbm_bound = ab["per_kernel"][dk] / (HBM_PEAK_GBS * 1e9) >= af["per_kernel"][dk] / (FP32_PEAK_TFLOPS * 1e12)
+    if dom_hbm_bound:
+        dom_roof = {"bound": "hbm", "achieved": round(dom_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(dom_gbs / HBM_PEAK_GBS, 4), "alu_frac": round(dom_tfl / FP32_PEAK_TFLOPS, 4)}
+    else:
+        dom_roof = {"bound": "alu", "achieved": round(dom_tfl, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(dom_tfl / FP32_PEAK_TFLOPS, 4), "hbm_frac": round(dom_gbs / HBM_PEAK_GBS, 4)}
     roof.update({"kernel": "rows + cols + out (the three kernels of one batched step)",
                  "traffic": traffic, "alg_bytes_per_launch": ab["step"], "alg_flops_per_launch": af["step"],
                  "kernel_ms": round(step_kernel_ms, 6), "other_bound": other,
-                 "dominant_kernel": {"kernel": dk, "ms": round(stage_ms[dom], 6), "bound": "alu",
-                                     "alg_flops": af["per_kernel"][dk], "achieved": round(dom_tfl, 3),
-                                     "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                                     "frac": round(dom_tfl / FP32_PEAK_TFLOPS, 4)},
+                 "dominant_kernel": dict({"kernel": dk, "ms": round(stage_ms[dom], 6),
+                                          "alg_bytes": ab["per_kernel"][dk], "alg_flops": af["per_kernel"][dk],
+                                          "GBs_with_intermediates": round(
+                                              ab["with_intermediates"][dk] / dsec / 1e9, 1)}, **dom_roof),
                  "per_kernel_GBs_with_intermediates": {
                      k: round(ab["with_intermediates"][k] / (v * 1e-3) / 1e9, 1) for k, v in zip(names, stage_ms)}})
     result = {
