@@ -21,24 +21,7 @@ __global__ void __launch_bounds__(256) polc_kernel(PolcArgs a) {
     float v = 0.f;
     if (a.pupil[e]) {
         const int i = e / n, j = e - (e / n) * n;
-        const int mask = M - 1;                          // M is a power of two: the periodic wrap
-        const float* lay = a.layers + (size_t)f * L * M * M;
-        const float4* tab = a.tab + (size_t)g * L;
-        float acc = 0.f;
-#pragma unroll
-        for (int l = 0; l < L; ++l) {
-            const float4 t = tab[l];
-            const float u = fmaf(t.x, (float)i, t.y);
-            const float w = fmaf(t.x, (float)j, t.z);
-            const float fu0 = floorf(u), fw0 = floorf(w);
-            const float fu = u - fu0, fw = w - fw0;
-            const int i0 = (int)fu0 & mask, j0 = (int)fw0 & mask;
-            const int i1 = (i0 + 1) & mask, j1 = (j0 + 1) & mask;
-            const float* X = lay + (size_t)l * M * M;
-            const float x00 = X[i0 * M + j0], x01 = X[i0 * M + j1];
-            const float x10 = X[i1 * M + j0], x11 = X[i1 * M + j1];
-            acc += (1.f - fu) * ((1.f - fw) * x00 + fw * x01) + fu * ((1.f - fw) * x10 + fw * x11);
-        }
+        const float acc = los_sum<L>(a.layers + (size_t)f * L * M * M, a.tab + (size_t)g * L, L, M, i, j);
         v = fmaf(a.weight, acc, a.wf[o]);
     }
     a.out[o] = v;

@@ -39,27 +39,16 @@ __global__ void __launch_bounds__(256) strehl_part_kernel(StrehlArgs a) {
     __shared__ float red[3 * 4];
     const int n = a.n, M = a.M;
     const int c = blockIdx.x, d = blockIdx.y, f = blockIdx.z;
-    const int mask = M - 1;
     const int e = c * 256 + threadIdx.x;
     Moments acc = {0.f, 0.f, 0.f};
     if (e < n * n && a.pupil[e]) {
-        const float* lay = a.layers + (size_t)f * L * M * M;
-        const float tx = a.dx[d], ty = a.dy[d];
         const int i = e / n, j = e - (e / n) * n;
-        float corr = 0.f;
+        // science lines of sight: table entries (m_l, base_l + theta_x hs_l, base_l + theta_y hs_l)
+        float4 tab[L];
 #pragma unroll
-        for (int l = 0; l < L; ++l) {
-            const float u = fmaf(a.m[l], (float)i, fmaf(tx, a.hs[l], a.base[l]));
-            const float w = fmaf(a.m[l], (float)j, fmaf(ty, a.hs[l], a.base[l]));
-            const float fu0 = floorf(u), fw0 = floorf(w);
-            const float fu = u - fu0, fw = w - fw0;
-            const int i0 = (int)fu0 & mask, j0 = (int)fw0 & mask;
-            const int i1 = (i0 + 1) & mask, j1 = (j0 + 1) & mask;
-            const float* X = lay + (size_t)l * M * M;
-            const float x00 = X[i0 * M + j0], x01 = X[i0 * M + j1];
-            const float x10 = X[i1 * M + j0], x11 = X[i1 * M + j1];
-            corr += (1.f - fu) * ((1.f - fw) * x00 + fw * x01) + fu * ((1.f - fw) * x10 + fw * x11);
-        }
+        for (int l = 0; l < L; ++l)
+            tab[l] = make_float4(a.m[l], fmaf(a.dx[d], a.hs[l], a.base[l]), fmaf(a.dy[d], a.hs[l], a.base[l]), 0.f);
+        const float corr = los_sum<L>(a.layers + (size_t)f * L * M * M, tab, L, M, i, j);
         acc = {1.f, a.open_loop[((size_t)f * a.D + d) * (size_t)n * n + e] - corr, 0.f};
     }
     for (int o = 1; o < 64; o <<= 1) {

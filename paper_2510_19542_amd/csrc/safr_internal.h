@@ -36,6 +36,33 @@ struct RowArgs {
     int n, J, p0, rows_per_block;
 };
 
+// Sum over layers of the commands `lay` ([L][M][M]) sampled by periodic bilinear interpolation at
+// (u0 + m i, v0 + m j) for tab[l] = (m, u0, v0, -): the layered operator of Sec. 2 along one line of
+// sight at pixel (i, j).  M a power of two; LC > 0 fixes L at compile time (all samples issued at once).
+template <int LC>
+__device__ __forceinline__ float los_sum(const float* __restrict__ lay, const float4* __restrict__ tab, int L, int M,
+                                         int i, int j) {
+    const int mask = M - 1;
+    const int nl = LC > 0 ? LC : L;
+    float acc = 0.f;
+#pragma unroll
+    for (int l = 0; l < (LC > 0 ? LC : kMaxL); ++l) {
+        if (LC == 0 && l >= nl) break;
+        const float4 t = tab[l];
+        const float u = fmaf(t.x, (float)i, t.y);
+        const float w = fmaf(t.x, (float)j, t.z);
+        const float fu0 = floorf(u), fw0 = floorf(w);
+        const float fu = u - fu0, fw = w - fw0;
+        const int i0 = (int)fu0 & mask, j0 = (int)fw0 & mask;
+        const int i1 = (i0 + 1) & mask, j1 = (j0 + 1) & mask;
+        const float* X = lay + (size_t)l * M * M;
+        const float x00 = X[i0 * M + j0], x01 = X[i0 * M + j1];
+        const float x10 = X[i1 * M + j0], x11 = X[i1 * M + j1];
+        acc += (1.f - fu) * ((1.f - fw) * x00 + fw * x01) + fu * ((1.f - fw) * x10 + fw * x11);
+    }
+    return acc;
+}
+
 // Layer spectra after the inverse column transforms, in row tiles of 8:
 // C[f][l][p / 8][k][p % 8] (float2), so that a tile of 8 rows is contiguous.
 __host__ __device__ inline size_t c_index(int f, int l, int L, int M, int k, int p) {
