@@ -322,3 +322,21 @@ def test_autotune_picks_valid_shapes_and_keeps_results():
     S.safr_reconstruct_batched(plan, F, wf, out)
     torch.cuda.synchronize()
     assert rel_l2(out.cpu().numpy(), ref) <= 1e-6
+
+
+@pytest.mark.parametrize("case", ["C2", "C5-Mid"])
+def test_column_frames_grouping_does_not_change_results(case):
+    # the per-launch default of frames per column block, explicit groupings and one frame per block all
+    # transform every frame with the same arithmetic: bit-identical layers
+    torch = _torch()
+    S = _lib()
+    geo = CASES[case]()
+    plan = S.precompute_geometry(geo)
+    F = 40
+    x = torch.from_numpy(synth.random_wavefronts(geo, F)).cuda()
+    ref = S.reconstruct(plan, x)                              # adaptive default
+    for cf in (1, 3, 16, 64):
+        S.safr_set_option(plan, S.SAFR_OPT_COL_FRAMES, cf)
+        got = S.reconstruct(plan, x)
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref), (case, cf)
