@@ -139,6 +139,9 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
  * on other streams must not run meanwhile.  Synchronises `stream`.  Errors: SAFR_ERR_ARG (bad
  * parameters or map), SAFR_ERR_DEVICE; SAFR_ERR_NUMERIC if a non-finite value appears, after
  * which the plan's operator is undefined (destroy the plan).
+ * A refresh that must not hold up a running loop (or a change of the layer weights or of the
+ * asterism, which needs safr_precompute) can be built as a second plan on another stream while the
+ * current plan keeps serving, and the loop switches plans between two frames.
  */
 safr_status safr_update_alpha(safr_plan* p, double alpha, double alpha_tt, int filter, const double* alpha_weight,
                               hipStream_t stream);
