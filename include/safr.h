@@ -328,6 +328,11 @@ safr_status safr_trainer_add_frames(safr_trainer* t, int count, const void* zl, 
 /* Copies parameters in (and resets the Adam state) or out (host arrays of SAFR_MLP_PARAMS). */
 safr_status safr_trainer_set_params(safr_trainer* t, const float* params);
 safr_status safr_trainer_get_params(const safr_trainer* t, float* params);
+/* Adam state for checkpoints: first and second moments (host arrays of SAFR_MLP_PARAMS) and the
+ * number of steps taken (bias correction).  Set after set_params, which resets the state; the
+ * moments must be finite and the second moments >= 0. */
+safr_status safr_trainer_get_state(const safr_trainer* t, float* m, float* v, int* step);
+safr_status safr_trainer_set_state(safr_trainer* t, const float* m, const float* v, int step);
 /* One Adam step (lr; beta1 0.9, beta2 0.999, eps 1e-8) on the frames listed (host indices);
  * loss (may be NULL) receives the batch loss before the step (synchronises when requested). */
 safr_status safr_trainer_step(safr_trainer* t, int nb, const int* frames, float lr, double* loss,

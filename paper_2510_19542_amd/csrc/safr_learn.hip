@@ -346,6 +346,26 @@ safr_status safr_trainer_get_params(const safr_trainer* t, float* host) {
     return SAFR_OK;
 }
 
+safr_status safr_trainer_get_state(const safr_trainer* t, float* m, float* v, int* step) {
+    if (!t || !m || !v || !step) return lfail(SAFR_ERR_ARG, "NULL argument");
+    L_TRY(hipMemcpy(m, t->m, 8705 * sizeof(float), hipMemcpyDeviceToHost));
+    L_TRY(hipMemcpy(v, t->v, 8705 * sizeof(float), hipMemcpyDeviceToHost));
+    *step = t->step;
+    return SAFR_OK;
+}
+
+safr_status safr_trainer_set_state(safr_trainer* t, const float* m, const float* v, int step) {
+    if (!t || !m || !v) return lfail(SAFR_ERR_ARG, "NULL argument");
+    if (step < 0) return lfail(SAFR_ERR_ARG, "step must be >= 0");
+    for (int i = 0; i < 8705; ++i)
+        if (!std::isfinite(m[i]) || !std::isfinite(v[i]) || v[i] < 0.f)
+            return lfail(SAFR_ERR_ARG, "Adam moments must be finite (second moments >= 0)");
+    L_TRY(hipMemcpy(t->m, m, 8705 * sizeof(float), hipMemcpyHostToDevice));
+    L_TRY(hipMemcpy(t->v, v, 8705 * sizeof(float), hipMemcpyHostToDevice));
+    t->step = step;
+    return SAFR_OK;
+}
+
 safr_status safr_trainer_gradient(safr_trainer* t, int nb, const int* frames, float* grad, double* loss,
                                   hipStream_t s) {
     if (!t || !frames || nb < 1) return lfail(SAFR_ERR_ARG, "bad argument");

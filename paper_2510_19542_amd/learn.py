@@ -28,6 +28,8 @@ def _lib():
         L.safr_trainer_add_frames.argtypes = [vp, i, vp, vp, fp, vp]
         L.safr_trainer_set_params.argtypes = [vp, fp]
         L.safr_trainer_get_params.argtypes = [vp, fp]
+        L.safr_trainer_get_state.argtypes = [vp, fp, fp, ctypes.POINTER(i)]
+        L.safr_trainer_set_state.argtypes = [vp, fp, fp, i]
         L.safr_trainer_step.argtypes = [vp, i, ctypes.POINTER(i), ctypes.c_float, ctypes.POINTER(d), vp]
         L.safr_trainer_gradient.argtypes = [vp, i, ctypes.POINTER(i), fp, ctypes.POINTER(d), vp]
         L.safr_trainer_frames.argtypes = [vp]
@@ -36,7 +38,8 @@ def _lib():
         L.safr_trainer_destroy.restype = None
         L.safr_mlp_infer.argtypes = [fp, vp, i, d, vp, vp]
         for name in ("safr_trainer_create", "safr_trainer_add_frames", "safr_trainer_set_params",
-                     "safr_trainer_get_params", "safr_trainer_step", "safr_trainer_gradient", "safr_mlp_infer"):
+                     "safr_trainer_get_params", "safr_trainer_get_state", "safr_trainer_set_state",
+                     "safr_trainer_step", "safr_trainer_gradient", "safr_mlp_infer"):
             getattr(L, name).restype = ctypes.c_int
         L._learn_bound = True
     return L
@@ -112,6 +115,35 @@ class Trainer:
                                                 p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
         return p
 
+    def get_state(self):
+        """(first moments, second moments, steps taken) of Adam."""
+        m = np.empty(N_PARAMS, dtype=np.float32)
+        v = np.empty(N_PARAMS, dtype=np.float32)
+        n = ctypes.c_int()
+        fp = ctypes.POINTER(ctypes.c_float)
+        S._check(_lib().safr_trainer_get_state(ctypes.c_void_p(self.handle), m.ctypes.data_as(fp),
+                                               v.ctypes.data_as(fp), ctypes.byref(n)))
+        return m, v, int(n.value)
+
+    def set_state(self, m, v, step: int):
+        m = np.ascontiguousarray(np.asarray(m, dtype=np.float32))
+        v = np.ascontiguousarray(np.asarray(v, dtype=np.float32))
+        fp = ctypes.POINTER(ctypes.c_float)
+        S._check(_lib().safr_trainer_set_state(ctypes.c_void_p(self.handle), m.ctypes.data_as(fp),
+                                               v.ctypes.data_as(fp), int(step)))
+
+    def save(self, path: str, **meta):
+        """Checkpoint: parameters and Adam state (see save_checkpoint)."""
+        m, v, n = self.get_state()
+        save_checkpoint(path, self.get_params(), m, v, n, **meta)
+
+    def load(self, path: str):
+        """Restore a checkpoint written by save (parameters first: that resets the Adam state)."""
+        params, m, v, n, _ = load_checkpoint(path)
+        self.set_params(params)
+        if m is not None:
+            self.set_state(m, v, n)
+
     def step(self, frames, lr: float, want_loss: bool = False) -> Optional[float]:
         f = np.ascontiguousarray(np.asarray(frames, dtype=np.int32))
         loss = ctypes.c_double()
@@ -164,6 +196,39 @@ def train(geo, frames: int = 20000, epochs: int = 3, batch: int = 16, lr: float 
     params = tr.get_params()
     tr.close()
     return params, hist
+
+
+def save_checkpoint(path: str, params, m=None, v=None, step: int = 0, **meta):
+    """Flat little-endian float32 file `path` (parameters, then the Adam moments if given) and the JSON
+    metadata `path`.json (layout, sizes, step count and any caller fields)."""
+    import json
+    arrays = [np.asarray(params, dtype="<f4").ravel()]
+    if m is not None:
+        arrays += [np.asarray(m, dtype="<f4").ravel(), np.asarray(v, dtype="<f4").ravel()]
+    for a in arrays:
+        if a.size != N_PARAMS:
+            raise ValueError(f"expected {N_PARAMS} values, got {a.size}")
+    np.concatenate(arrays).tofile(path)
+    info = {"format": "safr learned-filter checkpoint", "dtype": "float32 little-endian",
+            "n_params": N_PARAMS, "blocks": ["params"] + (["adam_m", "adam_v"] if m is not None else []),
+            "param_shapes": [list(sh) for sh in SHAPES], "adam_step": int(step), "meta": meta}
+    with open(path + ".json", "w") as f:
+        json.dump(info, f, indent=1)
+
+
+def load_checkpoint(path: str):
+    """(params, adam_m or None, adam_v or None, adam_step, metadata) from save_checkpoint's files."""
+    import json
+    with open(path + ".json") as f:
+        info = json.load(f)
+    if info.get("n_params") != N_PARAMS:
+        raise ValueError("checkpoint holds a different network")
+    flat = np.fromfile(path, dtype="<f4")
+    blocks = info["blocks"]
+    if flat.size != N_PARAMS * len(blocks):
+        raise ValueError("checkpoint size does not match its metadata")
+    parts = {b: flat[i * N_PARAMS:(i + 1) * N_PARAMS].astype(np.float32) for i, b in enumerate(blocks)}
+    return parts["params"], parts.get("adam_m"), parts.get("adam_v"), int(info.get("adam_step", 0)), info["meta"]
 
 
 def mlp_infer(params, feats, rows: int, noise: float, phi, stream=None):

@@ -35,6 +35,7 @@ EXPORTED = [
     "safr_polc", "safr_loop_step", "safr_strehl", "safr_update_alpha",
     # learned filter (bound in learn.py)
     "safr_trainer_create", "safr_trainer_add_frames", "safr_trainer_set_params", "safr_trainer_get_params",
+    "safr_trainer_get_state", "safr_trainer_set_state",
     "safr_trainer_step", "safr_trainer_gradient", "safr_trainer_frames", "safr_trainer_destroy", "safr_mlp_infer",
 ]
 

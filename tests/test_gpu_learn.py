@@ -104,3 +104,39 @@ def test_learned_filter_beats_tikhonov_on_heldout_frames():
             el.append(np.linalg.norm(rl - rl.mean(axis=(1, 2), keepdims=True) - tz) / np.linalg.norm(tz))
         print(f"eta {eta}: Tikhonov(alpha={geo.alpha}) {np.mean(et):.4f}  learned {np.mean(el):.4f}")
         assert np.mean(el) < np.mean(et)
+
+
+def test_checkpoint_resume_continues_training_identically(tmp_path):
+    """Training resumed from a checkpoint (parameters + Adam state) follows the uninterrupted run."""
+    torch, S, Lrn = _mods()
+    geo = synth.preset("C1")
+    amp = synth.vk_amplitude(geo).reshape(geo.L, -1)
+    batches = [[0, 3, 5], [1, 2, 7], [4, 6, 0], [2, 5, 3], [7, 1, 6]]
+    a = Lrn.Trainer(geo, amp, 8)
+    Lrn.add_seeded_frames(a, 200, 8)
+    a.set_params(synth.mlp_init(5))
+    for b in batches[:2]:
+        a.step(b, 2e-3)
+    path = str(tmp_path / "ckpt.bin")
+    a.save(path, geometry="C1", note="after two steps")
+    for b in batches[2:]:
+        a.step(b, 2e-3)
+    want = a.get_params()
+    _, _, n_a = a.get_state()
+    a.close()
+    b_ = Lrn.Trainer(geo, amp, 8)
+    Lrn.add_seeded_frames(b_, 200, 8)
+    b_.load(path)
+    m, v, n = b_.get_state()
+    assert n == 2 and np.all(v >= 0.0) and np.any(m != 0.0)
+    for b in batches[2:]:
+        b_.step(b, 2e-3)
+    got = b_.get_params()
+    _, _, n_b = b_.get_state()
+    b_.close()
+    assert n_a == n_b == 5
+    assert np.array_equal(got, want)
+    # a parameters-only checkpoint restarts Adam
+    Lrn.save_checkpoint(str(tmp_path / "p.bin"), want)
+    p, m0, v0, n0, meta = Lrn.load_checkpoint(str(tmp_path / "p.bin"))
+    assert np.array_equal(p, want) and m0 is None and v0 is None and n0 == 0 and meta == {}
