@@ -1,0 +1,91 @@
+"""Per-stage parity (white box): the intermediates a batched call leaves in the caller's workspace.
+
+After safr_reconstruct_batched the workspace holds, at offset 0, the row spectra
+R[f][star][k][row] (complex64, k = 0..M/2, the n pupil rows) of the transformed
+stars, and after them the layer spectra after the inverse column transforms,
+C[f][l][p / 8][k][p % 8] (complex64, row tiles of 8, columns k < M/2; the 1/M^2
+of IDFT2 is included).  Each is compared with what the oracle's steps give:
+* R: the DFT along the second grid axis of the zero-extended, pupil-masked rows
+  (numpy's FFT of the rows, a library primitive);
+* C: the oracle's B applied to the oracle's DFT2 of the prepared data (tip/tilt
+  removed for the laser stars of a mixed asterism), then the inverse DFT along the
+  first axis scaled by 1/M^2.
+Tolerance: relative L2 1e-5 per frame and star or layer (FP32 against FP64).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import safr as O
+
+pytestmark = pytest.mark.gpu
+
+
+def _mods():
+    import torch
+    from paper_2510_19542_amd import safr as S
+    assert torch.cuda.is_available()
+    S.lib()
+    return torch, S
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def _small_mixed():
+    rng = np.random.default_rng(77)
+    M, n, pitch = 32, 19, 0.5
+    stars = [(float(x), float(y), k) for (x, y), k in zip(rng.uniform(-3e-5, 3e-5, (5, 2)), (1, 1, 1, 0, 0))]
+    h = np.array([0.0, 3000.0, 8000.0])
+    return synth.Geometry(name="stage-mixed", n=n, M=M, pitch=pitch, diameter=(n - 1) * pitch, obstruction=0.2,
+                          stars=stars, h_lgs=90e3, heights=h, weights=np.array([0.6, 0.3, 0.1]), alpha=1e-3,
+                          alpha_tt=1e-3, beta=1.5, truth_heights=h, truth_fracs=np.array([0.6, 0.3, 0.1]),
+                          r0=0.15, L0=25.0, eta=0.01, config_id=177)
+
+
+CASES = {"C1": lambda: synth.preset("C1"), "C2": lambda: synth.preset("C2"), "m32-mixed": _small_mixed}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_row_and_column_pass_intermediates(case):
+    torch, S = _mods()
+    geo = CASES[case]()
+    plan = S.precompute_geometry(geo)
+    ref = O.precompute_geometry(geo)
+    F = 2
+    wf = synth.frames(geo, F, first=4)
+    x = torch.from_numpy(wf).cuda()
+    need = S.safr_workspace_size(plan, F)
+    ws = torch.zeros(need + 256, dtype=torch.uint8, device="cuda")
+    base = (int(ws.data_ptr()) + 255) & ~255
+    off = base - int(ws.data_ptr())
+    S.safr_set_workspace(plan, base, need)
+    out = torch.empty((F, geo.L, geo.M, geo.M), device="cuda")
+    S.safr_reconstruct_batched(plan, F, x, out)
+    torch.cuda.synchronize()
+    raw = ws[off:off + need].cpu().numpy()
+    S.safr_set_workspace(plan, 0, 0)
+
+    M, n, J, L = geo.M, geo.n, geo.J, geo.L
+    Kh = M // 2 + 1
+    p0 = (M - n + 1) // 2
+    pupil = ref.pupil
+    grp = ref.groups[0]                                     # the transformed group (laser stars when mixed)
+    r_bytes = F * J * Kh * n * 8
+    R = raw[:r_bytes].view(np.complex64).reshape(F, J, Kh, n)
+    r_end = (r_bytes + 255) // 256 * 256
+    C = raw[r_end:r_end + F * L * Kh * M * 8].view(np.complex64).reshape(F, L, M // 8, Kh, 8)
+    for f in range(F):
+        for g in grp.stars:
+            ext = np.zeros((n, M))
+            ext[:, p0:p0 + n] = np.where(pupil, wf[f, g].astype(np.float64), 0.0)
+            want = np.fft.fft(ext, axis=1)[:, :Kh].T          # [k][row]
+            assert rel(R[f, g], want) <= 1e-5, (case, f, g, rel(R[f, g], want))
+        psi = np.stack([O.prepare(wf[f, g].astype(np.float64), pupil, grp.tt_mode) for g in grp.stars])
+        b = O.apply_B(grp.B, O.dft2(O.zero_extend(psi, M)))    # [l][j][k]
+        want_c = np.fft.ifft(b, axis=1) / M                     # inverse along j, times 1/M^2 overall
+        got_c = C[f].transpose(0, 1, 3, 2).reshape(L, M, Kh)      # [l][p][k]
+        for l in range(L):
+            e = rel(got_c[l][:, :M // 2], want_c[l][:, :M // 2])
+            assert e <= 1e-5, (case, f, l, e)
