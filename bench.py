@@ -165,6 +165,19 @@ def run_loop(S, torch, plan, geo, pool, calls):
         ms = _timed(lambda: S.safr_loop_step(plan, 1, wf, a, gain, a, s), calls, s, torch)
         res[f"us_per_step_{name}"] = round(ms * 1000.0, 3)
     S.safr_set_option(plan, S.SAFR_OPT_GRAPH, 0)
+    # per-step latency (events around every eager step): tail against the 1 ms period of a 1 kHz loop
+    nstep = 1000
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nstep)]
+    torch.cuda.synchronize()
+    for e0, e1 in ev:
+        e0.record(cur)
+        S.safr_loop_step(plan, 1, wf, a, gain, a, cur)
+        e1.record(cur)
+    torch.cuda.synchronize()
+    lat = np.array([e0.elapsed_time(e1) * 1000.0 for e0, e1 in ev])
+    res["per_step_latency_us"] = {"steps": nstep, "p50": round(float(np.percentile(lat, 50)), 2),
+                                  "p99": round(float(np.percentile(lat, 99)), 2), "max": round(float(lat.max()), 2),
+                                  "over_1ms": int((lat > 1000.0).sum())}
     out = torch.empty_like(wf)
     ms = _timed(lambda: S.safr_polc(plan, 1, wf, a, 1.0, out, cur), calls, cur, torch)
     res["us_per_polc_call"] = round(ms * 1000.0, 3)
