@@ -91,6 +91,8 @@ CASES = {
     "m32-full-grid": lambda: _small(32, 32, (0, 0, 0), L=2, seed=6),
     "m64-mixed-L5": lambda: _small(64, 31, (1, 1, 1, 1, 0, 0, 0), L=5, seed=7),
     "m32-n1": lambda: _small(32, 1, (0, 0), L=1, seed=8),
+    "m256-ngs-L3-generic": lambda: _small(256, 61, (0, 0, 0), L=3, seed=9, pitch=0.5),
+    "m128-mixed-L4": lambda: _small(128, 45, (1, 1, 1, 0, 0), L=4, seed=10, obstruction=0.1),
 }
 
 
