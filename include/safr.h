@@ -10,6 +10,7 @@
  *     s_l(n)    = gamma_l^(1/2) / c_l (1 + pi^2 |n|^2 / (c_l T)^2)^(-beta/2)
  *     A_n = U S V^H,  B_n[l, g] = s_l(n) sum_r V[l, r] g(S_rr) conj(U[g, r]),
  *     Tikhonov filter g(s) = s / (s^2 + alpha)                              (Sec. 3.1)
+ *     (or truncation, a learned filter, and optionally alpha weighted per frequency)
  *   hard real time (Alg. 1): d_g = fft2(Psi_g) for the J guide-star wavefronts,
  *     b_l(n) = sum_g B_n[l, g] d_g(n), Phi_l = ifft2(b_l) for the L layers.
  *
@@ -28,10 +29,17 @@
  *     that plane and reconstructed with alpha_tt; the natural-star layers are
  *     resampled bilinearly (periodic) onto the laser layer grids and added.
  *
+ * Also: the closed-loop step of Alg. 3 (POLC and the integrator around the
+ * reconstruction), a Strehl estimate (Marechal, Sec. 4), refreshes of the filter
+ * without a new SVD, plan bundles for mixed sizes, an autotuner, and the trainer
+ * of the learned filter.
+ *
  * Memory: every data pointer passed to a reconstruct call is device memory
- * owned by the caller.  A plan owns B and a single-frame workspace.  Calls on a
- * plan are stream ordered on the stream given; reconstruct calls neither
- * allocate nor synchronise.  A plan may be used from one thread at a time.
+ * owned by the caller.  A plan owns B (and the per-frequency SVDs it was built
+ * from) and a single-frame workspace.  Calls on a plan are stream ordered on the
+ * stream given; reconstruct and loop-step calls neither allocate nor synchronise
+ * (unless the debug option SAFR_OPT_CHECK_FINITE is on).  A plan may be used from
+ * one thread at a time.
  * No C++ exception crosses this interface; errors are returned as negative
  * safr_status values and described by safr_last_error() (thread local).
  */
