@@ -49,7 +49,8 @@ struct OutShape {
     static constexpr int TPF = RT / 2;                              // row pairs (teams) per frame
     static constexpr int NF = NTEAM / TPF;                          // frames per iteration
     static constexpr int V4 = RT * M / (4 * 256);                   // 4-pixel groups per thread per frame
-    static constexpr int RUN4 = RT * Kh / 2;                        // float4 loads per frame
+    static constexpr int TILE4 = 4 * (M / 2);                       // float4 of one row tile, columns k < M/2
+    static constexpr int RUN4 = (RT / 8) * TILE4;                   // float4 loads per frame
     static constexpr int NLD = (NF * RUN4 + 255) / 256;             // float4 loads per thread per iteration
     static_assert(TPF <= NTEAM && NTEAM % TPF == 0, "row pairs must tile the teams");
     static_assert(V4 >= 1 && (RT * M) % 1024 == 0, "at least one 4-pixel group per thread");
@@ -83,30 +84,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void o
     float2* reg = tws + M + team * RS;                              // this team's region
     float* coef = reinterpret_cast<float*>(tws + M + O::NTEAM * RS); // [NF][nb]
 
-    // spectra of frame f: RT rows of layer l = one run of RT * Kh float2 (two float2 per float4)
+    // spectra of frame f: RT / 8 row tiles of layer l, each Kh * 8 float2 (two float2 per float4); the
+    // Nyquist column k = M/2 is neither written by the column pass nor read here
     auto run = [&](int f) {
         return reinterpret_cast<const float4*>(a.C + (((size_t)f * L + l) * (M / 8) + r0 / 8) * Kh * 8);
     };
+    constexpr bool EXACT = NF * O::RUN4 % 256 == 0;
     float4 ld[O::NLD];
     auto issue = [&](int fi0) {
 #pragma unroll
         for (int i = 0; i < O::NLD; ++i) {
             const int e = tid + 256 * i;
             const int fi = e / O::RUN4, s = e - fi * O::RUN4;
+            const int pb = s / O::TILE4, s4 = s - pb * O::TILE4;
             const int f = fi0 + fi;
-            ld[i] = (e < NF * O::RUN4 && f < fend) ? run(f)[s] : make_float4(0.f, 0.f, 0.f, 0.f);
+            ld[i] = ((EXACT || e < NF * O::RUN4) && f < fend) ? run(f)[pb * 4 * Kh + s4]
+                                                             : make_float4(0.f, 0.f, 0.f, 0.f);
         }
     };
     auto stash = [&]() {
 #pragma unroll
         for (int i = 0; i < O::NLD; ++i) {
             const int e = tid + 256 * i;
-            if (e >= NF * O::RUN4) break;
+            if (!EXACT && e >= NF * O::RUN4) break;
             const int fi = e / O::RUN4, s = e - fi * O::RUN4;
-            // float2 index 2s -> tile, k, row pair
-            const int pb = (2 * s) / (Kh * 8), rem = (2 * s) - pb * Kh * 8;
-            const int k = rem >> 3, rr = rem & 7;
-            const int task = fi * TPF + (pb * 8 + rr) / 2;
+            // float4 s4 of tile pb: column k = s4 / 4, rows 2 (s4 % 4) and 2 (s4 % 4) + 1 of the tile
+            const int pb = s / O::TILE4, s4 = s - pb * O::TILE4;
+            const int k = s4 >> 2;
+            const int task = fi * TPF + pb * 4 + (s4 & 3);
             float2* dst = smem + M + task * RS;
             dst[k] = make_float2(ld[i].x, ld[i].y);
             dst[Kh + k] = make_float2(ld[i].z, ld[i].w);
