@@ -127,7 +127,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void o
     for (int f0 = fbeg; f0 < fend; f0 += NF) {
         __syncthreads();                                    // previous epilogue done with the regions
         stash();
-        if (f0 + NF < fend) issue(f0 + NF);
         // natural stars' plane sums of this iteration's frames: requested now, reduced before the epilogue
         const PlaneArgs pa{a.mom, a.J, a.nchunk, a.nb / 2, f0, fend, min(NF, fend - f0) * (a.nb / 2)};
         float4 part[PMAX];
@@ -171,6 +170,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void o
             });
         }
         // natural stars' plane coefficients (b_g, c_g) of this iteration's frames, [NF][ng] as float2
+        if (f0 + NF < fend) issue(f0 + NF);
         if constexpr (MIXED) plane_finish<PMAX>(pa, star_of, part, a.tt_b, a.tt_c, reinterpret_cast<float2*>(coef));
         __syncthreads();
 
