@@ -15,8 +15,9 @@
 // turn, its two input rows (Hermitian half spectra), the pass-1 -> pass-2
 // exchange and its two output rows; loads of a phase are taken into registers
 // and a barrier separates them from the stores that overwrite the region.  The
-// next iteration's spectra are loaded into registers while the current one is
-// transformed.  The epilogue is pixel-stationary (thread -> 4-pixel groups of
+// next iteration's spectra are requested once the current rows are transformed
+// and arrive while the epilogue runs (requested before the transforms, they
+// were slower).  The epilogue is pixel-stationary (thread -> 4-pixel groups of
 // the block's rows): a group's basis pixels are read once per iteration (from
 // L2: the blocks of one row tile are XCD-contiguous) and serve its NF frames.
 // The kernel targets three wavefronts per SIMD; holding the basis pixels in
