@@ -4,8 +4,10 @@
 // only the n pupil rows are transformed; two real rows are packed into one
 // complex M-point FFT (z = a + i b) and separated afterwards with
 // A[k] = (Z[k] + conj Z[-k]) / 2,  B[k] = (Z[k] - conj Z[-k]) / (2 i).
-// Output: R[f][star][k][row] for k = 0..M/2 (half spectrum), rows contiguous so
-// the column pass reads each column as one run.
+// Output: R[f][star][k][row] for k < M/2 (the half spectrum without its Nyquist
+// column, which B ignores; R keeps a slot for it), rows contiguous so the column
+// pass reads each column as one run.  Each team takes its two rows from global
+// memory straight into the registers of the first transform pass.
 //
 // Split tomography (Sec. 3.3) needs the least-squares tip/tilt plane of each
 // wavefront over the pupil.  Each block writes the partial moments
@@ -18,11 +20,12 @@
 namespace safr {
 
 template <int M>
-__global__ void rows_kernel(RowArgs a) {
+__global__ __launch_bounds__(256) void rows_kernel(RowArgs a) {
     using S = FftShape<M>;
-    constexpr int T = S::T;
+    constexpr int T = S::T, N1 = S::N1, N2 = S::N2;
     constexpr int Kh = M / 2 + 1;
-    constexpr int TL = team_lds<M>();
+    constexpr int KC = M / 2;                       // columns written: the Nyquist column is not used
+    constexpr int TS = team_lds<M>() + 2;           // team region stride, 4 banks apart
     extern __shared__ float2 smem[];
 
     const int n = a.n;
@@ -35,55 +38,56 @@ __global__ void rows_kernel(RowArgs a) {
     const int nthr = blockDim.x;
     const int team = tid / T;
     const int t = tid % T;
-    const int nteams = a.rows_per_block / 2;
+    const int nteams = a.rows_per_block / 2;       // one row pair per team: the chunk is one round
     const int mode = a.tt_mode[star];
     const float* wf = a.wf + ((size_t)f * a.J + star) * (size_t)n * n + (size_t)r0 * n;
     const unsigned char* pup = a.pupil + (size_t)r0 * n;
 
-    // LDS: twiddles [M], then one region per team (stride TS, 4 banks apart) that holds in turn the
-    // pass-1 -> pass-2 exchange and the packed spectrum, then the staged rows, then 3 floats per
-    // wavefront for the moment reduction
-    constexpr int TS = TL + 2;
+    // LDS: twiddles [M], one region per team (the pass-1 -> pass-2 exchange, then the packed spectrum),
+    // 3 floats per wavefront for the moment reduction
     float2* tws = smem;
     float2* xch = smem + M + team * TS;
-    float* vals = reinterpret_cast<float*>(smem + M + nteams * TS);
-    float* red = vals + a.rows_per_block * n;
+    float* red = reinterpret_cast<float*>(smem + M + nteams * TS);
 
-    // stage the block's rows (pupil-masked): all loads of a chunk are issued before any is used
-    const float half = 0.5f * (float)(n - 1);
-    float m0 = 0.f, m1 = 0.f, m2 = 0.f;
-    const int total = rows * n;
-    for (int i = tid; i < M; i += nthr) tws[i] = a.tw[i];
-    constexpr int CH = 8;
-    for (int base = 0; base < total; base += CH * nthr) {
-        float v[CH];
-        unsigned char m[CH];
+    // the team's two pupil-masked rows straight into the pass-1 registers: x[n1] = (row a, row b) at grid
+    // column N2 n1 + t, i.e. pupil column N2 n1 + t - p0 (all loads issued before any is used)
+    const int ra = 2 * team;
+    const bool active = team < nteams && ra < rows;
+    const bool has_b = active && ra + 1 < rows;
+    const float* wa = wf + (size_t)ra * n;
+    const unsigned char* pa = pup + (size_t)ra * n;
+    float2 x[N1];
 #pragma unroll
-        for (int u = 0; u < CH; ++u) {
-            const int i = base + tid + u * nthr;
-            if (i < total) {
-                m[u] = pup[i];
-                v[u] = wf[i];
+    for (int n1 = 0; n1 < N1; ++n1) {
+        const int qc = N2 * n1 + t - a.p0;
+        const bool in = active && qc >= 0 && qc < n;
+        float va = 0.f, vb = 0.f;
+        unsigned char ma = 0, mb = 0;
+        if (in) {
+            ma = pa[qc];
+            va = wa[qc];
+            if (has_b) {
+                mb = pa[n + qc];
+                vb = wa[n + qc];
             }
         }
-#pragma unroll
-        for (int u = 0; u < CH; ++u) {
-            const int i = base + tid + u * nthr;
-            if (i < total) {
-                const float val = m[u] ? v[u] : 0.f;
-                vals[i] = val;
-                if (mode != 0) {
-                    const int pr = i / n;
-                    const float x = (float)(r0 + pr) - half;
-                    const float y = (float)(i - pr * n) - half;
-                    m0 += val;
-                    m1 += x * val;
-                    m2 += y * val;
-                }
-            }
-        }
+        x[n1] = make_float2(ma ? va : 0.f, mb ? vb : 0.f);
     }
+    for (int i = tid; i < M; i += nthr) tws[i] = a.tw[i];   // blocks may have fewer than M threads
+
     if (mode != 0) {
+        // partial moments (sum v, sum x v, sum y v) of the chunk, coordinates about the pupil centre
+        const float half = 0.5f * (float)(n - 1);
+        const float xa = (float)(r0 + ra) - half, xb = xa + 1.f;
+        float m0 = 0.f, m1 = 0.f, m2 = 0.f;
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) {
+            const float y = (float)(N2 * n1 + t - a.p0) - half;
+            const float s = x[n1].x + x[n1].y;
+            m0 += s;
+            m1 = fmaf(xa, x[n1].x, fmaf(xb, x[n1].y, m1));
+            m2 = fmaf(y, s, m2);
+        }
         for (int o = 32; o > 0; o >>= 1) {
             m0 += __shfl_xor(m0, o, 64);
             m1 += __shfl_xor(m1, o, 64);
@@ -111,47 +115,37 @@ __global__ void rows_kernel(RowArgs a) {
         }
     }
     if (mode == 2) return;          // natural star of a mixed asterism: only its plane is used
+    __syncthreads();                // twiddles visible
+
+    if (active) fft_pass1_regs<M, -1>(t, xch, tws, x);
+    __syncthreads();
+    float2 zr[N1 / T][N2];
+    if (active) fft_pass2_load<M>(t, xch, zr);
+    __syncthreads();
+    if (active) fft_pass2_regs<M, -1>(t, zr, [&](int k, float2 v) { xch[k] = v; });
     __syncthreads();
 
-    const int pairs = (rows + 1) / 2;
-    float2* Rb = a.R + ((size_t)f * a.J + star) * (size_t)Kh * n;
-    for (int base = 0; base < pairs; base += nteams) {
-        const int pair = base + team;
-        const bool active = team < nteams && pair < pairs;
-        const int ra = 2 * pair;
-        const bool has_b = active && (ra + 1 < rows);
-        if (active) {
-            const float* va = vals + ra * n;
-            const float* vb = vals + (has_b ? ra + 1 : ra) * n;
-            fft_pass1<M, -1>(t, xch, tws, [&](int q) -> float2 {
-                const int qc = q - a.p0;
-                if (qc < 0 || qc >= n) return make_float2(0.f, 0.f);
-                return make_float2(va[qc], has_b ? vb[qc] : 0.f);
-            });
-        }
-        __syncthreads();
-        float2 zr[S::N1 / T][S::N2];
-        if (active) fft_pass2_load<M>(t, xch, zr);
-        __syncthreads();
-        if (active) fft_pass2_regs<M, -1>(t, zr, [&](int k, float2 v) { xch[k] = v; });
-        __syncthreads();
-        // separate the two real rows and write the half spectrum, rows contiguous
-        const int nrow = min(2 * nteams, rows - 2 * base);
-        for (int idx = tid; idx < Kh * nrow; idx += nthr) {
-            const int k = idx / nrow;
-            const int r = idx - k * nrow;
-            const float2* z = smem + M + (r >> 1) * TS;
+    // separate the two real rows of each pair, A = (Z[k] + conj Z[-k]) / 2, B = (Z[k] - conj Z[-k]) / 2i,
+    // and write the half spectrum k < M/2, rows contiguous; thread -> (k, pair) over a power-of-two
+    // number of pair slots
+    int lg = 0;
+    while ((1 << lg) < nteams) ++lg;
+    const int npair = (rows + 1) / 2;
+    float2* Rb = a.R + ((size_t)f * a.J + star) * (size_t)Kh * n + r0;
+    for (int idx = tid; idx < (KC << lg); idx += nthr) {
+        const int k = idx >> lg;
+        const int pr = idx & ((1 << lg) - 1);
+        if (pr < npair) {
+            const float2* z = smem + M + pr * TS;
             const float2 zk = z[k];
             const float2 zm = cconj(z[(M - k) & (M - 1)]);
-            float2 v;
-            if ((r & 1) == 0) v = cscale(cadd(zk, zm), 0.5f);
-            else {
+            float2* dst = Rb + (size_t)k * n + 2 * pr;
+            dst[0] = cscale(cadd(zk, zm), 0.5f);
+            if (2 * pr + 1 < rows) {
                 const float2 d = csub(zk, zm);
-                v = make_float2(0.5f * d.y, -0.5f * d.x);
+                dst[1] = make_float2(0.5f * d.y, -0.5f * d.x);
             }
-            Rb[(size_t)k * n + r0 + 2 * base + r] = v;
         }
-        __syncthreads();
     }
 }
 
@@ -176,9 +170,9 @@ hipError_t launch_rows(int M, const RowArgs& a, int frames, int nchunk, int team
 }
 
 size_t rows_lds_bytes(int M, int n, int teams) {
+    (void)n;
     const int N1 = M == 32 ? 8 : (M == 64 ? 8 : 16), N2 = M / N1;
-    return ((size_t)M + (size_t)teams * (N1 * (N2 + 1) + 2)) * sizeof(float2) +
-           (size_t)(2 * teams) * n * sizeof(float) + 64 * sizeof(float);
+    return ((size_t)M + (size_t)teams * (N1 * (N2 + 1) + 2)) * sizeof(float2) + 64 * sizeof(float);
 }
 
 }  // namespace safr
