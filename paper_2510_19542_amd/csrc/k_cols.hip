@@ -164,12 +164,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
         // the first round's forward inputs; each later round's are requested after the previous
         // round's first pass, so at most two rounds of inputs are held at once
         if constexpr (FIX) load_fwd(f0, 0, xf[0]);
-        // tip/tilt plane sums of this iteration's frames, requested now and reduced after the forward transforms
-        const PlaneArgs pa{a.mom, a.J, a.nchunk, G, f0, fend, min(NF, fend - f0) * G};
+        // tip/tilt plane coefficients of this iteration's frames, requested now and stored after the
+        // forward transforms
+        const PlaneArgs pa{a.planes, a.J, G, f0, fend, min(NF, fend - f0) * G};
         auto star_of = [&](int g) { return gr.star[g]; };
-        constexpr int PMAX = 2;
-        float4 part[PMAX];
-        if (MODE != 0) plane_gather<PMAX>(pa, star_of, part);
+        float2 pl[1];
+        if (MODE != 0) plane_fetch<1>(pa, star_of, pl);
         __syncthreads();                                        // previous inverse transforms done with the slots
         // 1. forward column transforms into the star slots
         const int frounds = FIX ? FR_MAX : (ftasks + NTEAM - 1) / NTEAM;
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
             }
         }
         // tip/tilt plane coefficients of this iteration's frames (used by the apply, after the barrier)
-        if (MODE != 0) plane_finish<PMAX>(pa, star_of, part, a.tt_b, a.tt_c, coef);
+        if (MODE != 0) plane_put<1>(pa, star_of, pl, coef);
         __syncthreads();
 
         // 2. apply: b_l(j) = sum_g B[l][g][j] d_g(j) for the NF frames

@@ -98,11 +98,11 @@ __global__ __launch_bounds__(256) void cols_mfma_kernel(MfmaArgs a) {
 
     for (int i = tid; i < M; i += 256) tws[i] = a.tw[i];
     if (mode != 0) {
-        const PlaneArgs pa{a.mom, a.J, a.nchunk, G, fb, fb + nf, nf * G};   // nf = valid frames of the block
+        const PlaneArgs pa{a.planes, a.J, G, fb, fb + nf, nf * G};   // nf = valid frames of the block
         auto star_of = [&](int g) { return gr.star[g]; };
-        float4 part[2];
-        plane_gather<2>(pa, star_of, part);
-        plane_finish<2>(pa, star_of, part, a.tt_b, a.tt_c, coef);
+        float2 pl[1];
+        plane_fetch<1>(pa, star_of, pl);
+        plane_put<1>(pa, star_of, pl, coef);
     }
     __syncthreads();
 

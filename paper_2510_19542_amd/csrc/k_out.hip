@@ -124,14 +124,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void o
     if (tid < M) tws[tid] = twv;
 
     auto star_of = [&](int g) { return a.ngs_star[g]; };
-    constexpr int PMAX = 1;                                 // rounds of natural-star plane sums held in registers
     for (int f0 = fbeg; f0 < fend; f0 += NF) {
         __syncthreads();                                    // previous epilogue done with the regions
         stash();
-        // natural stars' plane sums of this iteration's frames: requested now, reduced before the epilogue
-        const PlaneArgs pa{a.mom, a.J, a.nchunk, a.nb / 2, f0, fend, min(NF, fend - f0) * (a.nb / 2)};
-        float4 part[PMAX];
-        if constexpr (MIXED) plane_gather<PMAX>(pa, star_of, part);
+        // natural stars' plane coefficients of this iteration's frames: requested now, stored before the
+        // epilogue
+        const PlaneArgs pa{a.planes, a.J, a.nb / 2, f0, fend, min(NF, fend - f0) * (a.nb / 2)};
+        float2 pl[1];
+        if constexpr (MIXED) plane_fetch<1>(pa, star_of, pl);
         __syncthreads();
 
         // packed C2R: Z[q] = A[q] + i B[q] over the Hermitian extensions of the team's two rows
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void o
         }
         // natural stars' plane coefficients (b_g, c_g) of this iteration's frames, [NF][ng] as float2
         if (f0 + NF < fend) issue(f0 + NF);
-        if constexpr (MIXED) plane_finish<PMAX>(pa, star_of, part, a.tt_b, a.tt_c, reinterpret_cast<float2*>(coef));
+        if constexpr (MIXED) plane_put<1>(pa, star_of, pl, reinterpret_cast<float2*>(coef));
         __syncthreads();
 
         // epilogue: 4-pixel groups, coalesced stores; a group's basis pixels are read (from L2) once per

@@ -11,9 +11,11 @@
 //
 // Split tomography (Sec. 3.3) needs the least-squares tip/tilt plane of each
 // wavefront over the pupil.  Each block writes the partial moments
-// (sum v, sum x v, sum y v) of its own rows; the column pass adds them up and
-// removes (laser stars) or keeps only (natural stars) the plane in the Fourier
-// domain.  Natural stars of a mixed asterism therefore need no row transform.
+// (sum v, sum x v, sum y v) of its own rows; plane_kernel adds them up once per
+// (frame, star) and forms the plane coefficients, which the column pass uses to
+// remove the plane of the laser stars in the Fourier domain and the output pass
+// to add the natural stars' layers.  Natural stars of a mixed asterism
+// therefore need no row transform.
 #include "fft_device.h"
 #include "safr_internal.h"
 
@@ -147,6 +149,41 @@ __global__ __launch_bounds__(256) void rows_kernel(RowArgs a) {
             }
         }
     }
+}
+
+// One wavefront per (frame, star): the least-squares plane of Sec. 3.3 from the chunk moments.  Lane q
+// adds chunks q, q + 64, ... (all loads in flight together), then a fixed shuffle tree sums the lanes,
+// so every call adds in the same order.
+__global__ __launch_bounds__(256) void plane_kernel(PlaneKArgs a) {
+    const int i = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= a.count) return;                       // whole wavefronts leave together
+    if (a.tt_mode[i % a.J] == 0) {
+        if (lane == 0) a.planes[i] = make_float2(0.f, 0.f);
+        return;
+    }
+    const float4* mo = reinterpret_cast<const float4*>(a.mom) + (size_t)i * a.nchunk;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+    for (int q = lane; q < a.nchunk; q += 64) {
+        const float4 v = mo[q];
+        s0 += v.x;
+        s1 += v.y;
+        s2 += v.z;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        s0 += __shfl_xor(s0, o, 64);
+        s1 += __shfl_xor(s1, o, 64);
+        s2 += __shfl_xor(s2, o, 64);
+    }
+    if (lane == 0)
+        a.planes[i] = make_float2(a.tt_b[0] * s0 + a.tt_b[1] * s1 + a.tt_b[2] * s2,
+                                  a.tt_c[0] * s0 + a.tt_c[1] * s1 + a.tt_c[2] * s2);
+}
+
+hipError_t launch_planes(const PlaneKArgs& a, hipStream_t s) {
+    if (a.count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(plane_kernel, dim3((a.count + 3) / 4), dim3(256), 0, s, a);
+    return hipGetLastError();
 }
 
 template <int M>

@@ -127,8 +127,12 @@ size_t ws_r(const safr_plan* p, int frames) { return align256((size_t)frames * p
 size_t ws_c(const safr_plan* p, int frames) {
     return align256((size_t)frames * p->L * p->Kh * p->M * sizeof(float2));
 }
-size_t ws_m(const safr_plan* p, int frames) {
+// (the moments, then the plane coefficients per frame and star)
+size_t ws_mom(const safr_plan* p, int frames) {
     return align256((size_t)frames * p->J * ((p->n + 1) / 2) * 4 * sizeof(float));
+}
+size_t ws_m(const safr_plan* p, int frames) {
+    return ws_mom(p, frames) + align256((size_t)frames * p->J * sizeof(float2));
 }
 // pseudo-open-loop wavefronts of the closed-loop step
 size_t ws_w(const safr_plan* p, int frames) { return align256((size_t)frames * p->J * p->n * p->n * sizeof(float)); }
@@ -1311,6 +1315,7 @@ safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, in
     float2* R = reinterpret_cast<float2*>(base);
     float2* C = reinterpret_cast<float2*>(base + ws_r(p, frames));
     float* mom = reinterpret_cast<float*>(base + ws_r(p, frames) + ws_c(p, frames));
+    float2* planes = reinterpret_cast<float2*>(base + ws_r(p, frames) + ws_c(p, frames) + ws_mom(p, frames));
     RowArgs ra{};
     ra.wf = wf;
     ra.R = R;
@@ -1324,6 +1329,20 @@ safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, in
     ra.rows_per_block = 2 * p->row_teams;
     const int nchunk = (p->n + ra.rows_per_block - 1) / ra.rows_per_block;
     HIP_TRY(launch_rows(p->M, ra, frames, nchunk, p->row_teams, s));
+    if (p->mixed) {                     // split tomography: the planes of every (frame, star), once
+        PlaneKArgs pk{};
+        pk.mom = mom;
+        pk.planes = planes;
+        pk.tt_mode = p->tt_mode;
+        for (int i = 0; i < 3; ++i) {
+            pk.tt_b[i] = p->tt_b[i];
+            pk.tt_c[i] = p->tt_c[i];
+        }
+        pk.J = p->J;
+        pk.nchunk = nchunk;
+        pk.count = frames * p->J;
+        HIP_TRY(launch_planes(pk, s));
+    }
     if (ev) HIP_TRY(hipEventRecord(ev[1], s));
 
     GroupArgs grp{};
@@ -1336,13 +1355,9 @@ safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, in
         ca.B = p->B32 + p->boff32[0];
         ca.C = C;
         ca.tw = p->tw;
-        ca.mom = mom;
+        ca.planes = planes;
         ca.Xh = p->Xh;
         ca.Yh = p->Yh;
-        for (int i = 0; i < 3; ++i) {
-            ca.tt_b[i] = p->tt_b[i];
-            ca.tt_c[i] = p->tt_c[i];
-        }
         ca.grp = grp;
         ca.n = p->n;
         ca.J = p->J;
@@ -1360,7 +1375,6 @@ safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, in
             fpb = std::max(nf, per / nf * nf);
         }
         ca.frames_per_block = std::max(1, std::min(fpb, frames));
-        ca.nchunk = nchunk;
         ca.prefetch = p->col_prefetch;
         HIP_TRY(launch_cols(p->M, ca, nf, frames, s));
     } else {
@@ -1373,19 +1387,14 @@ safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, in
         ma.lt = p->mf_lt[0];
         ma.ntile = p->mf_ntile[0];
         ma.ppm = p->mf_ppm[0];
-        ma.mom = mom;
+        ma.planes = planes;
         ma.Xh = p->Xh;
         ma.Yh = p->Yh;
-        for (int i = 0; i < 3; ++i) {
-            ma.tt_b[i] = p->tt_b[i];
-            ma.tt_c[i] = p->tt_c[i];
-        }
         ma.n = p->n;
         ma.J = p->J;
         ma.L = p->L;
         ma.p0 = p->p0;
         ma.frames = frames;
-        ma.nchunk = nchunk;
         HIP_TRY(launch_cols_mfma(p->M, ma, frames, p->mfma_frames, s));
     }
     if (ev) HIP_TRY(hipEventRecord(ev[2], s));
@@ -1395,16 +1404,11 @@ safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, in
     oa.out = out;
     oa.tw = p->tw;
     oa.P = p->P;
-    oa.mom = mom;
-    for (int i = 0; i < 3; ++i) {
-        oa.tt_b[i] = p->tt_b[i];
-        oa.tt_c[i] = p->tt_c[i];
-    }
+    oa.planes = planes;
     oa.nb = p->nb;
     for (int m = 0; m < p->nb / 2; ++m) oa.ngs_star[m] = p->gstar[1][m];
     oa.L = p->L;
     oa.J = p->J;
-    oa.nchunk = nchunk;
     oa.frames = frames;
     oa.frames_per_block = std::max(1, p->out_frames);
     oa.prev = prev;

@@ -76,12 +76,11 @@ struct ColArgs {
     const float2* B;            // [column block][l][g][column in block][j] (FP32 complex)
     float2* C;                  // see c_index
     const float2* tw;
-    const float* mom;           // partial moments from the row pass
+    const float2* planes;       // tip/tilt plane coefficients per (frame, star), see PlaneArgs
     const float2* Xh;           // DFT2 of x * pupil, [Kh][M]
     const float2* Yh;           // DFT2 of y * pupil, [Kh][M]
-    float tt_b[3], tt_c[3];     // rows 1 and 2 of the inverse normal matrix of the fit of [1, x, y]
     GroupArgs grp;
-    int n, J, L, p0, frames, frames_per_block, nchunk;
+    int n, J, L, p0, frames, frames_per_block;
     int prefetch;               // 1 = compile-time shape (d in registers, inputs prefetched), when available
 };
 
@@ -92,11 +91,10 @@ struct OutArgs {
     float* out;                 // [F][L][M][M]
     const float2* tw;
     const float* P;             // [L][nb][M][M] natural-star basis images (mixed asterisms)
-    const float* mom;           // partial moments from the row pass
-    float tt_b[3], tt_c[3];
+    const float2* planes;       // tip/tilt plane coefficients per (frame, star), see PlaneArgs
     int ngs_star[kMaxG];        // star index of natural star g
     int nb;                     // 2 x natural stars (0: no natural-star part)
-    int L, J, nchunk, frames, frames_per_block;
+    int L, J, frames, frames_per_block;
     const float* prev;          // integrator (Alg. 3): out = (1 - gain) prev + gain layers; nullptr = plain
     float gain;
 };
@@ -146,12 +144,11 @@ struct MfmaArgs {
     const uint16_t* Apack;      // packed real-split B tiles, hi and lo (bf16 bit patterns)
     float2* C;
     const float2* tw;
-    const float* mom;
+    const float2* planes;       // tip/tilt plane coefficients per (frame, star), see PlaneArgs
     const float2* Xh;
     const float2* Yh;
-    float tt_b[3], tt_c[3];
     GroupArgs grp;
-    int n, J, L, p0, frames, nchunk;
+    int n, J, L, p0, frames;
     int lt;                     // layers per tile
     int ntile;                  // layer tiles
     int ppm;                    // frequencies packed per matrix op
@@ -170,76 +167,53 @@ struct BasisArgs {
     float* P;                   // [L][2 G][M][M]
 };
 
-// Tip/tilt plane coefficients of `count` (frame, star) pairs from the row pass's partial moments
-// mom[f][star][chunk] = (sum v, sum x v, sum y v, 0); pair i = (frame f0 + i / per, star
-// star_of(i % per)); frames at or beyond fend use fend - 1.  A wavefront sums 64 / seg pairs at a
-// time, seg = 1 for at most 8 chunks, else the smallest power of two >= min(nchunk, 64): lane l
-// takes chunks l % seg,
-// l % seg + seg, ... of pair (round * waves + wave) * (64 / seg) + l / seg.  plane_gather requests
-// the first PMAX rounds into registers (early), plane_finish reduces each segment with a fixed
-// shuffle tree (deterministic order), does any further rounds, and the segment's first lane writes
-// (b, c) = rows 1 and 2 of the inverse normal matrix times the sums to out[i].  Every thread of the
-// block calls both with the same arguments.
+// Tip/tilt plane coefficients (b, c) of every (frame, star) of a call, planes[f][star] (float2), formed
+// once by plane_kernel from the row pass's partial moments.  A pass needing those of `count` pairs,
+// pair i = (frame f0 + i / per, star star_of(i % per)), frames at or beyond fend using fend - 1,
+// requests them early with plane_fetch (thread i % blockDim takes pair i, PMAX rounds in registers)
+// and stores them to out[i] (LDS) with plane_put; pairs beyond PMAX rounds are copied there directly.
+// Every thread of the block calls both with the same arguments.
 struct PlaneArgs {
-    const float* mom;
-    int J, nchunk, per, f0, fend, count;
+    const float2* planes;
+    int J, per, f0, fend, count;
 };
 
-__device__ inline int plane_seg(int nchunk) {
-    if (nchunk <= 8) return 1;                  // few chunks: one lane per pair, no shuffles
-    int seg = 1;
-    while (seg < nchunk && seg < 64) seg <<= 1;
-    return seg;
-}
-
 template <class StarOf>
-__device__ inline float4 plane_lane(const PlaneArgs& p, StarOf star_of, int round, int seg) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, waves = (blockDim.x + 63) >> 6;
-    const int i = (round * waves + wave) * (64 / seg) + lane / seg;
-    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (i < p.count) {
-        const int f = min(p.f0 + i / p.per, p.fend - 1), g = star_of(i % p.per);
-        const float4* mo = reinterpret_cast<const float4*>(p.mom) + ((size_t)f * p.J + g) * p.nchunk;
-        for (int q = lane % seg; q < p.nchunk; q += seg) {
-            const float4 v = mo[q];
-            s.x += v.x;
-            s.y += v.y;
-            s.z += v.z;
-        }
-    }
-    return s;
-}
-
-__device__ inline void plane_write(const PlaneArgs& p, float4 s, int round, int seg, const float* tt_b,
-                                   const float* tt_c, float2* out) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, waves = (blockDim.x + 63) >> 6;
-    for (int o = seg >> 1; o > 0; o >>= 1) {
-        s.x += __shfl_xor(s.x, o, 64);
-        s.y += __shfl_xor(s.y, o, 64);
-        s.z += __shfl_xor(s.z, o, 64);
-    }
-    const int i = (round * waves + wave) * (64 / seg) + lane / seg;
-    if (lane % seg == 0 && i < p.count)
-        out[i] = make_float2(tt_b[0] * s.x + tt_b[1] * s.y + tt_b[2] * s.z, tt_c[0] * s.x + tt_c[1] * s.y + tt_c[2] * s.z);
+__device__ inline float2 plane_at(const PlaneArgs& p, StarOf star_of, int i) {
+    const int f = min(p.f0 + i / p.per, p.fend - 1);
+    return p.planes[(size_t)f * p.J + star_of(i % p.per)];
 }
 
 template <int PMAX, class StarOf>
-__device__ inline void plane_gather(const PlaneArgs& p, StarOf star_of, float4 (&part)[PMAX]) {
-    const int seg = plane_seg(p.nchunk);
+__device__ inline void plane_fetch(const PlaneArgs& p, StarOf star_of, float2 (&v)[PMAX]) {
 #pragma unroll
-    for (int u = 0; u < PMAX; ++u) part[u] = plane_lane(p, star_of, u, seg);
+    for (int u = 0; u < PMAX; ++u) {
+        const int i = (int)threadIdx.x + u * (int)blockDim.x;
+        v[u] = i < p.count ? plane_at(p, star_of, i) : make_float2(0.f, 0.f);
+    }
 }
 
 template <int PMAX, class StarOf>
-__device__ inline void plane_finish(const PlaneArgs& p, StarOf star_of, float4 (&part)[PMAX], const float* tt_b,
-                                    const float* tt_c, float2* out) {
-    const int seg = plane_seg(p.nchunk), waves = (blockDim.x + 63) >> 6;
-    const int rounds = (p.count + waves * (64 / seg) - 1) / (waves * (64 / seg));
+__device__ inline void plane_put(const PlaneArgs& p, StarOf star_of, const float2 (&v)[PMAX], float2* out) {
 #pragma unroll
-    for (int u = 0; u < PMAX; ++u)
-        if (u < rounds) plane_write(p, part[u], u, seg, tt_b, tt_c, out);
-    for (int u = PMAX; u < rounds; ++u) plane_write(p, plane_lane(p, star_of, u, seg), u, seg, tt_b, tt_c, out);
+    for (int u = 0; u < PMAX; ++u) {
+        const int i = (int)threadIdx.x + u * (int)blockDim.x;
+        if (i < p.count) out[i] = v[u];
+    }
+    for (int i = (int)threadIdx.x + PMAX * (int)blockDim.x; i < p.count; i += blockDim.x) out[i] = plane_at(p, star_of, i);
 }
+
+// Plane coefficients of `count` = F x J (frame, star) pairs: the chunk moments summed in chunk order,
+// (b, c) = rows 1 and 2 of the inverse normal matrix of the fit of [1, x, y] times the sums; (0, 0)
+// for stars whose plane is not used.
+struct PlaneKArgs {
+    const float* mom;           // [F][J][nchunk][4] partial moments (sum v, sum x v, sum y v, 0)
+    float2* planes;             // [F][J]
+    const int* tt_mode;         // [J]
+    float tt_b[3], tt_c[3];
+    int J, nchunk, count;
+};
+hipError_t launch_planes(const PlaneKArgs& a, hipStream_t s);
 
 // Lets a kernel use up to the full 160 KiB of LDS of a gfx950 compute unit (once per kernel).
 inline void allow_large_lds(const void* kernel) {
