@@ -11,6 +11,11 @@ of IDFT2 is included).  Each is compared with what the oracle's steps give:
   removed for the laser stars of a mixed asterism), then the inverse DFT along the
   first axis scaled by 1/M^2.
 Tolerance: relative L2 1e-5 per frame and star or layer (FP32 against FP64).
+
+For mixed asterisms the workspace also holds, after the partial moments, the
+tip/tilt plane coefficients (b, c) of every frame and star, planes[f][star]: the
+plane b x + c y they define over the pupil must match the oracle's least-squares
+fit (Sec. 3.3) within 1e-5 of the largest wavefront value.
 """
 import numpy as np
 import pytest
@@ -90,3 +95,20 @@ def test_row_and_column_pass_intermediates(case):
         for l in range(L):
             e = rel(got_c[l][:, :M // 2], want_c[l][:, :M // 2])
             assert e <= 1e-5, (case, f, l, e)
+
+    mixed = len(ref.groups) > 1
+    if not mixed:
+        return
+    a256 = lambda b: (b + 255) // 256 * 256
+    p_off = a256(r_bytes) + a256(F * L * Kh * M * 8) + a256(F * J * ((n + 1) // 2) * 16)
+    planes = raw[p_off:p_off + F * J * 8].view(np.float32).reshape(F, J, 2)
+    x = np.arange(n) - (n - 1) / 2.0
+    X, Y = np.meshgrid(x, x, indexing="ij")
+    for f in range(F):
+        for g in range(J):
+            psi = np.where(pupil, wf[f, g].astype(np.float64), 0.0)
+            want_p = np.where(pupil, O.tt_plane(psi, pupil), 0.0)
+            b, c = planes[f, g].astype(np.float64)
+            got_p = np.where(pupil, b * X + c * Y, 0.0)
+            err = np.max(np.abs(got_p - want_p))
+            assert err <= 1e-5 * np.max(np.abs(psi)), (case, f, g, err, np.max(np.abs(psi)))
