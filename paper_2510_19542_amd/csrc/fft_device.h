@@ -98,6 +98,16 @@ template <int N, int DIR> __device__ __forceinline__ void dft(float2* x) {
     else static_assert(N == 2 || N == 4 || N == 8 || N == 16, "unsupported radix");
 }
 
+// Orders the LDS accesses of one wavefront.  A team never straddles a wavefront and the DS
+// operations of a wavefront are performed in issue order, so the exchanges inside a team's own
+// region need no workgroup barrier: the fences and the wave barrier only keep the compiler from
+// moving memory operations across this point.
+__device__ __forceinline__ void team_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Factorisation and team size per transform length.
 template <int M> struct FftShape;
 template <> struct FftShape<32>  { static constexpr int N1 = 8,  N2 = 4,  T = 4;  };

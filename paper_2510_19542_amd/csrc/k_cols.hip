@@ -191,10 +191,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
             if constexpr (FIX) {
                 if (r + 1 < FR_MAX) load_fwd(f0, r + 1, xf[r + 1 < FR_MAX ? r + 1 : r]);
             }
-            __syncthreads();
+            team_sync();                        // the team's own slot
             float2 z[N1 / T][S::N2];
             if (active) fft_pass2_load<M>(t, sl, z);
-            __syncthreads();
+            team_sync();                        // the team's own slot
             if (active) fft_pass2_regs<M, -1>(t, z, [&](int jj, float2 v) { sl[jj] = v; });
         }
         // B of the block's first two layers, requested before the barrier; later layers two ahead of use
@@ -272,9 +272,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
 #pragma unroll
                 for (int n1 = 0; n1 < N1; ++n1) x[n1] = sl[S::N2 * n1 + t];
             }
-            __syncthreads();
+            team_sync();                        // the team's own slot
             if (active) fft_pass1_regs<M, +1>(t, sl, tws, x);
-            __syncthreads();
+            team_sync();                        // the team's own slot
             if (active && kk < KC && f < fend) {
                 const int nfr = min(NF, fend - f0);
                 const size_t cfr = (size_t)L * Kh * M;        // float2 per frame of C

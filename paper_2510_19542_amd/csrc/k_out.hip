@@ -157,12 +157,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void o
                 x[n1] = z;
             }
         }
-        __syncthreads();
+        team_sync();                        // the team's own region
         fft_pass1_regs<M, +1>(t, reg, tws, x);
-        __syncthreads();
+        team_sync();                        // the team's own region
         float2 z[S::N1 / S::T][S::N2];
         fft_pass2_load<M>(t, reg, z);
-        __syncthreads();
+        team_sync();                        // the team's own region
         {
             float* rows = reinterpret_cast<float*>(reg);    // [2][M]
             fft_pass2_regs<M, +1>(t, z, [&](int p, float2 v) {

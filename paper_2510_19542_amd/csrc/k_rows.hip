@@ -120,10 +120,10 @@ __global__ __launch_bounds__(256) void rows_kernel(RowArgs a) {
     __syncthreads();                // twiddles visible
 
     if (active) fft_pass1_regs<M, -1>(t, xch, tws, x);
-    __syncthreads();
+    team_sync();                    // the team's own region
     float2 zr[N1 / T][N2];
     if (active) fft_pass2_load<M>(t, xch, zr);
-    __syncthreads();
+    team_sync();                    // the team's own region
     if (active) fft_pass2_regs<M, -1>(t, zr, [&](int k, float2 v) { xch[k] = v; });
     __syncthreads();
 
