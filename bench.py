@@ -97,8 +97,14 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(frames: int):
-    """HBM bytes per step from the committed counter summary, if it was taken on the current kernels."""
+# the kernels of each timed stage of the batched MORFEO-like step
+KERNEL_NAMES = {"rows": "rows_kernel<256> + plane_kernel", "cols": "cols_kernel<256, 4, 6, 9, 1, 1>",
+                "out": "out_kernel<256, 8, 6>"}
+
+
+def measured_traffic(frames: int, stage: str = None):
+    """HBM bytes per step (or per launch of one stage's kernels) from the committed counter summary, if it
+    was taken on the current kernels."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -106,7 +112,10 @@ def measured_traffic(frames: int):
         return None
     if t.get("kernel_source_digest") != kernel_source_digest() or int(t.get("frames", -1)) != frames:
         return None
-    return t.get("bytes_per_step")
+    if stage is None:
+        return t.get("bytes_per_step")
+    parts = [v["bytes"] for v in t.get("per_kernel", {}).values() if v.get("stage") == stage]
+    return sum(parts) if parts else None
 
 
 def _timed(fn, iters, stream, torch):
@@ -526,16 +535,17 @@ def main():
     gbs = ab["step"] / (step_kernel_ms * 1e-3) / 1e9
     tfl = af["step"] / (step_kernel_ms * 1e-3) / 1e12
     traffic = measured_traffic(F)
+    # whole step (rows with the plane kernel, cols, out): the larger of its algorithmic HBM and ALU times
     if t_alu >= t_hbm:
-        roof = {"bound": "alu", "achieved": round(tfl, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(tfl / FP32_PEAK_TFLOPS, 4)}
-        other = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                 "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        step_roof = {"bound": "alu", "achieved": round(tfl, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(tfl / FP32_PEAK_TFLOPS, 4), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
     else:
-        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gbs / HBM_PEAK_GBS, 4)}
-        other = {"bound": "alu", "achieved": round(tfl, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                 "frac": round(tfl / FP32_PEAK_TFLOPS, 4)}
+        step_roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "alu_frac": round(tfl / FP32_PEAK_TFLOPS, 4)}
+    step_roof.update({"kernel_ms": round(step_kernel_ms, 6), "alg_bytes": ab["step"], "alg_flops": af["step"],
+                      "traffic": traffic})
+    # the dominant (longest) kernel against its own binding resource: algorithmic bytes or flops of one
+    # launch over its duration (HIP events on the launch stream)
     dom = int(np.argmax(stage_ms))
     dk = names[dom]
     dsec = stage_ms[dom] * 1e-3
@@ -543,18 +553,16 @@ def main():
     dom_gbs = ab["per_kernel"][dk] / dsec / 1e9
     dom_hbm_bound = ab["per_kernel"][dk] / (HBM_PEAK_GBS * 1e9) >= af["per_kernel"][dk] / (FP32_PEAK_TFLOPS * 1e12)
     if dom_hbm_bound:
-        dom_roof = {"bound": "hbm", "achieved": round(dom_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(dom_gbs / HBM_PEAK_GBS, 4), "alu_frac": round(dom_tfl / FP32_PEAK_TFLOPS, 4)}
+        roof = {"bound": "hbm", "achieved": round(dom_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(dom_gbs / HBM_PEAK_GBS, 4)}
     else:
-        dom_roof = {"bound": "alu", "achieved": round(dom_tfl, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(dom_tfl / FP32_PEAK_TFLOPS, 4), "hbm_frac": round(dom_gbs / HBM_PEAK_GBS, 4)}
-    roof.update({"kernel": "rows + cols + out (the three kernels of one batched step)",
-                 "traffic": traffic, "alg_bytes_per_launch": ab["step"], "alg_flops_per_launch": af["step"],
-                 "kernel_ms": round(step_kernel_ms, 6), "other_bound": other,
-                 "dominant_kernel": dict({"kernel": dk, "ms": round(stage_ms[dom], 6),
-                                          "alg_bytes": ab["per_kernel"][dk], "alg_flops": af["per_kernel"][dk],
-                                          "GBs_with_intermediates": round(
-                                              ab["with_intermediates"][dk] / dsec / 1e9, 1)}, **dom_roof),
+        roof = {"bound": "alu", "achieved": round(dom_tfl, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(dom_tfl / FP32_PEAK_TFLOPS, 4)}
+    roof.update({"traffic": measured_traffic(F, dk), "kernel": KERNEL_NAMES[dk], "kernel_ms": round(stage_ms[dom], 6),
+                 "alg_bytes_per_launch": ab["per_kernel"][dk], "alg_flops_per_launch": af["per_kernel"][dk],
+                 "hbm_frac": round(dom_gbs / HBM_PEAK_GBS, 4), "alu_frac": round(dom_tfl / FP32_PEAK_TFLOPS, 4),
+                 "GBs_with_intermediates": round(ab["with_intermediates"][dk] / dsec / 1e9, 1),
+                 "step": step_roof,
                  "per_kernel_GBs_with_intermediates": {
                      k: round(ab["with_intermediates"][k] / (v * 1e-3) / 1e9, 1) for k, v in zip(names, stage_ms)}})
     result = {
