@@ -222,10 +222,11 @@ enum { SAFR_OPT_GRAPH = 0, SAFR_OPT_ROW_TEAMS = 1, SAFR_OPT_OUT_ROWS = 2, SAFR_O
        SAFR_OPT_COL_TOGETHER = 7, SAFR_OPT_CHECK_FINITE = 8 };
 safr_status safr_set_option(safr_plan* p, int option, int value);
 
-/* Measures the three kernels of the hard-real-time step (row pass, column pass
- * with the apply, output pass) with HIP events recorded on `stream` around each
- * launch, over `iters` synchronised repetitions of a batched call; writes the
- * average milliseconds of each to ms[0..2].  Same buffers and workspace rules as
+/* Measures the three stages of the hard-real-time step (row pass, with the small
+ * kernel that forms the tip/tilt planes of a mixed asterism; column pass with the
+ * apply; output pass) with HIP events recorded on `stream` around each, over
+ * `iters` synchronised repetitions of a batched call; writes the average
+ * milliseconds of each to ms[0..2].  Same buffers and workspace rules as
  * safr_reconstruct_batched. */
 safr_status safr_time_stages(safr_plan* p, int frames, const float* wavefronts, float* layers,
                              int precision, int iters, hipStream_t stream, double* ms);
