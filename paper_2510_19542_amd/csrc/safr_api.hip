@@ -700,6 +700,7 @@ safr_status safr_workspace_size(const safr_plan* p, int frames, int precision, s
 safr_status safr_set_workspace(safr_plan* p, void* dev, size_t bytes) {
     if (!p) return fail(SAFR_ERR_ARG, "plan is NULL");
     if (dev && (reinterpret_cast<uintptr_t>(dev) & 255)) return fail(SAFR_ERR_ARG, "workspace not 256-byte aligned");
+    if (dev != p->ws_user || (dev ? bytes : 0) != p->ws_user_bytes) drop_graphs(p);   // graphs hold workspace addresses
     p->ws_user = dev;
     p->ws_user_bytes = dev ? bytes : 0;
     return SAFR_OK;

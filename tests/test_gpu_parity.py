@@ -265,6 +265,36 @@ def test_graph_replay_matches_eager():
     S.safr_set_workspace(plan, 0, 0)
 
 
+def test_graph_follows_a_rebound_workspace():
+    """A captured graph holds workspace addresses: binding another workspace must re-capture, so the
+    old buffer (kept allocated, filled with a sentinel) is not written by later calls."""
+    torch = _torch()
+    S = _lib()
+    geo = _geo("C1")
+    plan = S.precompute_geometry(geo)
+    F = 3
+    need = S.safr_workspace_size(plan, F)
+    wsa = torch.zeros(need + 256, dtype=torch.uint8, device="cuda")
+    wsb = torch.zeros(need + 256, dtype=torch.uint8, device="cuda")
+    wf = torch.from_numpy(synth.random_wavefronts(geo, F, seed=9)).cuda()
+    out = torch.empty((F, geo.L, geo.M, geo.M), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.Stream()
+    S.safr_set_option(plan, S.SAFR_OPT_GRAPH, 1)
+    S.safr_set_workspace(plan, (wsa.data_ptr() + 255) & ~255, need)
+    S.safr_reconstruct_batched(plan, F, wf, out, S.SAFR_FP32, stream)         # captured with workspace A
+    stream.synchronize()
+    ref = out.clone()
+    S.safr_set_workspace(plan, (wsb.data_ptr() + 255) & ~255, need)
+    wsa.fill_(0xA5)
+    out.zero_()
+    torch.cuda.synchronize()
+    S.safr_reconstruct_batched(plan, F, wf, out, S.SAFR_FP32, stream)
+    stream.synchronize()
+    assert torch.equal(out, ref)
+    assert bool((wsa == 0xA5).all()), "the replay wrote the workspace bound before"
+    S.safr_set_workspace(plan, 0, 0)
+
+
 def test_tuning_options_do_not_change_results():
     torch = _torch()
     S = _lib()
