@@ -51,11 +51,12 @@ struct OutShape {
     static constexpr int NF = NTEAM / TPF;                          // frames per iteration
     static constexpr int V4 = RT * M / (4 * 256);                   // 4-pixel groups per thread per frame
     static constexpr int TILE4 = 4 * (M / 2);                       // float4 of one row tile, columns k < M/2
-    static constexpr int RUN4 = (RT / 8) * TILE4;                   // float4 loads per frame
-    static constexpr int NLD = (NF * RUN4 + 255) / 256;             // float4 loads per thread per iteration
+    static constexpr int TPW = (64 / T) / 4;                        // row tiles per wavefront (its teams' row pairs)
+    static constexpr int NLD = TPW * TILE4 / 64;                    // float4 loads per lane per iteration
     static_assert(TPF <= NTEAM && NTEAM % TPF == 0, "row pairs must tile the teams");
     static_assert(V4 >= 1 && (RT * M) % 1024 == 0, "at least one 4-pixel group per thread");
     static_assert(2 * Kh <= TL && M <= TL, "a team region holds two rows");
+    static_assert(TPW >= 1 && NF * (RT / 8) == 4 * TPW && (TPW * TILE4) % 64 == 0, "a wavefront loads its own tiles");
 };
 
 }  // namespace
@@ -90,30 +91,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void o
     auto run = [&](int f) {
         return reinterpret_cast<const float4*>(a.C + (((size_t)f * L + l) * (M / 8) + r0 / 8) * Kh * 8);
     };
-    constexpr bool EXACT = NF * O::RUN4 % 256 == 0;
+    // each wavefront loads the row tiles of its own teams (tile = 4 teams = 8 rows of one frame; tile
+    // index fi * (RT / 8) + pb), so the spectra it stashes are read by its own teams only
+    const int wave = tid >> 6, lane = tid & 63;
     float4 ld[O::NLD];
     auto issue = [&](int fi0) {
 #pragma unroll
         for (int i = 0; i < O::NLD; ++i) {
-            const int e = tid + 256 * i;
-            const int fi = e / O::RUN4, s = e - fi * O::RUN4;
-            const int pb = s / O::TILE4, s4 = s - pb * O::TILE4;
+            const int e = lane + 64 * i;
+            const int tile = wave * O::TPW + e / O::TILE4, s4 = e % O::TILE4;
+            const int fi = tile / (RT / 8), pb = tile % (RT / 8);
             const int f = fi0 + fi;
-            ld[i] = ((EXACT || e < NF * O::RUN4) && f < fend) ? run(f)[pb * 4 * Kh + s4]
-                                                             : make_float4(0.f, 0.f, 0.f, 0.f);
+            ld[i] = f < fend ? run(f)[pb * 4 * Kh + s4] : make_float4(0.f, 0.f, 0.f, 0.f);
         }
     };
     auto stash = [&]() {
 #pragma unroll
         for (int i = 0; i < O::NLD; ++i) {
-            const int e = tid + 256 * i;
-            if (!EXACT && e >= NF * O::RUN4) break;
-            const int fi = e / O::RUN4, s = e - fi * O::RUN4;
-            // float4 s4 of tile pb: column k = s4 / 4, rows 2 (s4 % 4) and 2 (s4 % 4) + 1 of the tile
-            const int pb = s / O::TILE4, s4 = s - pb * O::TILE4;
+            const int e = lane + 64 * i;
+            // float4 s4 of the tile: column k = s4 / 4, rows 2 (s4 % 4) and 2 (s4 % 4) + 1 of the tile
+            const int tile = wave * O::TPW + e / O::TILE4, s4 = e % O::TILE4;
             const int k = s4 >> 2;
-            const int task = fi * TPF + pb * 4 + (s4 & 3);
-            float2* dst = smem + M + task * RS;
+            float2* dst = smem + M + (tile * 4 + (s4 & 3)) * RS;
             dst[k] = make_float2(ld[i].x, ld[i].y);
             dst[Kh + k] = make_float2(ld[i].z, ld[i].w);
         }
@@ -132,7 +131,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void o
         const PlaneArgs pa{a.planes, a.J, a.nb / 2, f0, fend, min(NF, fend - f0) * (a.nb / 2)};
         float2 pl[1];
         if constexpr (MIXED) plane_fetch<1>(pa, star_of, pl);
-        __syncthreads();
+        team_sync();                        // the wavefront's own teams' regions
 
         // packed C2R: Z[q] = A[q] + i B[q] over the Hermitian extensions of the team's two rows
         float2 x[S::N1];
