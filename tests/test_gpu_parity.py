@@ -121,6 +121,26 @@ def test_reconstruct_matches_oracle(case):
     assert err <= 1e-5, (case, err)
 
 
+def test_many_row_chunks_mixed():
+    """A large pupil split into more row chunks than a wavefront has lanes (n = 160, two rows per
+    row-pass block: 80 chunks), mixed asterism: the tip/tilt planes sum their chunk moments in several
+    lane rounds.  Two frames in one batched call against the oracle."""
+    torch = _torch()
+    S = _lib()
+    geo = _small(256, 160, (1, 1, 0), L=2, seed=11, pitch=0.5)
+    plan = S.precompute_geometry(geo)
+    ref = _oracle(geo)
+    F = 2
+    wf = np.stack([_wavefronts(geo, f) for f in range(F)])
+    x = torch.from_numpy(np.ascontiguousarray(wf, dtype=np.float32)).cuda()
+    for teams in (1, 8):
+        S.safr_set_option(plan, S.SAFR_OPT_ROW_TEAMS, teams)
+        got = S.reconstruct(plan, x).cpu().numpy()
+        for f in range(F):
+            err = rel_l2(got[f], O.reconstruct(ref, wf[f].astype(np.float64)))
+            assert err <= 1e-5, (teams, f, err)
+
+
 def test_exact_recovery_on_gpu():
     """Periodic data from the exact forward operator, alpha = 0, J > L: the layers come back.
 
