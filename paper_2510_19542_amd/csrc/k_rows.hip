@@ -158,13 +158,10 @@ __global__ __launch_bounds__(256) void plane_kernel(PlaneKArgs a) {
     const int i = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (i >= a.count) return;                       // whole wavefronts leave together
-    if (a.tt_mode[i % a.J] == 0) {
-        if (lane == 0) a.planes[i] = make_float2(0.f, 0.f);
-        return;
-    }
+    const bool used = (a.mask >> (i % a.J)) & 1u;   // (0, 0) for a star whose plane is not used
     const float4* mo = reinterpret_cast<const float4*>(a.mom) + (size_t)i * a.nchunk;
     float s0 = 0.f, s1 = 0.f, s2 = 0.f;
-    for (int q = lane; q < a.nchunk; q += 64) {
+    for (int q = lane; used && q < a.nchunk; q += 64) {
         const float4 v = mo[q];
         s0 += v.x;
         s1 += v.y;

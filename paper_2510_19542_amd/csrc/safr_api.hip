@@ -89,6 +89,7 @@ struct safr_plan {
     int weighted = 0;               // B was made with a per-frequency alpha map
     unsigned char* pupil = nullptr;
     int* tt_mode = nullptr;
+    unsigned plane_mask = 0;     // bit g: star g's tip/tilt plane is used (split tomography)
     float4* polc_tab = nullptr;     // [J][L] line-of-sight sampling of the output grids (closed loop)
     float* strehl_part = nullptr;   // per-chunk moments of the Strehl estimate (grown on demand)
     size_t strehl_part_floats = 0;
@@ -570,6 +571,8 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
         PC_TRY(hipMemcpy(p->pupil, pup.data(), pup.size(), hipMemcpyHostToDevice));
         PC_TRY(hipMalloc(&p->tt_mode, J * sizeof(int)));
         PC_TRY(hipMemcpy(p->tt_mode, mode.data(), J * sizeof(int), hipMemcpyHostToDevice));
+        for (int g = 0; g < J; ++g)
+            if (mode[g] != 0) p->plane_mask |= 1u << g;
         {
             // closed loop: star g's line of sight through pupil pixel (i, j) crosses output layer l at
             // c^s_l r + theta_g h_l, r = (p0 + i - M/2, p0 + j - M/2) pitch; on the layer grid (spacing
@@ -1334,7 +1337,7 @@ safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, in
         PlaneKArgs pk{};
         pk.mom = mom;
         pk.planes = planes;
-        pk.tt_mode = p->tt_mode;
+        pk.mask = p->plane_mask;
         for (int i = 0; i < 3; ++i) {
             pk.tt_b[i] = p->tt_b[i];
             pk.tt_c[i] = p->tt_c[i];

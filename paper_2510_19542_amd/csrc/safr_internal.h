@@ -209,10 +209,11 @@ __device__ inline void plane_put(const PlaneArgs& p, StarOf star_of, const float
 struct PlaneKArgs {
     const float* mom;           // [F][J][nchunk][4] partial moments (sum v, sum x v, sum y v, 0)
     float2* planes;             // [F][J]
-    const int* tt_mode;         // [J]
+    unsigned mask;              // bit g: star g's plane is used (J <= 32)
     float tt_b[3], tt_c[3];
     int J, nchunk, count;
 };
+static_assert(kMaxJ <= 32, "the plane mask holds one bit per star");
 hipError_t launch_planes(const PlaneKArgs& a, hipStream_t s);
 
 // Lets a kernel use up to the full 160 KiB of LDS of a gfx950 compute unit (once per kernel).
