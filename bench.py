@@ -11,7 +11,7 @@ loop's mode) is reported beside it.  Inputs are seeded synthetic frames (von
 Karman screens, 35-layer synthetic profile, 2% noise, frozen flow) resident in
 HBM before timing starts.
 
-Prints one JSON line.  ``--gpus`` above 1 is refused: this build runs on one GPU.
+Prints one JSON line.  ``--gpus`` above 1 is refused: the benchmark runs on one GPU.
 """
 from __future__ import annotations
 
@@ -466,7 +466,7 @@ def main():
     ap.add_argument("--c4-frames", type=int, default=20000, help="training frames of the learned filter")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: --gpus {args.gpus} is not supported; this build measures one GPU (use --gpus 1)",
+        print(f"bench.py: --gpus {args.gpus} is not supported; the benchmark measures one GPU (use --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
 

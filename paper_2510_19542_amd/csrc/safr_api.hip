@@ -820,7 +820,7 @@ safr_status safr_reconstruct_batched(safr_plan* p, int frames, const float* wf, 
     if (frames < 1) return fail(SAFR_ERR_ARG, "frames must be >= 1");
     if (precision != SAFR_FP32 && precision != SAFR_BF16X3) return fail(SAFR_ERR_ARG, "bad precision");
     if (precision == SAFR_BF16X3 && !p->Apack)
-        return fail(SAFR_ERR_UNSUPPORTED, "BF16 path not available in this build");
+        return fail(SAFR_ERR_UNSUPPORTED, "BF16 path not available for this plan");
     const size_t need = ws_bytes(p, frames);
     void* ws = nullptr;
     if (p->ws_user && p->ws_user_bytes >= need) ws = p->ws_user;
