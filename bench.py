@@ -464,6 +464,8 @@ def main():
                     help="after timing, copy 256 MiB device to device three times (counter calibration)")
     ap.add_argument("--no-extras", action="store_true", help="skip the 1024-frame, learned-filter and mixed-size runs")
     ap.add_argument("--c4-frames", type=int, default=20000, help="training frames of the learned filter")
+    ap.add_argument("--only-c3", action="store_true",
+                    help="only the 1024-frame FP32 and BF16x3 (matrix-core) runs, printed as one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; the benchmark measures one GPU (use --gpus 1)",
@@ -475,6 +477,10 @@ def main():
 
     import synth
     from paper_2510_19542_amd import safr as S
+
+    if args.only_c3:
+        print(json.dumps({"c3_batched_1024": run_c3(S, torch, torch.cuda.current_stream())}), flush=True)
+        return
 
     dev = torch.device("cuda:0")
     geo = synth.preset("C2")
