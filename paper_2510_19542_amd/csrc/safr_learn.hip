@@ -67,25 +67,25 @@ namespace {
 
 void free_trainer(safr_trainer* t) {
     if (!t) return;
-    hipFree(t->fq.U);
-    hipFree(t->fq.V);
-    hipFree(t->fq.inv_sigma);
-    hipFree(t->fq.feat);
-    hipFree(t->fq.s);
-    hipFree(t->fq.ph);
-    hipFree(t->fq.mult);
-    hipFree(t->fq_dev);
-    hipFree(t->amp);
-    hipFree(t->stats);
-    hipFree(t->eta);
-    hipFree(t->params);
-    hipFree(t->m);
-    hipFree(t->v);
-    hipFree(t->act);
-    hipFree(t->partials);
-    hipFree(t->loss_part);
-    hipFree(t->frames);
-    hipFree(t->grad);
+    (void)hipFree(t->fq.U);
+    (void)hipFree(t->fq.V);
+    (void)hipFree(t->fq.inv_sigma);
+    (void)hipFree(t->fq.feat);
+    (void)hipFree(t->fq.s);
+    (void)hipFree(t->fq.ph);
+    (void)hipFree(t->fq.mult);
+    (void)hipFree(t->fq_dev);
+    (void)hipFree(t->amp);
+    (void)hipFree(t->stats);
+    (void)hipFree(t->eta);
+    (void)hipFree(t->params);
+    (void)hipFree(t->m);
+    (void)hipFree(t->v);
+    (void)hipFree(t->act);
+    (void)hipFree(t->partials);
+    (void)hipFree(t->loss_part);
+    (void)hipFree(t->frames);
+    (void)hipFree(t->grad);
     delete t;
 }
 
@@ -94,7 +94,7 @@ safr_status run_batch(safr_trainer* t, int nb, const int* frames, hipStream_t s,
     for (int i = 0; i < nb; ++i)
         if (frames[i] < 0 || frames[i] >= t->nframes) return lfail(SAFR_ERR_ARG, "frame index %d out of range", frames[i]);
     if (nb > t->frames_cap) {
-        hipFree(t->frames);
+        (void)hipFree(t->frames);
         t->frames = nullptr;
         L_TRY(hipMalloc(&t->frames, nb * sizeof(int)));
         t->frames_cap = nb;
@@ -102,7 +102,7 @@ safr_status run_batch(safr_trainer* t, int nb, const int* frames, hipStream_t s,
     L_TRY(hipMemcpy(t->frames, frames, nb * sizeof(int), hipMemcpyHostToDevice));
     const size_t rows = (size_t)nb * t->H * t->r;
     if (rows > t->act_rows) {
-        hipFree(t->act);
+        (void)hipFree(t->act);
         t->act = nullptr;
         L_TRY(hipMalloc(&t->act, rows * ACT_PLANES * sizeof(float)));
         t->act_rows = rows;
@@ -110,7 +110,7 @@ safr_status run_batch(safr_trainer* t, int nb, const int* frames, hipStream_t s,
     const int threads = 128;
     const int blocks = (int)((nb * t->H + threads - 1) / threads);
     if (blocks > t->loss_cap) {
-        hipFree(t->loss_part);
+        (void)hipFree(t->loss_part);
         t->loss_part = nullptr;
         L_TRY(hipMalloc(&t->loss_part, blocks * sizeof(float)));
         t->loss_cap = blocks;
@@ -135,7 +135,7 @@ safr_status run_batch(safr_trainer* t, int nb, const int* frames, hipStream_t s,
     L_TRY(hipGetLastError());
     const int chunks = (int)std::min<size_t>(256, (rows + 1023) / 1024);
     if (chunks > t->chunks_cap) {
-        hipFree(t->partials);
+        (void)hipFree(t->partials);
         t->partials = nullptr;
         L_TRY(hipMalloc(&t->partials, (size_t)chunks * 8705 * sizeof(float)));
         t->chunks_cap = chunks;
@@ -203,9 +203,9 @@ safr_status safr_trainer_create(const safr_geometry* geo, int L, const double* h
     double* sig = nullptr;
     safr_status st = SAFR_OK;
     auto bail = [&](safr_status s2) {
-        hipFree(W);
-        hipFree(Qd);
-        hipFree(sig);
+        (void)hipFree(W);
+        (void)hipFree(Qd);
+        (void)hipFree(sig);
         free_trainer(t);
         return s2;
     };
@@ -294,9 +294,9 @@ safr_status safr_trainer_create(const safr_geometry* geo, int L, const double* h
     T_TRY(hipMemsetAsync(t->v, 0, 8705 * sizeof(float), stream));
     T_TRY(hipStreamSynchronize(stream));
 #undef T_TRY
-    hipFree(W);
-    hipFree(Qd);
-    hipFree(sig);
+    (void)hipFree(W);
+    (void)hipFree(Qd);
+    (void)hipFree(sig);
     (void)st;
     *out = t;
     return SAFR_OK;
@@ -426,7 +426,7 @@ safr_status safr_mlp_infer(const float* params, const float* feats, int rows, do
     hipError_t e = hipMemcpy(p, params, 8705 * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = launch_mlp_infer(p, feats, phi, rows, (float)std::log10(noise), s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    hipFree(p);
+    (void)hipFree(p);
     if (e != hipSuccess) return lfail(SAFR_ERR_DEVICE, "network inference failed: %s", hipGetErrorString(e));
     return SAFR_OK;
 }
