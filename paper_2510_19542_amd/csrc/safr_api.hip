@@ -1034,11 +1034,17 @@ safr_status safr_autotune(safr_plan* p, int frames, const float* wf, float* out,
     for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
     safr_status st = SAFR_OK;
     const int T = team_size(p->M);
-    // row pass: transform teams per block
+    // row pass: transform teams per block (powers of two, and the counts that split the pupil rows into
+    // equal chunks)
     {
         int best = p->row_teams;
         double bt = 1e30;
-        for (int teams : {1, 2, 4, 8, 16}) {
+        std::vector<int> cand = {1, 2, 4, 8, 16};
+        const int npairs = (p->n + 1) / 2;
+        for (int c = 1; c <= npairs; ++c) cand.push_back((npairs + c - 1) / c);
+        std::sort(cand.begin(), cand.end());
+        cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+        for (int teams : cand) {
             if (teams * T > 256 || rows_lds_bytes(p->M, p->n, teams) > kMaxLds || 2 * teams > 2 * p->n) continue;
             p->row_teams = teams;
             double ms = 0.0;
