@@ -336,6 +336,12 @@ def run_c4(S, torch, stream, frames):
     wmap = (1.0 + (nidx[:, None] ** 2 + nidx[None, :] ** 2) / 64.0) ** (1.0 / 3.0)
     wtik = S.precompute_geometry(geo, pupil=None)
     _attach_workspace(S, torch, wtik, F, S.SAFR_FP32)
+    # the Sobolev smoothness beta of the layer prior (Sec. 3.1): one plan per beta, alpha swept on each
+    betas = (0.0, 0.5, 1.0, 1.5, 2.0, 2.5)
+    bplans = [S.precompute_geometry(geo.replace(beta=bt), pupil=None) for bt in betas]
+    for p in bplans:
+        _attach_workspace(S, torch, p, F, S.SAFR_FP32)
+    balphas = [float(a) for a in np.logspace(-8, 0, 17)]
     res = {"workload": f"C1 geometry with data on the whole 64x64 grid; trained on {frames} frames "
                        f"(eta ~ U[0.5%, 5%]), evaluated on 1000 held-out seeds",
            "train_s": round(train_s, 2), "heldout": {}}
@@ -363,11 +369,21 @@ def run_c4(S, torch, stream, frames):
             S.safr_reconstruct_batched(wtik, F, x, out, S.SAFR_FP32, stream)
             werrs.append(_layer_error(torch, out, tt))
         wb = int(np.argmin(werrs))
+        bsweep = {}
+        for bt, p in zip(betas, bplans):
+            berrs = []
+            for a in balphas:
+                S.safr_update_alpha(p, a, a)
+                S.safr_reconstruct_batched(p, F, x, out, S.SAFR_FP32, stream)
+                berrs.append(_layer_error(torch, out, tt))
+            bb = int(np.argmin(berrs))
+            bsweep[str(bt)] = {"best": round(berrs[bb], 5), "best_alpha": float(f"{balphas[bb]:.3g}")}
         res["heldout"][str(eta)] = {"learned": round(e_l, 5), f"tikhonov_alpha_{geo.alpha:g}": round(errs[0], 5),
                                     "tikhonov_best": round(errs[b], 5), "best_alpha": float(f"{alphas[b]:.3g}"),
                                     "tsvd_best": round(terrs[tb], 5), "tsvd_best_alpha": float(f"{alphas[1 + tb]:.3g}"),
                                     "weighted_tikhonov_best": round(werrs[wb], 5),
-                                    "weighted_best_alpha": float(f"{alphas[1 + wb]:.3g}")}
+                                    "weighted_best_alpha": float(f"{alphas[1 + wb]:.3g}"),
+                                    "tikhonov_best_by_beta": bsweep}
         if not speed:
             for name, p in (("learned", lrn), ("tikhonov", tik[0])):
                 speed[name] = round(F * 1000.0 / _timed(
@@ -466,6 +482,8 @@ def main():
     ap.add_argument("--c4-frames", type=int, default=20000, help="training frames of the learned filter")
     ap.add_argument("--only-c3", action="store_true",
                     help="only the 1024-frame FP32 and BF16x3 (matrix-core) runs, printed as one JSON line")
+    ap.add_argument("--only-c4", action="store_true",
+                    help="only the learned-filter run and the classical filter sweeps, printed as one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; the benchmark measures one GPU (use --gpus 1)",
@@ -480,6 +498,10 @@ def main():
 
     if args.only_c3:
         print(json.dumps({"c3_batched_1024": run_c3(S, torch, torch.cuda.current_stream())}), flush=True)
+        return
+    if args.only_c4:
+        print(json.dumps({"c4_learned_filter": run_c4(S, torch, torch.cuda.current_stream(), args.c4_frames)[0]}),
+              flush=True)
         return
 
     dev = torch.device("cuda:0")

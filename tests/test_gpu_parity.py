@@ -93,6 +93,8 @@ CASES = {
     "m32-n1": lambda: _small(32, 1, (0, 0), L=1, seed=8),
     "m256-ngs-L3-generic": lambda: _small(256, 61, (0, 0, 0), L=3, seed=9, pitch=0.5),
     "m128-mixed-L4": lambda: _small(128, 45, (1, 1, 1, 0, 0), L=4, seed=10, obstruction=0.1),
+    "m64-lgs-beta0": lambda: _small(64, 31, (1, 1, 1), L=3, seed=12, beta=0.0),
+    "m32-mixed-beta2.5": lambda: _small(32, 19, (1, 1, 1, 0, 0), L=3, seed=13, beta=2.5),
 }
 
 
