@@ -466,7 +466,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--frames", type=int, default=64, help="independent frames per step (one batched call)")
     ap.add_argument("--batches", type=int, default=8,
                     help="distinct input batches cycled through (each is re-read only every this many steps)")
@@ -544,6 +544,17 @@ def main():
     torch.cuda.synchronize()
     ms_step = t0.elapsed_time(t1) / args.steps
     fps = F * 1000.0 / ms_step
+    # five more timed runs of the same length, for the spread (not part of the reported value)
+    reruns = []
+    if not args.only_batched:
+        for _ in range(5):
+            torch.cuda.synchronize()
+            t0.record(stream)
+            for i in range(args.steps):
+                S.safr_reconstruct_batched(plan, F, batches[i % len(batches)], out, S.SAFR_FP32, stream)
+            t1.record(stream)
+            torch.cuda.synchronize()
+            reruns.append(round(F * 1000.0 / (t0.elapsed_time(t1) / args.steps), 1))
 
     # per-kernel durations of the batched call (HIP events on the launch stream, inside the library)
     stage_ms = S.safr_time_stages(plan, F, batches[0], out, S.SAFR_FP32, 20, stream)
@@ -613,6 +624,7 @@ def main():
                    "launch_shapes": {"batched": list(tuned), "single": list(tuned1), "autotuned_now": args.autotune}},
         "roofline": roof,
         "stage_ms": {k: round(v, 6) for k, v in zip(names, stage_ms)},
+        "reruns_frames_per_s": {"runs": reruns, "median": float(np.median(reruns)) if reruns else None},
         "frame_alg_bytes": algorithmic_bytes(desc, geo.n, 1)["step"],
         "frame_alg_flops": algorithmic_flops(desc, 1)["step"],
     }
