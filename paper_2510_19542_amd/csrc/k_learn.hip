@@ -26,7 +26,6 @@ namespace safr {
 
 namespace {
 
-constexpr int H64 = 64;
 constexpr int OFF_W1 = 0, OFF_B1 = 256, OFF_W2 = 320, OFF_B2 = 4416, OFF_W3 = 4480, OFF_B3 = 8576,
               OFF_W4 = 8640, OFF_B4 = 8704;
 

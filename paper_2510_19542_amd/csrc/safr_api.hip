@@ -143,10 +143,10 @@ size_t ws_bytes(const safr_plan* p, int frames) {
 
 // captured graphs hold launch shapes and pointers: dropped whenever a tuning option changes
 void drop_graphs(safr_plan* p) {
-    if (p->gexec) hipGraphExecDestroy(p->gexec);
-    if (p->graph) hipGraphDestroy(p->graph);
-    if (p->lexec) hipGraphExecDestroy(p->lexec);
-    if (p->lgraph) hipGraphDestroy(p->lgraph);
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->lexec) (void)hipGraphExecDestroy(p->lexec);
+    if (p->lgraph) (void)hipGraphDestroy(p->lgraph);
     p->gexec = nullptr;
     p->graph = nullptr;
     p->lexec = nullptr;
@@ -156,26 +156,26 @@ void drop_graphs(safr_plan* p) {
 void free_plan(safr_plan* p) {
     if (!p) return;
     drop_graphs(p);
-    hipFree(p->B64);
-    hipFree(p->B32);
-    hipFree(p->Apack);
-    hipFree(p->tw);
-    hipFree(p->Xh);
-    hipFree(p->Yh);
-    hipFree(p->P);
-    hipFree(p->pupil);
-    hipFree(p->tt_mode);
-    hipFree(p->polc_tab);
-    hipFree(p->strehl_part);
+    (void)hipFree(p->B64);
+    (void)hipFree(p->B32);
+    (void)hipFree(p->Apack);
+    (void)hipFree(p->tw);
+    (void)hipFree(p->Xh);
+    (void)hipFree(p->Yh);
+    (void)hipFree(p->P);
+    (void)hipFree(p->pupil);
+    (void)hipFree(p->tt_mode);
+    (void)hipFree(p->polc_tab);
+    (void)hipFree(p->strehl_part);
     for (int gi = 0; gi < 2; ++gi) {
-        hipFree(p->pre[gi].W);
-        hipFree(p->pre[gi].Q);
-        hipFree(p->pre[gi].sigma);
+        (void)hipFree(p->pre[gi].W);
+        (void)hipFree(p->pre[gi].Q);
+        (void)hipFree(p->pre[gi].sigma);
     }
-    hipFree(p->X64);
-    hipFree(p->Y64);
-    hipFree(p->dfirst);
-    hipFree(p->ws_own);
+    (void)hipFree(p->X64);
+    (void)hipFree(p->Y64);
+    (void)hipFree(p->dfirst);
+    (void)hipFree(p->ws_own);
     delete p;
 }
 
@@ -313,9 +313,9 @@ safr_status build_basis(safr_plan* p, hipStream_t s) {
         BT_TRY(launch_ngs_basis(ba, s));
         BT_TRY(hipStreamSynchronize(s));
     } while (0);
-    hipFree(tw64);
-    hipFree(Tb);
-    hipFree(Eb);
+    (void)hipFree(tw64);
+    (void)hipFree(Tb);
+    (void)hipFree(Eb);
     return st;
 }
 
@@ -679,11 +679,11 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
         PC_TRY(hipStreamSynchronize(stream));
 #undef PC_TRY
     } while (0);
-    hipFree(feats);
-    hipFree(phi);
-    hipFree(mlp_dev);
-    hipFree(aw_dev);
-    hipFree(dbad);
+    (void)hipFree(feats);
+    (void)hipFree(phi);
+    (void)hipFree(mlp_dev);
+    (void)hipFree(aw_dev);
+    (void)hipFree(dbad);
     if (st != SAFR_OK) {
         free_plan(p);
         return st;
@@ -809,8 +809,8 @@ safr_status safr_update_alpha(safr_plan* p, double alpha, double alpha_tt, int f
         p->filter = filter;
         p->weighted = alpha_weight != nullptr;
     } while (0);
-    hipFree(aw_dev);
-    hipFree(dbad);
+    (void)hipFree(aw_dev);
+    (void)hipFree(dbad);
     return st;
 }
 
@@ -836,8 +836,8 @@ safr_status safr_reconstruct_batched(safr_plan* p, int frames, const float* wf, 
         const bool hit = p->gexec && p->g_frames == frames && p->g_prec == precision && p->g_wf == wf &&
                          p->g_out == out && p->g_stream == s;
         if (!hit) {
-            if (p->gexec) hipGraphExecDestroy(p->gexec);
-            if (p->graph) hipGraphDestroy(p->graph);
+            if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+            if (p->graph) (void)hipGraphDestroy(p->graph);
             p->gexec = nullptr;
             p->graph = nullptr;
             HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -845,7 +845,7 @@ safr_status safr_reconstruct_batched(safr_plan* p, int frames, const float* wf, 
             hipGraph_t g = nullptr;
             hipError_t e = hipStreamEndCapture(s, &g);
             if (st != SAFR_OK) {
-                if (g) hipGraphDestroy(g);
+                if (g) (void)hipGraphDestroy(g);
                 return st;
             }
             if (e != hipSuccess) return fail(SAFR_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
@@ -908,7 +908,7 @@ safr_status safr_strehl(safr_plan* p, int frames, int D, const double* dirs, con
     const size_t need = (size_t)frames * D * strehl_chunks(p->n) * 3;
     if (p->strehl_part_floats < need) {          // grown on demand (synchronises the device once)
         HIP_TRY(hipStreamSynchronize(s));
-        hipFree(p->strehl_part);
+        (void)hipFree(p->strehl_part);
         p->strehl_part = nullptr;
         p->strehl_part_floats = 0;
         HIP_TRY(hipMalloc(&p->strehl_part, need * sizeof(float)));
@@ -939,8 +939,8 @@ safr_status safr_loop_step(safr_plan* p, int frames, const float* wf, const floa
         const bool hit = p->lexec && p->l_frames == frames && p->l_gain == gain && p->l_wf == wf &&
                          p->l_ain == a_in && p->l_aout == a_out && p->l_stream == s;
         if (!hit) {
-            if (p->lexec) hipGraphExecDestroy(p->lexec);
-            if (p->lgraph) hipGraphDestroy(p->lgraph);
+            if (p->lexec) (void)hipGraphExecDestroy(p->lexec);
+            if (p->lgraph) (void)hipGraphDestroy(p->lgraph);
             p->lexec = nullptr;
             p->lgraph = nullptr;
             HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -948,7 +948,7 @@ safr_status safr_loop_step(safr_plan* p, int frames, const float* wf, const floa
             hipGraph_t g = nullptr;
             hipError_t e = hipStreamEndCapture(s, &g);
             if (st != SAFR_OK) {
-                if (g) hipGraphDestroy(g);
+                if (g) (void)hipGraphDestroy(g);
                 return st;
             }
             if (e != hipSuccess) return fail(SAFR_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
@@ -988,13 +988,13 @@ safr_status safr_time_stages(safr_plan* p, int frames, const float* wf, float* o
             st = fail(SAFR_ERR_DEVICE, "event synchronisation failed");
             break;
         }
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < 3 && st == SAFR_OK; ++k) {
             float t = 0.f;
-            hipEventElapsedTime(&t, ev[k], ev[k + 1]);
+            if (hipEventElapsedTime(&t, ev[k], ev[k + 1]) != hipSuccess) st = fail(SAFR_ERR_DEVICE, "event timing failed");
             acc[k] += t;
         }
     }
-    for (auto& e : ev) hipEventDestroy(e);
+    for (auto& e : ev) (void)hipEventDestroy(e);
     if (st != SAFR_OK) return st;
     for (int k = 0; k < 3; ++k) ms[k] = acc[k] / iters;
     return SAFR_OK;
@@ -1011,7 +1011,7 @@ safr_status time_stage(safr_plan* p, int frames, const float* wf, float* out, in
         if (st != SAFR_OK) return st;
         if (hipEventSynchronize(ev[3]) != hipSuccess) return fail(SAFR_ERR_DEVICE, "event synchronisation failed");
         float t = 0.f;
-        hipEventElapsedTime(&t, ev[stage], ev[stage + 1]);
+        HIP_TRY(hipEventElapsedTime(&t, ev[stage], ev[stage + 1]));
         acc += t;
     }
     *ms = acc / iters;
@@ -1105,7 +1105,7 @@ safr_status safr_autotune(safr_plan* p, int frames, const float* wf, float* out,
         p->col_nf = bestn;
         p->col_frames_auto = 0;
     }
-    for (auto& e : ev) hipEventDestroy(e);
+    for (auto& e : ev) (void)hipEventDestroy(e);
     drop_graphs(p);
     if (choice) {
         choice[0] = p->row_teams;
@@ -1140,12 +1140,12 @@ namespace {
 
 void free_multi(safr_multi* m) {
     if (!m) return;
-    if (m->exec) hipGraphExecDestroy(m->exec);
-    if (m->graph) hipGraphDestroy(m->graph);
-    for (void* w : m->ws) hipFree(w);
-    for (hipStream_t st : m->side) hipStreamDestroy(st);
-    for (hipEvent_t e : m->done) hipEventDestroy(e);
-    if (m->fork) hipEventDestroy(m->fork);
+    if (m->exec) (void)hipGraphExecDestroy(m->exec);
+    if (m->graph) (void)hipGraphDestroy(m->graph);
+    for (void* w : m->ws) (void)hipFree(w);
+    for (hipStream_t st : m->side) (void)hipStreamDestroy(st);
+    for (hipEvent_t e : m->done) (void)hipEventDestroy(e);
+    if (m->fork) (void)hipEventDestroy(m->fork);
     delete m;
 }
 
@@ -1220,8 +1220,8 @@ safr_status safr_multi_execute(safr_multi* m, const float* const* wf, float* con
     bool hit = m->exec && m->g_stream == s;
     for (int i = 0; hit && i < m->count; ++i) hit = m->g_wf[i] == wf[i] && m->g_out[i] == out[i];
     if (!hit) {
-        if (m->exec) hipGraphExecDestroy(m->exec);
-        if (m->graph) hipGraphDestroy(m->graph);
+        if (m->exec) (void)hipGraphExecDestroy(m->exec);
+        if (m->graph) (void)hipGraphDestroy(m->graph);
         m->exec = nullptr;
         m->graph = nullptr;
         HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -1229,7 +1229,7 @@ safr_status safr_multi_execute(safr_multi* m, const float* const* wf, float* con
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(s, &g);
         if (st != SAFR_OK) {
-            if (g) hipGraphDestroy(g);
+            if (g) (void)hipGraphDestroy(g);
             return st;
         }
         if (e != hipSuccess) return fail(SAFR_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
@@ -1257,8 +1257,8 @@ safr_status safr_multi_autotune(safr_multi* m, const float* const* wf, float* co
         if (st != SAFR_OK) return st;
     }
     if (m->exec) {
-        hipGraphExecDestroy(m->exec);
-        hipGraphDestroy(m->graph);
+        (void)hipGraphExecDestroy(m->exec);
+        (void)hipGraphDestroy(m->graph);
         m->exec = nullptr;
         m->graph = nullptr;
     }

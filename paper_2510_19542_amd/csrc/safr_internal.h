@@ -222,7 +222,7 @@ inline void allow_large_lds(const void* kernel) {
     static thread_local int ndone = 0;
     for (int i = 0; i < ndone; ++i)
         if (done[i] == kernel) return;
-    hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     (void)hipGetLastError();
     if (ndone < 64) done[ndone++] = kernel;
 }

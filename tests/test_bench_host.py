@@ -19,21 +19,43 @@ class _Desc:
 def test_algorithmic_bytes_of_the_morfeo_step():
     ab = bench.algorithmic_bytes(_Desc, 69, 64)
     wf, out = 9 * 69 * 69 * 4, 9 * 256 * 256 * 4            # wavefronts in, layers out per frame
-    B = (6 + 3) * 9 * 129 * 256 * 8                          # both groups' B, FP32 complex, read once
-    assert (wf, out, B) == (171_396, 2_359_296, 21_399_552)
-    assert ab["step"] == 64 * (wf + out) + B == 183_363_840
-    assert ab["per_kernel"]["rows"] == 64 * wf
-    assert ab["per_kernel"]["cols"] == 6 * 9 * 129 * 256 * 8
-    assert ab["per_kernel"]["out"] == 64 * out + 9 * 6 * 256 * 256 * 4
+    B_lgs = 128 * 256 * 9 * 6 * 8                            # laser group's FP32 B, columns below Nyquist
+    basis = 9 * 6 * 256 * 256 * 4                            # natural-star basis images, FP32
+    assert (wf, out, B_lgs, basis) == (171_396, 2_359_296, 14_155_776, 14_155_776)
+    assert ab["per_kernel"] == {"rows": 64 * wf, "cols": B_lgs, "out": 64 * out + basis}
+    assert ab["step"] == 64 * (wf + out) + B_lgs + basis
+    # the paper's algorithm: both groups' B over the half spectrum instead of the basis images
+    assert ab["method_step"] == 64 * (wf + out) + (6 + 3) * 9 * 129 * 256 * 8 == 183_363_840
 
 
-def test_algorithmic_flops_follow_the_table_1_model():
-    af = bench.algorithmic_flops(_Desc, 1)
-    fft = 2.5 * 256 * 256 * 16                               # benchFFT: 2.5 N log2 N, N = M^2
-    fwd, inv, app = 9 * fft, 2 * 9 * fft, 8 * 9 * 9 * 129 * 256
-    assert abs(af["step"] - (fwd + inv + app)) < 1.0
-    assert abs(af["step"] - 92.18e6) < 0.01e6
-    assert abs(sum(af["per_kernel"].values()) - af["step"]) < 1.0
+def test_flops_credit_each_kernel_with_the_work_it_performs():
+    af = bench.algorithmic_flops(_Desc, 69, 1)
+    c1 = 5 * 256 * 8                                         # benchFFT, complex 256-point transform
+    rows = 6 * 35 * c1 + 6 * 9 * 69 * 69                     # 35 packed row pairs per laser star + moments
+    cols = (6 + 9) * 128 * c1 + 8 * 9 * 6 * 128 * 256 + 8 * 6 * 128 * 256
+    out = 9 * 128 * c1 + 2 * 6 * 9 * 256 * 256              # C2R rows + 6 basis multiply-adds per pixel
+    assert (rows, cols, out) == (2_407_494, 35_389_440, 18_874_368)
+    assert {k: round(v) for k, v in af["per_kernel"].items()} == {"rows": rows, "cols": cols, "out": out}
+    assert abs(af["step"] - (rows + cols + out)) < 1.0
+    # Table 1 for the whole method: 9 forward + 2 x 9 inverse real 2-D transforms + the apply
+    fft = 2.5 * 256 * 256 * 16
+    assert abs(af["method_step"] - (9 * fft + 2 * 9 * fft + 8 * 9 * 9 * 129 * 256)) < 1.0
+    assert abs(af["method_step"] - 92.18e6) < 0.01e6
+    # the 64-frame column pass: 2.265 GFLOP
+    assert abs(bench.algorithmic_flops(_Desc, 69, 64)["per_kernel"]["cols"] - 2.2649e9) < 1e5
+
+
+def test_single_kind_asterism_transforms_every_star():
+    class D:
+        M, J, L, groups = 64, 4, 2, 1
+        group_size = (4, 0)
+        B_complex_per_group = (33 * 64 * 2 * 4, 0)
+    af = bench.algorithmic_flops(D, 33, 1)
+    c1 = 5 * 64 * 6
+    assert round(af["per_kernel"]["rows"]) == 4 * 17 * c1
+    assert round(af["per_kernel"]["cols"]) == (4 + 2) * 32 * c1 + 8 * 2 * 4 * 32 * 64
+    assert round(af["per_kernel"]["out"]) == 2 * 32 * c1
+    assert bench.algorithmic_bytes(D, 33, 1)["per_kernel"]["out"] == 2 * 64 * 64 * 4
 
 
 def test_more_than_one_gpu_is_refused_before_any_device_work():
