@@ -79,6 +79,10 @@ __device__ __forceinline__ void store_f2(__amdgpu_buffer_rsrc_t r, int byte_off,
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, byte_off, 0, 0);
 }
 
+// byte offset beyond every descriptor's range: a buffer store there is dropped by the hardware (lanes without
+// work store there instead of branching around the store)
+constexpr int kDropOffset = 0x7FFFFFF8;
+
 // linear block -> (column block, frame run), XCD-contiguous (blocks are dealt to the 8 XCDs round-robin)
 __device__ __forceinline__ bool xcd_work(int nwork, int& w) {
     const int b = blockIdx.x, per = gridDim.x / 8;
@@ -88,7 +92,7 @@ __device__ __forceinline__ bool xcd_work(int nwork, int& w) {
 
 }  // namespace
 
-template <int M, int NF, int GC, int LC, int MODE, int LSPLIT = 1>
+template <int M, int NF, int GC, int LC, int MODE, int LSPLIT = 1, int NN = 0>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 2 : 3))) void cols_kernel(ColArgs a) {
     using S = FftShape<M>;
     constexpr int T = S::T, N1 = S::N1, NTEAM = 256 / T, TL = team_lds<M>() + 2;   // slot stride, 4 banks apart
@@ -124,9 +128,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
     const int fend = min(a.frames, fbeg + a.frames_per_block);
     const int tid = threadIdx.x, team = tid / T, t = tid % T;
     const int c = tid / M, j = tid % M;                        // apply: column in block, frequency
-    const int k = kb * CPW + c;
-    const bool kvalid = k < KC;
-    const GroupArgs& gr = a.grp;
+    const int k = kb * CPW + c;                                // < KC: blocks past the work left above
     auto slot = [&](int cc, int f, int s) { return slots + ((size_t)(cc * NF + f) * SPF + s) * TL; };
 
     // forward tasks: (column, frame, star); rounds of NTEAM teams
@@ -135,6 +137,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
     float2 xf[FR_MAX][N1];
     // R of frames f0 .. f0 + NF - 1 through one descriptor (byte offsets stay below 2^31)
     const int fstride = a.J * Kh * a.n;                        // float2 per frame of R
+    // pupil rows: compile-time when NN > 0.  Team thread t's inputs are the column's rows N2 n1 + t, so only
+    // the n1 in [WLO, WHI] can meet the pupil rows p0 .. p0 + n - 1; the others are literal zeros (no load,
+    // no register)
+    constexpr int P0 = NN > 0 ? (M - NN + 1) / 2 : 0;
+    constexpr int WLO = NN > 0 && P0 - T + 1 > 0 ? (P0 - T + 1 + S::N2 - 1) / S::N2 : 0;
+    constexpr int WHI = NN > 0 ? ((P0 + NN - 1) / S::N2 < N1 - 1 ? (P0 + NN - 1) / S::N2 : N1 - 1) : N1 - 1;
+    const int pn = NN > 0 ? NN : a.n, pp0 = NN > 0 ? P0 : a.p0;
+    // every load is issued (rows outside the pupil, idle teams and frames past the run read offset 0 of the
+    // descriptor and are replaced by zero), so the loads need no branches and their waits can be counted
     auto load_fwd = [&](int f0, int round, float2 (&x)[N1]) {
         const int task = round * NTEAM + team;
         const int cc = task / (NF * G), rem = task - cc * (NF * G);
@@ -143,33 +154,49 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
         const bool ok = task < ftasks && kk < KC && f < fend;
         const int nfr = min(NF, fend - f0);
         const __amdgpu_buffer_rsrc_t rr = block_rsrc(a.R + (size_t)f0 * fstride, (unsigned)(nfr * fstride * 8));
-        const int colb = ((fl * a.J + gr.star[g]) * Kh + kk) * a.n;
+        const int colb = ((fl * a.J + g) * Kh + kk) * a.n;       // R holds the group's stars first
 #pragma unroll
         for (int n1 = 0; n1 < N1; ++n1) {
-            const int pr = S::N2 * n1 + t - a.p0;
-            x[n1] = (ok && pr >= 0 && pr < a.n) ? load_f2(rr, (colb + pr) * 8) : make_float2(0.f, 0.f);
+            if (n1 < WLO || n1 > WHI) {
+                x[n1] = make_float2(0.f, 0.f);
+                continue;
+            }
+            const int pr = S::N2 * n1 + t - pp0;
+            const bool in = ok && pr >= 0 && pr < pn;
+            const float2 v = load_f2(rr, in ? (colb + pr) * 8 : 0);
+            x[n1] = in ? v : make_float2(0.f, 0.f);
         }
     };
 
     const float2 twv = tid < M ? a.tw[tid] : make_float2(0.f, 0.f);
     float2 xh = make_float2(0.f, 0.f), yh = make_float2(0.f, 0.f);
-    if (MODE != 0 && kvalid) {
+    if (MODE != 0) {
         xh = a.Xh[(size_t)k * M + j];
         yh = a.Yh[(size_t)k * M + j];
     }
     if (tid < M) tws[tid] = twv;
     const __amdgpu_buffer_rsrc_t Brs = block_rsrc(a.B + (size_t)kb * L * G * 256, (unsigned)(L * G * 256 * 8));
 
-    for (int f0 = fbeg; f0 < fend; f0 += NF) {
-        // the first round's forward inputs; each later round's are requested after the previous
-        // round's first pass, so at most two rounds of inputs are held at once
-        if constexpr (FIX) load_fwd(f0, 0, xf[0]);
+    // Software pipelined over the block's frames: the loop body runs the inverse transforms of one iteration
+    // (NF frames) and then the forward transforms and the apply of the next.  With the pupil size at compile
+    // time (PFN: only the inputs that can meet the pupil rows are held) the next iteration's first forward
+    // inputs are requested at the start of the body, before its layer-spectrum stores: the vector-memory
+    // counter counts loads and stores in issue order, so inputs requested after those stores could only be
+    // waited for together with them, and inputs carried over the loop's back edge would be waited for when
+    // the compiler copies them into place.  Otherwise (all M inputs of a round in registers) they are
+    // requested at the start of the forward transforms.  Each later round's inputs are requested after the
+    // previous round's first pass, so at most two rounds of inputs are held at once.
+    //
+    // forward transforms and apply of the NF frames from f0 (for compile-time shapes their first round's
+    // inputs are in xf[0] already)
+    constexpr bool PFN = FIX && NN > 0;        // next inputs requested ahead of the stores (pupil size known)
+    auto fwd_apply = [&](int f0) {
+        if constexpr (FIX && !PFN) load_fwd(f0, 0, xf[0]);
         // tip/tilt plane coefficients of this iteration's frames, requested now and stored after the
         // forward transforms
-        const PlaneArgs pa{a.planes, a.J, G, f0, fend, min(NF, fend - f0) * G};
-        auto star_of = [&](int g) { return gr.star[g]; };
+        const PlaneArgs pa{a.planes, a.J, G, f0, fend, min(NF, fend - f0) * G, 0};
         float2 pl[1];
-        if (MODE != 0) plane_fetch<1>(pa, star_of, pl);
+        if (MODE != 0) plane_fetch<1>(pa, pl);
         __syncthreads();                                        // previous inverse transforms done with the slots
         // 1. forward column transforms into the star slots
         const int frounds = FIX ? FR_MAX : (ftasks + NTEAM - 1) / NTEAM;
@@ -201,67 +228,73 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
         constexpr int BD = 3;                                   // B buffers in flight (prefetch distance 2)
         float2 bq[BD][FIX ? GC : 1];
         if constexpr (FIX) {
-            if (kvalid) {
 #pragma unroll
-                for (int q = 0; q < BD - 1; ++q) {
-                    if (q < LB && (LSPLIT == 1 || q < nl)) {
+            for (int q = 0; q < BD - 1; ++q) {
+                if (q < LB && (LSPLIT == 1 || q < nl)) {
 #pragma unroll
-                        for (int g = 0; g < GC; ++g) bq[q][g] = load_b(Brs, tid * 8, (l0 + q) * GC + g);
-                    }
+                    for (int g = 0; g < GC; ++g) bq[q][g] = load_b(Brs, tid * 8, (l0 + q) * GC + g);
                 }
             }
         }
         // tip/tilt plane coefficients of this iteration's frames (used by the apply, after the barrier)
-        if (MODE != 0) plane_put<1>(pa, star_of, pl, coef);
+        if (MODE != 0) plane_put<1>(pa, pl, coef);
         __syncthreads();
 
         // 2. apply: b_l(j) = sum_g B[l][g][j] d_g(j) for the NF frames
-        if (kvalid) {
-            if constexpr (FIX) {
-                float2 dv[NF][GC];
+        if constexpr (FIX) {
+            float2 dv[NF][GC];
 #pragma unroll
-                for (int fl = 0; fl < NF; ++fl)
+            for (int fl = 0; fl < NF; ++fl)
 #pragma unroll
-                    for (int g = 0; g < GC; ++g) {
-                        const float2 d = slot(c, fl, g)[j];
-                        dv[fl][g] = MODE != 0 ? remove_plane(d, coef[fl * GC + g], xh, yh) : d;
-                    }
-                // B of layer l + 2 is requested before the products of layer l
-#pragma unroll
-                for (int l = 0; l < LB; ++l) {
-                    if (LSPLIT > 1 && l >= nl) break;
-                    const float2* bv = bq[l % BD];
-                    if (l + BD - 1 < LB && (LSPLIT == 1 || l + BD - 1 < nl)) {
-#pragma unroll
-                        for (int g = 0; g < GC; ++g) bq[(l + BD - 1) % BD][g] = load_b(Brs, tid * 8, (l0 + l + BD - 1) * GC + g);
-                    }
-#pragma unroll
-                    for (int fl = 0; fl < NF; ++fl) {
-                        float2 acc = make_float2(0.f, 0.f);
-#pragma unroll
-                        for (int g = 0; g < GC; ++g) acc = cmac(acc, bv[g], dv[fl][g]);
-                        slot(c, fl, l)[j] = acc;
-                    }
+                for (int g = 0; g < GC; ++g) {
+                    const float2 d = slot(c, fl, g)[j];
+                    dv[fl][g] = MODE != 0 ? remove_plane(d, coef[fl * GC + g], xh, yh) : d;
                 }
-            } else {
-                for (int l = 0; l < L; ++l) {
+            // B of layer l + 2 is requested before the products of layer l
+#pragma unroll
+            for (int l = 0; l < LB; ++l) {
+                if (LSPLIT > 1 && l >= nl) break;
+                const float2* bv = bq[l % BD];
+                if (l + BD - 1 < LB && (LSPLIT == 1 || l + BD - 1 < nl)) {
+#pragma unroll
+                    for (int g = 0; g < GC; ++g) bq[(l + BD - 1) % BD][g] = load_b(Brs, tid * 8, (l0 + l + BD - 1) * GC + g);
+                }
+#pragma unroll
+                for (int fl = 0; fl < NF; ++fl) {
                     float2 acc = make_float2(0.f, 0.f);
-                    for (int g = 0; g < G; ++g) {
-                        float2 d = slot(c, 0, g)[j];
-                        if (MODE != 0) d = remove_plane(d, coef[g], xh, yh);
-                        const float2 bv = load_b(Brs, tid * 8, l * G + g);
-                        acc = cmac(acc, bv, d);
-                    }
-                    slot(c, 0, LS + l)[j] = acc;
+#pragma unroll
+                    for (int g = 0; g < GC; ++g) acc = cmac(acc, bv[g], dv[fl][g]);
+                    slot(c, fl, l)[j] = acc;
                 }
             }
+        } else {
+            for (int l = 0; l < L; ++l) {
+                float2 acc = make_float2(0.f, 0.f);
+                for (int g = 0; g < G; ++g) {
+                    float2 d = slot(c, 0, g)[j];
+                    if (MODE != 0) d = remove_plane(d, coef[g], xh, yh);
+                    const float2 bv = load_b(Brs, tid * 8, l * G + g);
+                    acc = cmac(acc, bv, d);
+                }
+                slot(c, 0, LS + l)[j] = acc;
+            }
         }
-        __syncthreads();
-
-        // 3. inverse column transforms of the layer slots, in place, written to C
+    };
+    // inverse transforms of the NF frames from f0 (the apply's layer spectra complete in LDS)
+    auto inverse = [&](int f0) {
+        // 3. inverse column transforms of the layer slots, in place, written to C.  Compile-time shapes run a
+        // fixed number of rounds with every lane storing: a lane without a task (or whose frame lies past the
+        // run) stores to an offset beyond the descriptor's range, which the hardware drops, so the stores need
+        // no branches and the waits after them can be counted.
         const int itasks = CPW * NF * nl;
-        for (int base = 0; base < itasks; base += NTEAM) {
-            const int task = base + team;
+        constexpr int IR_MAX = FIX ? (CPW * NF * LB + NTEAM - 1) / NTEAM : 1;
+        const int irounds = FIX ? IR_MAX : (itasks + NTEAM - 1) / NTEAM;
+        const int nfr = min(NF, fend - f0);
+        const size_t cfr = (size_t)L * Kh * M;                 // float2 per frame of C
+        const __amdgpu_buffer_rsrc_t cr = block_rsrc(a.C + c_index(f0, 0, L, M, 0, 0), (unsigned)(nfr * cfr * 8));
+#pragma unroll
+        for (int r = 0; r < irounds; ++r) {
+            const int task = r * NTEAM + team;
             const int cc = task / (NF * nl), rem = task - cc * (NF * nl);
             const int fl = rem / nl, l = rem - fl * nl;
             const int kk = kb * CPW + cc, f = f0 + fl;
@@ -273,19 +306,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
                 for (int n1 = 0; n1 < N1; ++n1) x[n1] = sl[S::N2 * n1 + t];
             }
             team_sync();                        // the team's own slot
-            if (active) fft_pass1_regs<M, +1>(t, sl, tws, x);
+            if (active) fft_pass1_regs<M, +1>(t, sl, tws, x);   // idle teams must not write another team's slot
             team_sync();                        // the team's own slot
-            if (active && kk < KC && f < fend) {
-                const int nfr = min(NF, fend - f0);
-                const size_t cfr = (size_t)L * Kh * M;        // float2 per frame of C
-                const __amdgpu_buffer_rsrc_t cr = block_rsrc(a.C + c_index(f0, 0, L, M, 0, 0), (unsigned)(nfr * cfr * 8));
-                const int base = (int)(c_index(fl, l0 + l, L, M, kk, 0));
-                fft_pass2<M, +1>(t, sl, [&](int p, float2 v) {
-                    store_f2(cr, (base + (p >> 3) * (Kh * 8) + (p & 7)) * 8, v);
-                });
-            }
+            // idle teams read slot 0 (another team's data, possibly mid-transform) and drop their stores
+            const bool store = active && f < fend;
+            const int base = store ? (int)(c_index(fl, l0 + l, L, M, kk, 0)) : 0;
+            fft_pass2<M, +1>(t, sl, [&](int p, float2 v) {
+                store_f2(cr, store ? (base + (p >> 3) * (Kh * 8) + (p & 7)) * 8 : kDropOffset, v);
+            });
         }
+    };
+    if constexpr (PFN) load_fwd(fbeg, 0, xf[0]);
+    fwd_apply(fbeg);
+    int f0 = fbeg;
+    for (; f0 + NF < fend; f0 += NF) {
+        __syncthreads();                                        // the apply's layer spectra
+        if constexpr (PFN) load_fwd(f0 + NF, 0, xf[0]);         // ahead of this iteration's stores
+        inverse(f0);
+        fwd_apply(f0 + NF);
     }
+    __syncthreads();
+    inverse(f0);
 }
 
 size_t cols_lds_bytes(int M, int G, int L, int nf, bool fixed) {
@@ -310,29 +351,36 @@ hipError_t launch_cols_kernel(K kernel, int M, int nf, bool fixed, const ColArgs
     return hipGetLastError();
 }
 
-// shapes with a compile-time kernel: (M, L, group size, mode)
+// shapes with a compile-time kernel: (M, L, group size, mode, pupil size of the configured workload); a
+// matching shape with another pupil size takes the same kernels with the pupil size at run time
 #define SAFR_FIXED_SHAPES(X) \
-    X(256, 9, 6, 1)          \
-    X(256, 9, 6, 0)          \
-    X(128, 5, 6, 0)          \
-    X(64, 2, 4, 0)           \
-    X(64, 3, 4, 0)
+    X(256, 9, 6, 1, 69)      \
+    X(256, 9, 6, 0, 69)      \
+    X(128, 5, 6, 0, 41)      \
+    X(64, 2, 4, 0, 33)       \
+    X(64, 3, 4, 0, 33)
 
 // fewer column blocks than CUs (one-frame calls at M = 256): split the layers of each column over two blocks
 constexpr int kCUs = 256;
 
-template <int M, int G, int L, int MODE>
-hipError_t launch_fixed(const ColArgs& a, int nf, int frames, hipStream_t s) {
+template <int M, int G, int L, int MODE, int NN>
+hipError_t launch_fixed_n(const ColArgs& a, int nf, int frames, hipStream_t s) {
     const int CPW = 256 / M, kblocks = (M / 2) / CPW;
     const int runs = (frames + a.frames_per_block - 1) / a.frames_per_block;
     if (nf == 1 && L >= 2 && kblocks * runs * 2 <= kCUs + kCUs / 8)
-        return launch_cols_kernel(&cols_kernel<M, 1, G, L, MODE, 2>, M, 1, true, a, frames, s, 2);
+        return launch_cols_kernel(&cols_kernel<M, 1, G, L, MODE, 2, NN>, M, 1, true, a, frames, s, 2);
     switch (nf) {
-        case 1: return launch_cols_kernel(&cols_kernel<M, 1, G, L, MODE>, M, 1, true, a, frames, s);
-        case 2: return launch_cols_kernel(&cols_kernel<M, 2, G, L, MODE>, M, 2, true, a, frames, s);
-        case 4: return launch_cols_kernel(&cols_kernel<M, 4, G, L, MODE>, M, 4, true, a, frames, s);
+        case 1: return launch_cols_kernel(&cols_kernel<M, 1, G, L, MODE, 1, NN>, M, 1, true, a, frames, s);
+        case 2: return launch_cols_kernel(&cols_kernel<M, 2, G, L, MODE, 1, NN>, M, 2, true, a, frames, s);
+        case 4: return launch_cols_kernel(&cols_kernel<M, 4, G, L, MODE, 1, NN>, M, 4, true, a, frames, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+template <int M, int G, int L, int MODE, int NN>
+hipError_t launch_fixed(const ColArgs& a, int nf, int frames, hipStream_t s) {
+    return a.n == NN ? launch_fixed_n<M, G, L, MODE, NN>(a, nf, frames, s)
+                     : launch_fixed_n<M, G, L, MODE, 0>(a, nf, frames, s);
 }
 
 template <int M>
@@ -344,7 +392,7 @@ hipError_t launch_generic(const ColArgs& a, int frames, hipStream_t s) {
 }  // namespace
 
 bool cols_fixed_shape(int M, int L, int G, int mode) {
-#define SAFR_MATCH(m, l, g, md) \
+#define SAFR_MATCH(m, l, g, md, nn) \
     if (M == m && L == l && G == g && mode == md) return true;
     SAFR_FIXED_SHAPES(SAFR_MATCH)
 #undef SAFR_MATCH
@@ -354,9 +402,9 @@ bool cols_fixed_shape(int M, int L, int G, int mode) {
 hipError_t launch_cols(int M, const ColArgs& a, int nf, int frames, hipStream_t s) {
     const int G = a.grp.G, mode = a.grp.mode;
     if (a.prefetch && cols_fixed_shape(M, a.L, G, mode)) {
-#define SAFR_LAUNCH(m, l, g, md)                    \
+#define SAFR_LAUNCH(m, l, g, md, nn)                \
     if (M == m && a.L == l && G == g && mode == md) \
-        return launch_fixed<m, g, l, md>(a, nf, frames, s);
+        return launch_fixed<m, g, l, md, nn>(a, nf, frames, s);
         SAFR_FIXED_SHAPES(SAFR_LAUNCH)
 #undef SAFR_LAUNCH
     }

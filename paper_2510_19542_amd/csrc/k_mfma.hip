@@ -98,11 +98,10 @@ __global__ __launch_bounds__(256) void cols_mfma_kernel(MfmaArgs a) {
 
     for (int i = tid; i < M; i += 256) tws[i] = a.tw[i];
     if (mode != 0) {
-        const PlaneArgs pa{a.planes, a.J, G, fb, fb + nf, nf * G};   // nf = valid frames of the block
-        auto star_of = [&](int g) { return gr.star[g]; };
+        const PlaneArgs pa{a.planes, a.J, G, fb, fb + nf, nf * G, 0};   // nf = valid frames of the block
         float2 pl[1];
-        plane_fetch<1>(pa, star_of, pl);
-        plane_put<1>(pa, star_of, pl, coef);
+        plane_fetch<1>(pa, pl);
+        plane_put<1>(pa, pl, coef);
     }
     __syncthreads();
 
@@ -113,7 +112,7 @@ __global__ __launch_bounds__(256) void cols_mfma_kernel(MfmaArgs a) {
         const bool active = task < ftasks;
         const int f = task / G, g = task % G;
         if (active) {
-            const float2* col = a.R + (((size_t)(fb + f) * a.J + gr.star[g]) * Kh + k) * n;
+            const float2* col = a.R + (((size_t)(fb + f) * a.J + g) * Kh + k) * n;   // group slot g
             fft_pass1<M, -1>(t, xch, tws, [&](int p) -> float2 {
                 const int pr = p - a.p0;
                 return (pr >= 0 && pr < n) ? col[pr] : make_float2(0.f, 0.f);

@@ -25,10 +25,16 @@
 //
 // C layout (row tiles of 8): C[f][l][p / 8][k][p % 8]; a block's rows of one
 // frame are one contiguous run.
+#include <type_traits>
+
 #include "fft_device.h"
 #include "safr_internal.h"
 
 namespace safr {
+
+#ifndef OUT_WAVES
+#define OUT_WAVES 2
+#endif
 
 namespace {
 
@@ -61,13 +67,24 @@ struct OutShape {
 
 }  // namespace
 
-// NB: natural-star basis images held in registers (0: none; a.nb <= NB, the rest are re-read)
-template <int M, int RT, int NB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void out_kernel(OutArgs a) {
+// NB: natural-star basis images (0: none; 2, 4 or 6: exactly that many; 8: the first 8 of a.nb >= 8, the rest
+// re-read per frame).  INTEG: the closed-loop integrator (a.prev is read).
+//
+// Memory order of an iteration: the vector-memory counter counts loads and stores in issue order, so a
+// load can only be waited for together with everything issued before it.  Each iteration therefore
+// issues, after its transforms, first the loads it needs itself (its basis pixels), then the next
+// iteration's spectra and plane coefficients, and only then its stores; the epilogue waits for the basis
+// pixels with the prefetch still in flight, and the next iteration waits for the prefetch without waiting
+// for the stores.  Every load is issued unconditionally (inputs past the frame run read the run's last
+// frame, which is not stored), so no wait is placed conservatively behind a branch.
+template <int M, int RT, int NB, bool INTEG>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OUT_WAVES))) void out_kernel(OutArgs a) {
     constexpr bool MIXED = NB > 0;
+    constexpr bool TAIL = NB == 8;                                  // more basis images than registers hold
     using S = FftShape<M>;
     using O = OutShape<M, RT>;
-    constexpr int T = O::T, RS = O::RS, Kh = O::Kh, NF = O::NF, TPF = O::TPF;
+    constexpr int T = O::T, RS = O::RS, Kh = O::Kh, NF = O::NF, TPF = O::TPF, V4 = O::V4;
+    constexpr int NBR = MIXED ? NB : 1;
     extern __shared__ float2 smem[];
 
     const int runs = (a.frames + a.frames_per_block - 1) / a.frames_per_block;
@@ -81,6 +98,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void o
     const int team = tid / T;
     const int t = tid % T;
     const int L = a.L;
+    const int nb = MIXED ? (TAIL ? a.nb : NB) : 0;
 
     float2* tws = smem;                                             // [M]
     float2* reg = tws + M + team * RS;                              // this team's region
@@ -101,8 +119,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void o
             const int e = lane + 64 * i;
             const int tile = wave * O::TPW + e / O::TILE4, s4 = e % O::TILE4;
             const int fi = tile / (RT / 8), pb = tile % (RT / 8);
-            const int f = fi0 + fi;
-            ld[i] = f < fend ? run(f)[pb * 4 * Kh + s4] : make_float4(0.f, 0.f, 0.f, 0.f);
+            ld[i] = run(min(fi0 + fi, fend - 1))[pb * 4 * Kh + s4];
         }
     };
     auto stash = [&]() {
@@ -117,22 +134,42 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void o
             dst[Kh + k] = make_float2(ld[i].z, ld[i].w);
         }
     };
+    // natural stars' plane coefficients (b_g, c_g) of an iteration's frames, [NF][ng] as float2
+    auto planes_of = [&](int f0) {
+        return PlaneArgs{a.planes, a.J, nb / 2, f0, fend, min(NF, fend - f0) * (nb / 2), a.ngs_base};
+    };
 
     const float2 twv = tid < M ? a.tw[tid] : make_float2(0.f, 0.f);
     issue(fbeg);
+    float2 pl[1];
+    if constexpr (MIXED) plane_fetch<1>(planes_of(fbeg), pl);
+    // the block's basis pixels (its rows, every frame): loaded once, before any store
+    float4 pv[V4][NBR];
+    if constexpr (MIXED) {
+#pragma unroll
+        for (int v = 0; v < V4; ++v) {
+            const int e = 4 * (tid + 256 * v);
+            const int r = e / M, q = e % M;
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+                pv[v][i] = *reinterpret_cast<const float4*>(a.P + (((size_t)l * nb + i) * M + r0 + r) * M + q);
+        }
+    }
     if (tid < M) tws[tid] = twv;
+    stash();
+    if constexpr (MIXED) plane_put<1>(planes_of(fbeg), pl, reinterpret_cast<float2*>(coef));
+    // every load so far (the basis pixels included) complete here, once: the loop body's waits then only
+    // count what the body itself issued, and a later iteration's epilogue does not wait for the previous
+    // iteration's stores on the basis pixels' account (vmcnt(0); expcnt and lgkmcnt at their maxima)
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __syncthreads();                                        // twiddles, spectra and plane coefficients
 
-    auto star_of = [&](int g) { return a.ngs_star[g]; };
-    for (int f0 = fbeg; f0 < fend; f0 += NF) {
-        __syncthreads();                                    // previous epilogue done with the regions
-        stash();
-        // natural stars' plane coefficients of this iteration's frames: requested now, stored before the
-        // epilogue
-        const PlaneArgs pa{a.planes, a.J, a.nb / 2, f0, fend, min(NF, fend - f0) * (a.nb / 2)};
-        float2 pl[1];
-        if constexpr (MIXED) plane_fetch<1>(pa, star_of, pl);
-        team_sync();                        // the wavefront's own teams' regions
-
+    // one iteration: NF frames from f0, whose spectra and plane coefficients are in LDS.  PF: the next
+    // iteration's are requested after the transforms and put into LDS at the end (waiting for them then
+    // passes over this iteration's stores only); FULL: all NF frames lie in the run.  Both are compile-time,
+    // so the body has no branches that would blur the counts the compiler's waits are based on.
+    auto body = [&](int f0, auto pf, auto full) {
+        constexpr bool PF = decltype(pf)::value, FULL = decltype(full)::value;
         // packed C2R: Z[q] = A[q] + i B[q] over the Hermitian extensions of the team's two rows
         float2 x[S::N1];
         {
@@ -169,73 +206,74 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void o
                 rows[M + p] = v.y;
             });
         }
-        // natural stars' plane coefficients (b_g, c_g) of this iteration's frames, [NF][ng] as float2
-        if (f0 + NF < fend) issue(f0 + NF);
-        if constexpr (MIXED) plane_put<1>(pa, star_of, pl, reinterpret_cast<float2*>(coef));
-        __syncthreads();
+        if constexpr (PF) {
+            issue(f0 + NF);
+            if constexpr (MIXED) plane_fetch<1>(planes_of(f0 + NF), pl);
+        }
+        __syncthreads();                    // rows of every team
 
-        // epilogue: 4-pixel groups, coalesced stores; a group's basis pixels are read (from L2) once per
-        // iteration and serve its NF frames
-#pragma unroll 1
-        for (int v = 0; v < O::V4; ++v) {
+        // epilogue: 4-pixel groups, coalesced stores; a group's basis pixels serve every frame of the block
+#pragma unroll
+        for (int v = 0; v < V4; ++v) {
             const int e = 4 * (tid + 256 * v);
             const int r = e / M, q = e % M;
-            float4 pv[MIXED ? NB : 1];
-            if constexpr (MIXED) {
-                // an opaque zero keeps these loop-invariant loads inside the frame loop (hoisted, they would
-                // hold 4 NB registers through the transforms and halve the occupancy)
-                int zero;
-                asm volatile("s_mov_b32 %0, 0" : "=s"(zero));
-                const float* Pb = a.P + zero;
-#pragma unroll
-                for (int i = 0; i < NB; ++i)
-                    if (i < a.nb)
-                        pv[i] = *reinterpret_cast<const float4*>(Pb + (((size_t)l * a.nb + i) * M + r0 + r) * M + q);
-            }
 #pragma unroll
             for (int fi = 0; fi < NF; ++fi) {
                 const int f = f0 + fi;
-                if (f >= fend) break;
                 const float* src = reinterpret_cast<const float*>(smem + M + (fi * TPF + r / 2) * RS) + (r & 1) * M + q;
                 float4 o = *reinterpret_cast<const float4*>(src);
                 if constexpr (MIXED) {
-                    const float* cf = coef + fi * a.nb;
+                    const float* cf = coef + fi * nb;
 #pragma unroll
                     for (int i = 0; i < NB; ++i) {
-                        if (i < a.nb) {
+                        const float c = cf[i];
+                        o.x = fmaf(c, pv[v][i].x, o.x);
+                        o.y = fmaf(c, pv[v][i].y, o.y);
+                        o.z = fmaf(c, pv[v][i].z, o.z);
+                        o.w = fmaf(c, pv[v][i].w, o.w);
+                    }
+                    if constexpr (TAIL) {
+                        for (int i = NB; i < nb; ++i) {
                             const float c = cf[i];
-                            o.x += c * pv[i].x;
-                            o.y += c * pv[i].y;
-                            o.z += c * pv[i].z;
-                            o.w += c * pv[i].w;
+                            const float4 pw =
+                                *reinterpret_cast<const float4*>(a.P + (((size_t)l * nb + i) * M + r0 + r) * M + q);
+                            o.x = fmaf(c, pw.x, o.x);
+                            o.y = fmaf(c, pw.y, o.y);
+                            o.z = fmaf(c, pw.z, o.z);
+                            o.w = fmaf(c, pw.w, o.w);
                         }
                     }
-                    for (int i = NB; i < a.nb; ++i) {
-                        const float c = cf[i];
-                        const float4 pw =
-                            *reinterpret_cast<const float4*>(a.P + (((size_t)l * a.nb + i) * M + r0 + r) * M + q);
-                        o.x += c * pw.x;
-                        o.y += c * pw.y;
-                        o.z += c * pw.z;
-                        o.w += c * pw.w;
+                }
+                if (FULL || f < fend) {
+                    const size_t oi = (((size_t)f * L + l) * M + r0 + r) * M + q;
+                    if constexpr (INTEG) {          // integrator of the closed loop (Alg. 3)
+                        const float4 pr = *reinterpret_cast<const float4*>(a.prev + oi);
+                        const float keep = 1.f - a.gain;
+                        o.x = fmaf(a.gain, o.x, keep * pr.x);
+                        o.y = fmaf(a.gain, o.y, keep * pr.y);
+                        o.z = fmaf(a.gain, o.z, keep * pr.z);
+                        o.w = fmaf(a.gain, o.w, keep * pr.w);
                     }
+                    // the layers are not read again by the step: streamed past the caches that hold C and the basis
+                    typedef float f32x4 __attribute__((ext_vector_type(4)));
+                    const f32x4 ov = {o.x, o.y, o.z, o.w};
+                    __builtin_nontemporal_store(ov, reinterpret_cast<f32x4*>(a.out + oi));
                 }
-                const size_t oi = (((size_t)f * L + l) * M + r0 + r) * M + q;
-                if (a.prev) {                   // integrator of the closed loop (Alg. 3)
-                    const float4 pr = *reinterpret_cast<const float4*>(a.prev + oi);
-                    const float keep = 1.f - a.gain;
-                    o.x = fmaf(a.gain, o.x, keep * pr.x);
-                    o.y = fmaf(a.gain, o.y, keep * pr.y);
-                    o.z = fmaf(a.gain, o.z, keep * pr.z);
-                    o.w = fmaf(a.gain, o.w, keep * pr.w);
-                }
-                // the layers are not read again by the step: streamed past the caches that hold C and the basis
-                typedef float f32x4 __attribute__((ext_vector_type(4)));
-                const f32x4 ov = {o.x, o.y, o.z, o.w};
-                __builtin_nontemporal_store(ov, reinterpret_cast<f32x4*>(a.out + oi));
             }
         }
-    }
+        if constexpr (PF) {
+            __syncthreads();                // every epilogue done with the regions and the coefficients
+            stash();
+            if constexpr (MIXED) plane_put<1>(planes_of(f0 + NF), pl, reinterpret_cast<float2*>(coef));
+            __syncthreads();
+        }
+    };
+    using yes = std::integral_constant<bool, true>;
+    using no = std::integral_constant<bool, false>;
+    int f0 = fbeg;
+    for (; f0 + NF < fend; f0 += NF) body(f0, yes{}, yes{});
+    if (f0 + NF == fend) body(f0, no{}, yes{});
+    else body(f0, no{}, no{});
 }
 
 bool out_rows_supported(int M, int RT) {
@@ -259,14 +297,19 @@ size_t out_lds_bytes(int M, int RT, int nb) {
 
 namespace {
 
-template <int M, int RT, int NB>
-hipError_t launch_out_t(const OutArgs& a, int frames, hipStream_t s) {
+template <int M, int RT, int NB, bool INTEG>
+hipError_t launch_out_k(const OutArgs& a, int frames, hipStream_t s) {
     const size_t lds = out_lds_bytes(M, RT, a.nb);
-    allow_large_lds(reinterpret_cast<const void*>(&out_kernel<M, RT, NB>));
+    allow_large_lds(reinterpret_cast<const void*>(&out_kernel<M, RT, NB, INTEG>));
     const int fpb = a.frames_per_block;
     const int nwork = (M / RT) * a.L * ((frames + fpb - 1) / fpb);
-    hipLaunchKernelGGL((out_kernel<M, RT, NB>), dim3((nwork + 7) / 8 * 8), dim3(256), lds, s, a);
+    hipLaunchKernelGGL((out_kernel<M, RT, NB, INTEG>), dim3((nwork + 7) / 8 * 8), dim3(256), lds, s, a);
     return hipGetLastError();
+}
+
+template <int M, int RT, int NB>
+hipError_t launch_out_t(const OutArgs& a, int frames, hipStream_t s) {
+    return a.prev ? launch_out_k<M, RT, NB, true>(a, frames, s) : launch_out_k<M, RT, NB, false>(a, frames, s);
 }
 
 template <int M, int NB>
@@ -281,7 +324,8 @@ hipError_t launch_out_rt(const OutArgs& a, int rt, int frames, hipStream_t s) {
     return hipErrorInvalidValue;
 }
 
-// basis images in registers: exactly 2, 4 or 6 of them (one to three natural stars), else the first 8
+// basis images in registers: exactly 2, 4 or 6 of them (one to three natural stars), else the first 8 (and
+// the rest re-read per frame)
 template <int M>
 hipError_t launch_out_m(const OutArgs& a, int rt, int frames, hipStream_t s) {
     switch (a.nb) {

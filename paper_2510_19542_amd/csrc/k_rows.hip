@@ -4,7 +4,7 @@
 // only the n pupil rows are transformed; two real rows are packed into one
 // complex M-point FFT (z = a + i b) and separated afterwards with
 // A[k] = (Z[k] + conj Z[-k]) / 2,  B[k] = (Z[k] - conj Z[-k]) / (2 i).
-// Output: R[f][star][k][row] for k < M/2 (the half spectrum without its Nyquist
+// Output: R[f][slot][k][row] (the star's group slot) for k < M/2 (the half spectrum without its Nyquist
 // column, which B ignores; R keeps a slot for it), rows contiguous so the column
 // pass reads each column as one run.  Each team takes its two rows from global
 // memory straight into the registers of the first transform pass.
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(256) void rows_kernel(RowArgs a) {
     int lg = 0;
     while ((1 << lg) < nteams) ++lg;
     const int npair = (rows + 1) / 2;
-    float2* Rb = a.R + ((size_t)f * a.J + star) * (size_t)Kh * n + r0;
+    float2* Rb = a.R + ((size_t)f * a.J + a.slot[star]) * (size_t)Kh * n + r0;
     for (int idx = tid; idx < (KC << lg); idx += nthr) {
         const int k = idx >> lg;
         const int pr = idx & ((1 << lg) - 1);
@@ -151,9 +151,9 @@ __global__ __launch_bounds__(256) void rows_kernel(RowArgs a) {
     }
 }
 
-// One wavefront per (frame, star): the least-squares plane of Sec. 3.3 from the chunk moments.  Lane q
-// adds chunks q, q + 64, ... (all loads in flight together), then a fixed shuffle tree sums the lanes,
-// so every call adds in the same order.
+// One wavefront per (frame, star): the least-squares plane of Sec. 3.3 from the chunk moments, stored in
+// the star's group slot.  Lane q adds chunks q, q + 64, ... (all loads in flight together), then a fixed
+// shuffle tree sums the lanes, so every call adds in the same order.
 __global__ __launch_bounds__(256) void plane_kernel(PlaneKArgs a) {
     const int i = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(256) void plane_kernel(PlaneKArgs a) {
         s2 += __shfl_xor(s2, o, 64);
     }
     if (lane == 0)
-        a.planes[i] = make_float2(a.tt_b[0] * s0 + a.tt_b[1] * s1 + a.tt_b[2] * s2,
+        a.planes[(size_t)(i / a.J) * a.J + a.slot[i % a.J]] = make_float2(a.tt_b[0] * s0 + a.tt_b[1] * s1 + a.tt_b[2] * s2,
                                   a.tt_c[0] * s0 + a.tt_c[1] * s1 + a.tt_c[2] * s2);
 }
 

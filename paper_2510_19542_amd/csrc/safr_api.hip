@@ -1337,6 +1337,8 @@ safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, in
     ra.J = p->J;
     ra.p0 = p->p0;
     ra.rows_per_block = 2 * p->row_teams;
+    for (int gi = 0, slot = 0; gi < p->ngroups; ++gi)
+        for (int m = 0; m < p->gsize[gi]; ++m) ra.slot[p->gstar[gi][m]] = slot++;
     const int nchunk = (p->n + ra.rows_per_block - 1) / ra.rows_per_block;
     HIP_TRY(launch_rows(p->M, ra, frames, nchunk, p->row_teams, s));
     if (p->mixed) {                     // split tomography: the planes of every (frame, star), once
@@ -1351,6 +1353,8 @@ safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, in
         pk.J = p->J;
         pk.nchunk = nchunk;
         pk.count = frames * p->J;
+        for (int gi = 0, slot = 0; gi < p->ngroups; ++gi)
+            for (int m = 0; m < p->gsize[gi]; ++m) pk.slot[p->gstar[gi][m]] = slot++;
         HIP_TRY(launch_planes(pk, s));
     }
     if (ev) HIP_TRY(hipEventRecord(ev[1], s));
@@ -1358,7 +1362,6 @@ safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, in
     GroupArgs grp{};
     grp.G = p->gsize[0];
     grp.mode = p->mixed ? 1 : 0;
-    for (int m = 0; m < grp.G; ++m) grp.star[m] = p->gstar[0][m];
     if (precision == SAFR_FP32) {
         ColArgs ca{};
         ca.R = R;
@@ -1416,7 +1419,7 @@ safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, in
     oa.P = p->P;
     oa.planes = planes;
     oa.nb = p->nb;
-    for (int m = 0; m < p->nb / 2; ++m) oa.ngs_star[m] = p->gstar[1][m];
+    oa.ngs_base = p->gsize[0];
     oa.L = p->L;
     oa.J = p->J;
     oa.frames = frames;

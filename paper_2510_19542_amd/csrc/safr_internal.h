@@ -17,15 +17,18 @@ constexpr double kSqrtEps = 1.4901161193847656e-08;   // 2^-26: the learned filt
 // The star group the column kernels transform: all stars of a single-kind
 // asterism (mode 0), or the laser stars of a mixed one (mode 1: tip/tilt plane
 // removed).  The natural stars of a mixed asterism enter through precomputed
-// basis images in the output pass (Sec. 3.3).
+// basis images in the output pass (Sec. 3.3).  Per-star data of a call (row
+// spectra, plane coefficients) is stored in group order, the transformed group's
+// stars in slots 0 .. G - 1, so the column kernels address member g directly.
 struct GroupArgs {
     int G;                  // stars in the group
     int mode;               // 0 plain, 1 remove the tip/tilt plane
-    int star[kMaxG];        // star index of member g
 };
 
 // Row pass (forward): pupil mask, tip/tilt moments and the R2C FFT of the n
-// nonzero rows of each zero-extended wavefront.  R layout [f][star][k][n].
+// nonzero rows of each zero-extended wavefront.  R layout [f][slot][k][n] with
+// star g's spectra in its group slot slot[g] (the natural stars of a mixed
+// asterism, which are not transformed, leave their slots unwritten).
 struct RowArgs {
     const float* wf;            // [F][J][n][n]
     float2* R;                  // [F][J][Kh][n]
@@ -34,6 +37,7 @@ struct RowArgs {
     const int* tt_mode;         // [J]: 0 none, 1 remove tip/tilt, 2 plane only (moments, no transform)
     const float2* tw;           // (cos, sin)(2 pi e / M), e < M
     int n, J, p0, rows_per_block;
+    int slot[kMaxJ];            // group slot of star g
 };
 
 // Sum over layers of the commands `lay` ([L][M][M]) sampled by periodic bilinear interpolation at
@@ -72,11 +76,11 @@ __host__ __device__ inline size_t c_index(int f, int l, int L, int M, int k, int
 // Column pass: column FFT of the group's spectra, per-frequency apply of B,
 // inverse column FFT of the L layer spectra into C.
 struct ColArgs {
-    const float2* R;            // [F][J][Kh][n]
+    const float2* R;            // [F][J][Kh][n], group order
     const float2* B;            // [column block][l][g][column in block][j] (FP32 complex)
     float2* C;                  // see c_index
     const float2* tw;
-    const float2* planes;       // tip/tilt plane coefficients per (frame, star), see PlaneArgs
+    const float2* planes;       // tip/tilt plane coefficients per (frame, group slot), see PlaneArgs
     const float2* Xh;           // DFT2 of x * pupil, [Kh][M]
     const float2* Yh;           // DFT2 of y * pupil, [Kh][M]
     GroupArgs grp;
@@ -91,8 +95,8 @@ struct OutArgs {
     float* out;                 // [F][L][M][M]
     const float2* tw;
     const float* P;             // [L][nb][M][M] natural-star basis images (mixed asterisms)
-    const float2* planes;       // tip/tilt plane coefficients per (frame, star), see PlaneArgs
-    int ngs_star[kMaxG];        // star index of natural star g
+    const float2* planes;       // tip/tilt plane coefficients per (frame, group slot), see PlaneArgs
+    int ngs_base;               // group slot of the first natural star (the laser group's size)
     int nb;                     // 2 x natural stars (0: no natural-star part)
     int L, J, frames, frames_per_block;
     const float* prev;          // integrator (Alg. 3): out = (1 - gain) prev + gain layers; nullptr = plain
@@ -144,7 +148,7 @@ struct MfmaArgs {
     const uint16_t* Apack;      // packed real-split B tiles, hi and lo (bf16 bit patterns)
     float2* C;
     const float2* tw;
-    const float2* planes;       // tip/tilt plane coefficients per (frame, star), see PlaneArgs
+    const float2* planes;       // tip/tilt plane coefficients per (frame, group slot), see PlaneArgs
     const float2* Xh;
     const float2* Yh;
     GroupArgs grp;
@@ -167,51 +171,55 @@ struct BasisArgs {
     float* P;                   // [L][2 G][M][M]
 };
 
-// Tip/tilt plane coefficients (b, c) of every (frame, star) of a call, planes[f][star] (float2), formed
-// once by plane_kernel from the row pass's partial moments.  A pass needing those of `count` pairs,
-// pair i = (frame f0 + i / per, star star_of(i % per)), frames at or beyond fend using fend - 1,
-// requests them early with plane_fetch (thread i % blockDim takes pair i, PMAX rounds in registers)
-// and stores them to out[i] (LDS) with plane_put; pairs beyond PMAX rounds are copied there directly.
-// Every thread of the block calls both with the same arguments.
+// Tip/tilt plane coefficients (b, c) of every (frame, star) of a call, formed once by plane_kernel from the
+// row pass's partial moments and stored in group order: planes[f][slot] (float2), the laser (or only)
+// group's stars in slots 0 .. G0 - 1 and the natural stars of a mixed asterism after them, so a pass reads
+// its group's coefficients without looking up star indices (a dependent load would make it wait for every
+// earlier memory operation).  A pass needing those of `count` pairs, pair i = (frame f0 + i / per, group
+// slot base + i % per), frames at or beyond fend using fend - 1, requests them early with plane_fetch
+// (thread i % blockDim takes pair i, PMAX rounds in registers) and stores them to out[i] (LDS) with
+// plane_put; pairs beyond PMAX rounds are copied there directly.  Every thread of the block calls both
+// with the same arguments.
 struct PlaneArgs {
     const float2* planes;
-    int J, per, f0, fend, count;
+    int J, per, f0, fend, count, base;
 };
 
-template <class StarOf>
-__device__ inline float2 plane_at(const PlaneArgs& p, StarOf star_of, int i) {
+__device__ inline float2 plane_at(const PlaneArgs& p, int i) {
     const int f = min(p.f0 + i / p.per, p.fend - 1);
-    return p.planes[(size_t)f * p.J + star_of(i % p.per)];
+    return p.planes[(size_t)f * p.J + p.base + i % p.per];
 }
 
-template <int PMAX, class StarOf>
-__device__ inline void plane_fetch(const PlaneArgs& p, StarOf star_of, float2 (&v)[PMAX]) {
+template <int PMAX>
+__device__ inline void plane_fetch(const PlaneArgs& p, float2 (&v)[PMAX]) {
 #pragma unroll
     for (int u = 0; u < PMAX; ++u) {
         const int i = (int)threadIdx.x + u * (int)blockDim.x;
-        v[u] = i < p.count ? plane_at(p, star_of, i) : make_float2(0.f, 0.f);
+        const float2 w = plane_at(p, min(i, p.count - 1));     // always issued (count >= 1): no branch
+        v[u] = i < p.count ? w : make_float2(0.f, 0.f);
     }
 }
 
-template <int PMAX, class StarOf>
-__device__ inline void plane_put(const PlaneArgs& p, StarOf star_of, const float2 (&v)[PMAX], float2* out) {
+template <int PMAX>
+__device__ inline void plane_put(const PlaneArgs& p, const float2 (&v)[PMAX], float2* out) {
 #pragma unroll
     for (int u = 0; u < PMAX; ++u) {
         const int i = (int)threadIdx.x + u * (int)blockDim.x;
         if (i < p.count) out[i] = v[u];
     }
-    for (int i = (int)threadIdx.x + PMAX * (int)blockDim.x; i < p.count; i += blockDim.x) out[i] = plane_at(p, star_of, i);
+    for (int i = (int)threadIdx.x + PMAX * (int)blockDim.x; i < p.count; i += blockDim.x) out[i] = plane_at(p, i);
 }
 
 // Plane coefficients of `count` = F x J (frame, star) pairs: the chunk moments summed in chunk order,
 // (b, c) = rows 1 and 2 of the inverse normal matrix of the fit of [1, x, y] times the sums; (0, 0)
-// for stars whose plane is not used.
+// for stars whose plane is not used.  Star g's coefficients go to group slot slot[g] (see PlaneArgs).
 struct PlaneKArgs {
     const float* mom;           // [F][J][nchunk][4] partial moments (sum v, sum x v, sum y v, 0)
-    float2* planes;             // [F][J]
+    float2* planes;             // [F][J] in group order
     unsigned mask;              // bit g: star g's plane is used (J <= 32)
     float tt_b[3], tt_c[3];
     int J, nchunk, count;
+    int slot[kMaxJ];            // group slot of star g
 };
 static_assert(kMaxJ <= 32, "the plane mask holds one bit per star");
 hipError_t launch_planes(const PlaneKArgs& a, hipStream_t s);

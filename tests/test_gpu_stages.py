@@ -1,7 +1,7 @@
 """Per-stage parity (white box): the intermediates a batched call leaves in the caller's workspace.
 
 After safr_reconstruct_batched the workspace holds, at offset 0, the row spectra
-R[f][star][k][row] (complex64, slots k = 0..M/2 of which k < M/2 are written: B
+R[f][slot][k][row] (complex64, group order, slots k = 0..M/2 of which k < M/2 are written: B
 ignores the Nyquist column; the n pupil rows) of the transformed stars, and after them the layer spectra after the inverse column transforms,
 C[f][l][p / 8][k][p % 8] (complex64, row tiles of 8, columns k < M/2; the 1/M^2
 of IDFT2 is included).  Each is compared with what the oracle's steps give:
@@ -82,11 +82,12 @@ def test_row_and_column_pass_intermediates(case):
     r_end = (r_bytes + 255) // 256 * 256
     C = raw[r_end:r_end + F * L * Kh * M * 8].view(np.complex64).reshape(F, L, M // 8, Kh, 8)
     for f in range(F):
-        for g in grp.stars:
+        # R is stored in group order: the transformed group's stars first, slot i = its i-th star
+        for slot, g in enumerate(grp.stars):
             ext = np.zeros((n, M))
             ext[:, p0:p0 + n] = np.where(pupil, wf[f, g].astype(np.float64), 0.0)
             want = np.fft.fft(ext, axis=1)[:, :Kh].T          # [k][row]
-            e = rel(R[f, g][: M // 2], want[: M // 2])
+            e = rel(R[f, slot][: M // 2], want[: M // 2])
             assert e <= 1e-5, (case, f, g, e)
         psi = np.stack([O.prepare(wf[f, g].astype(np.float64), pupil, grp.tt_mode) for g in grp.stars])
         b = O.apply_B(grp.B, O.dft2(O.zero_extend(psi, M)))    # [l][j][k]
@@ -102,13 +103,15 @@ def test_row_and_column_pass_intermediates(case):
     a256 = lambda b: (b + 255) // 256 * 256
     p_off = a256(r_bytes) + a256(F * L * Kh * M * 8) + a256(F * J * ((n + 1) // 2) * 16)
     planes = raw[p_off:p_off + F * J * 8].view(np.float32).reshape(F, J, 2)
+    # stored in group order: the laser stars first, then the natural stars, each in star order
+    slot = {g: i for i, g in enumerate([g for grp in ref.groups for g in grp.stars])}
     x = np.arange(n) - (n - 1) / 2.0
     X, Y = np.meshgrid(x, x, indexing="ij")
     for f in range(F):
         for g in range(J):
             psi = np.where(pupil, wf[f, g].astype(np.float64), 0.0)
             want_p = np.where(pupil, O.tt_plane(psi, pupil), 0.0)
-            b, c = planes[f, g].astype(np.float64)
+            b, c = planes[f, slot[g]].astype(np.float64)
             got_p = np.where(pupil, b * X + c * Y, 0.0)
             err = np.max(np.abs(got_p - want_p))
             assert err <= 1e-5 * np.max(np.abs(psi)), (case, f, g, err, np.max(np.abs(psi)))
