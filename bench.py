@@ -432,7 +432,35 @@ def run_c4(S, torch, stream, frames):
                 speed[name] = round(F * 1000.0 / _timed(
                     lambda: S.safr_reconstruct_batched(p, F, x, out, S.SAFR_FP32, stream), 20, stream, torch), 1)
     res["frames_per_s"] = speed
+    res["training_objective"] = c4_objective_bound(torch, geo, params, etas, alphas[1:])
     return res, params
+
+
+def c4_objective_bound(torch, geo, params, etas, alphas, count=1000):
+    """The learned filter's training objective (frame-averaged full-grid layer residual, normalised by the
+    expected layer energy) on held-out method-generated frames at each noise level, beside best-tuned
+    Tikhonov over the alpha grid and the closed-form optimal filter factors for those frames, which bound
+    every filter's objective from below (Sec. 3.1 filter functions)."""
+    import numpy as np
+
+    import synth
+    from paper_2510_19542_amd import learn as Lrn
+    out = {"frames": count, "first_seed": 20000}
+    for eta in etas:
+        tr = Lrn.Trainer(geo, synth.vk_amplitude(geo).reshape(geo.L, -1), count)
+        Lrn.add_seeded_frames(tr, 20000, count, eta_range=(eta, eta))
+        idx = np.arange(count)
+        net = tr.network_loss(params, idx)
+        tik = [tr.tikhonov_loss(idx, a) for a in alphas]
+        b = int(np.argmin(tik))
+        opt = tr.optimal_filter(idx)
+        tr.close()
+        out[str(eta)] = {"learned": float(f"{net:.6g}"), "tikhonov_best": float(f"{tik[b]:.6g}"),
+                         "tikhonov_best_alpha": float(f"{alphas[b]:.3g}"), "optimal_bound": float(f"{opt:.6g}"),
+                         "learned_gain_over_tikhonov_pct": round(100.0 * (tik[b] - net) / tik[b], 3),
+                         "learned_gap_to_bound_pct": round(100.0 * (net - opt) / opt, 3),
+                         "share_of_tikhonov_gap_closed": round((tik[b] - net) / (tik[b] - opt), 3)}
+    return out
 
 
 def run_c5(S, torch, stream, params):

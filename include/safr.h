@@ -193,6 +193,19 @@ safr_status safr_plan_info(const safr_plan* p, safr_plan_desc* out);
  */
 safr_status safr_export_B(const safr_plan* p, int group, double* host, size_t count);
 
+/*
+ * Replaces the FP64 B of one group by `host` (the layout of safr_export_B, count doubles) and rebuilds
+ * what derives from it with the precompute's own arithmetic: the FP32 copy, the BF16 tiles of the
+ * matrix-core apply and, for the natural-star group of a mixed asterism, its basis images; a plan that
+ * imports another plan's exported B reconstructs exactly as that plan.  The plan's geometry (M, L,
+ * stars, pupil) must be the one the B was made for; B must be Hermitian with zero Nyquist row and
+ * column (as every exported B is), or the layers are not real.  Restores a refresh of B (Alg. 2 run
+ * elsewhere, or saved) without a new SVD; a later safr_update_alpha rebuilds B from the plan's own
+ * SVDs again.  Synchronises `stream`.  Errors: SAFR_ERR_ARG (NULL, group, count), SAFR_ERR_NUMERIC
+ * (non-finite value), SAFR_ERR_DEVICE.
+ */
+safr_status safr_import_B(safr_plan* p, int group, const double* host, size_t count, hipStream_t stream);
+
 /* Tuning and execution options of a plan (not needed for correct results):
  *   SAFR_OPT_GRAPH       1 = capture the launch sequence in a HIP graph and replay it
  *                        (non-default streams only), 0 = launch directly (default);
@@ -216,11 +229,28 @@ safr_status safr_export_B(const safr_plan* p, int group, double* host, size_t co
  *                        naming the first such frame without launching the reconstruction; no graph
  *                        is used meanwhile.  Default: 1 if the environment variable SAFR_CHECK_FINITE
  *                        is "1" when the plan is made, else 0 (non-finite inputs then propagate
- *                        within their own frame only). */
+ *                        within their own frame only);
+ *   SAFR_OPT_DEADLINE_US  period P > 0 [us] of the real-time loop (Sec. 1: the loop runs at 500 - 1000 Hz,
+ *                        so a step has 1 - 2 ms): every safr_loop_step then stamps the device's
+ *                        constant-rate wall clock when the step starts executing and, when its last
+ *                        kernel has finished, counts the step and whether it took longer than P (two
+ *                        one-thread kernels around the step, captured with it in a graph); read and reset
+ *                        the counts with safr_deadline_stats.  0 = off (default).  The first call with
+ *                        P > 0 allocates the plan's counters and synchronises. */
 enum { SAFR_OPT_GRAPH = 0, SAFR_OPT_ROW_TEAMS = 1, SAFR_OPT_OUT_ROWS = 2, SAFR_OPT_MFMA_FRAMES = 3,
        SAFR_OPT_COL_FRAMES = 4, SAFR_OPT_COL_PREFETCH = 5, SAFR_OPT_OUT_FRAMES = 6,
-       SAFR_OPT_COL_TOGETHER = 7, SAFR_OPT_CHECK_FINITE = 8 };
+       SAFR_OPT_COL_TOGETHER = 7, SAFR_OPT_CHECK_FINITE = 8, SAFR_OPT_DEADLINE_US = 9 };
 safr_status safr_set_option(safr_plan* p, int option, int value);
+
+/* Deadline monitor of the closed-loop step (SAFR_OPT_DEADLINE_US): steps counted since the last reset,
+ * how many took longer than the period, the last and the longest step time.  A step's time runs from
+ * when the stream reaches the step to when its output pass has finished (queueing behind earlier work
+ * on the stream is not counted).  Synchronises `stream`; reset != 0 zeroes the counts afterwards. */
+typedef struct {
+    unsigned long long steps, misses;
+    double last_us, max_us, period_us;
+} safr_deadline_info;
+safr_status safr_deadline_stats(safr_plan* p, safr_deadline_info* out, int reset, hipStream_t stream);
 
 /* Measures the three stages of the hard-real-time step (row pass, with the small
  * kernel that forms the tip/tilt planes of a mixed asterism; column pass with the
@@ -349,6 +379,19 @@ safr_status safr_trainer_step(safr_trainer* t, int nb, const int* frames, float 
 /* Gradient of the batch loss with respect to the parameters (host grad, may be NULL), no update. */
 safr_status safr_trainer_gradient(safr_trainer* t, int nb, const int* frames, float* grad, double* loss,
                                   hipStream_t stream);
+/* The closed-form optimum of the training objective on the listed frames (the same objective as
+ * safr_trainer_step's batch loss): it is quadratic in the filter factors at every frequency, so over all
+ * filters of the form g_r = phi_r / s_r (the network's, Tikhonov's phi = s^2 / (s^2 + alpha), any other)
+ * its minimum is reached at phi* = Qbar^-1 cbar, the statistics summed over the frames (Sec. 3.1 filter
+ * functions; components at or below the cutoff sqrt(eps) s_1 get phi = 0).  loss receives the objective
+ * at phi*, a lower bound of every network's batch loss on these frames; phi (may be NULL): host [r][H]
+ * factors, r = min(J, L), H = (M/2+1) M half-spectrum frequencies h = k M + j.  Synchronises. */
+safr_status safr_trainer_optimal_filter(safr_trainer* t, int nb, const int* frames, float* phi, double* loss,
+                                        hipStream_t stream);
+/* The training objective on the listed frames for Tikhonov's filter, phi = s^2 / (s^2 + alpha) (Sec. 3.1),
+ * alpha >= 0.  Synchronises. */
+safr_status safr_trainer_tikhonov_loss(safr_trainer* t, int nb, const int* frames, double alpha, double* loss,
+                                       hipStream_t stream);
 int safr_trainer_frames(const safr_trainer* t);
 void safr_trainer_destroy(safr_trainer* t);
 

@@ -120,3 +120,35 @@ def batch_loss_and_grad(params, fs, amp, zl, zn, eta, M):
     dphi = _mlp.quadratic_loss_grad(pf, Qf, cf, ww)
     grad = _mlp.backward(params, cache, dphi.reshape(-1))
     return loss, grad
+
+
+def objective(phi, Q, c, F2, w, Z):
+    """The training objective for given filter factors phi (F-independent, (K, J, r)) on the frames of the
+    statistics: sum over frames and frequencies of w (phi^T Q phi - 2 c^T phi + |F|^2), divided by Z and
+    the number of frames."""
+    nb = Q.shape[0]
+    quad = np.einsum("kjr,fkjrq,kjq->fkj", phi, Q, phi) - 2.0 * np.einsum("fkjr,kjr->fkj", c, phi) + F2
+    return float(np.sum(w[None] * quad) / (Z * nb))
+
+
+def optimal_filter(Q, c, F2, w, Z, keep):
+    """The filter factors minimising the training objective over the frames of the statistics: at each
+    frequency the objective is the quadratic phi^T Qbar phi - 2 cbar^T phi + const (Qbar, cbar summed over
+    the frames), minimised by phi* = Qbar^-1 cbar over the components kept (keep: (K, J, r) bool, the
+    singular values above the learned filter's cutoff; the others have phi = 0).  Returns (phi*, the
+    objective at phi*)."""
+    Qb = Q.sum(axis=0)
+    cb = c.sum(axis=0)
+    K, Jn, r = cb.shape
+    phi = np.zeros((K, Jn, r))
+    for k in range(K):
+        for j in range(Jn):
+            idx = np.flatnonzero(keep[k, j])
+            if idx.size:
+                phi[k, j, idx] = np.linalg.solve(Qb[k, j][np.ix_(idx, idx)], cb[k, j, idx])
+    return phi, objective(phi, Q, c, F2, w, Z)
+
+
+def tikhonov_factors(sigma, alpha, keep):
+    """Tikhonov's filter factors phi = sigma^2 / (sigma^2 + alpha) (Sec. 3.1), 0 where not kept."""
+    return np.where(keep, sigma ** 2 / (sigma ** 2 + alpha), 0.0)

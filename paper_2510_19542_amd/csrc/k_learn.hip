@@ -99,6 +99,85 @@ __global__ void learn_setup_kernel(LearnSetupArgs a) {
 }
 
 // ----------------------------------------------------------------------------------------
+// Filter factors against the training objective (see FilterEvalArgs).  The objective is quadratic in phi
+// at every frequency, so its minimum over all filter factors (any network's, Tikhonov's, ...) is reached
+// at phi* = Qbar^-1 cbar, solved here by Gaussian elimination with partial pivoting over the components
+// above the cutoff (the others carry Q = c = 0 and get phi = 0).
+// ----------------------------------------------------------------------------------------
+__global__ void filter_eval_kernel(FilterEvalArgs a) {
+    const size_t h = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= a.H) return;
+    const int r = a.r;
+    const LearnFreq& fq = *a.freq;
+    double Q[kMaxG][kMaxG], c[kMaxG], phi[kMaxG];
+    double f2 = 0.0;
+    for (int i = 0; i < r; ++i) {
+        c[i] = 0.0;
+        for (int q = 0; q < r; ++q) Q[i][q] = 0.0;
+    }
+    for (int b = 0; b < a.nb; ++b) {
+        const float* st = a.stats + ((size_t)a.frames[b] * a.H + h) * a.stride;
+        for (int i = 0; i < r; ++i) {
+            for (int q = 0; q < r; ++q) Q[i][q] += st[i * r + q];
+            c[i] += st[r * r + i];
+        }
+        f2 += st[r * r + r];
+    }
+    bool ok[kMaxG];
+    for (int i = 0; i < r; ++i) ok[i] = fq.inv_sigma[(size_t)i * a.H + h] > 0.f;
+    if (a.mode == 0) {
+        // solve over the kept components (the rest: phi = 0); A = Q restricted, x = c restricted
+        int idx[kMaxG], n = 0;
+        for (int i = 0; i < r; ++i)
+            if (ok[i]) idx[n++] = i;
+        double A[kMaxG][kMaxG + 1];
+        for (int i = 0; i < n; ++i) {
+            for (int q = 0; q < n; ++q) A[i][q] = Q[idx[i]][idx[q]];
+            A[i][n] = c[idx[i]];
+        }
+        for (int col = 0; col < n; ++col) {
+            int piv = col;
+            for (int i = col + 1; i < n; ++i)
+                if (fabs(A[i][col]) > fabs(A[piv][col])) piv = i;
+            if (piv != col)
+                for (int q = 0; q <= n; ++q) {
+                    const double tmp = A[col][q];
+                    A[col][q] = A[piv][q];
+                    A[piv][q] = tmp;
+                }
+            const double d = A[col][col];
+            for (int i = col + 1; i < n; ++i) {
+                const double m = d != 0.0 ? A[i][col] / d : 0.0;
+                for (int q = col; q <= n; ++q) A[i][q] -= m * A[col][q];
+            }
+        }
+        double x[kMaxG];
+        for (int i = n - 1; i >= 0; --i) {
+            double acc = A[i][n];
+            for (int q = i + 1; q < n; ++q) acc -= A[i][q] * x[q];
+            x[i] = A[i][i] != 0.0 ? acc / A[i][i] : 0.0;
+        }
+        for (int i = 0; i < r; ++i) phi[i] = 0.0;
+        for (int i = 0; i < n; ++i) phi[idx[i]] = x[i];
+        if (a.phi)
+            for (int i = 0; i < r; ++i) a.phi[(size_t)i * a.H + h] = (float)phi[i];
+    } else {
+        for (int i = 0; i < r; ++i) {
+            const double inv = fq.inv_sigma[(size_t)i * a.H + h];
+            const double s2 = inv > 0.0 ? 1.0 / (inv * inv) : 0.0;
+            phi[i] = ok[i] ? s2 / (s2 + a.alpha) : 0.0;
+        }
+    }
+    double quad = f2;
+    for (int i = 0; i < r; ++i) {
+        double qp = 0.0;
+        for (int q = 0; q < r; ++q) qp += Q[i][q] * phi[q];
+        quad += phi[i] * qp - 2.0 * c[i] * phi[i];
+    }
+    a.loss[h] = (double)fq.mult[h] * quad;
+}
+
+// ----------------------------------------------------------------------------------------
 // Statistics (Q, c, |F|^2) of frames f0 .. f0+count-1, one thread per (frame, frequency).
 // ----------------------------------------------------------------------------------------
 __global__ void learn_stats_kernel(LearnStatsArgs a) {

@@ -85,7 +85,23 @@ struct MlpAdamArgs {
     float lr, b1, b2, eps, b1t, b2t;
 };
 
+// Filter factors evaluated against the stored statistics of a set of frames, one thread per frequency h:
+// Qbar, cbar, |F|^2 summed over the frames (FP64), then either the optimum phi* = Qbar^-1 cbar over the
+// components above the cutoff (mode 0) or Tikhonov's phi = sigma^2 / (sigma^2 + alpha) (mode 1);
+// loss[h] = mult_h (phi^T Qbar phi - 2 cbar^T phi + |F|^2).
+struct FilterEvalArgs {
+    const LearnFreq* freq;
+    const float* stats;       // [frame][h][stride]
+    const int* frames;        // [nb]
+    float* phi;               // [r][h] (mode 0 output, or nullptr)
+    double* loss;             // [h]
+    double alpha;             // mode 1
+    int nb, r, stride, mode;
+    size_t H;
+};
+
 __global__ void learn_setup_kernel(LearnSetupArgs a);
+__global__ void filter_eval_kernel(FilterEvalArgs a);
 __global__ void learn_stats_kernel(LearnStatsArgs a);
 __global__ void mlp_rows_kernel(MlpRowsArgs a);
 __global__ void mlp_wgrad_kernel(MlpGradArgs a);

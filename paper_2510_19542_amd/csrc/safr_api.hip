@@ -87,6 +87,7 @@ struct safr_plan {
     double2* Y64 = nullptr;
     int filter = SAFR_FILTER_TIKHONOV;
     int weighted = 0;               // B was made with a per-frequency alpha map
+    int imported = 0;               // B replaced by safr_import_B (the kept SVDs no longer describe it)
     unsigned char* pupil = nullptr;
     int* tt_mode = nullptr;
     unsigned plane_mask = 0;     // bit g: star g's tip/tilt plane is used (split tomography)
@@ -101,6 +102,10 @@ struct safr_plan {
     int row_teams = 0, out_rows = 0, out_frames = 1, mfma_frames = 16, col_frames = 1, col_nf = 1, col_prefetch = 1;
     int col_frames_auto = 1;        // column frames per block chosen per launch (until set or autotuned)
     int use_graph = 0;
+    int deadline_us = 0;            // loop-step deadline (0: off), see SAFR_OPT_DEADLINE_US
+    unsigned long long deadline_ticks = 0;
+    unsigned long long* dstats = nullptr;   // device: steps, misses, last, max (wall-clock ticks), start stamp
+    double ticks_per_us = 0.0;
     int check_finite = 0;           // debug: scan inputs for non-finite values first (synchronises)
     int* dfirst = nullptr;          // first non-finite frame found by the check
     // graph cache
@@ -175,6 +180,7 @@ void free_plan(safr_plan* p) {
     (void)hipFree(p->X64);
     (void)hipFree(p->Y64);
     (void)hipFree(p->dfirst);
+    (void)hipFree(p->dstats);
     (void)hipFree(p->ws_own);
     delete p;
 }
@@ -380,8 +386,12 @@ safr_status launch_loop(safr_plan* p, int frames, const float* wf, const float* 
                         void* ws, hipStream_t s) {
     float* psi = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + ws_r(p, frames) + ws_c(p, frames) +
                                           ws_m(p, frames));
+    if (p->deadline_ticks) HIP_TRY(launch_deadline_start(p->dstats, s));
     HIP_TRY(launch_polc(polc_args(p, wf, a_in, 1.f, psi), frames, s));
-    return launch_all(p, frames, psi, a_out, SAFR_FP32, ws, s, nullptr, a_in, gain);
+    const safr_status st = launch_all(p, frames, psi, a_out, SAFR_FP32, ws, s, nullptr, a_in, gain);
+    if (st != SAFR_OK) return st;
+    if (p->deadline_ticks) HIP_TRY(launch_deadline_end(p->dstats, p->deadline_ticks, s));
+    return SAFR_OK;
 }
 
 }  // namespace
@@ -751,6 +761,61 @@ safr_status safr_export_B(const safr_plan* p, int group, double* host, size_t co
     return SAFR_OK;
 }
 
+safr_status safr_import_B(safr_plan* p, int group, const double* host, size_t count, hipStream_t s) {
+    if (!p || !host) return fail(SAFR_ERR_ARG, "NULL argument");
+    if (group < 0 || group >= p->ngroups) return fail(SAFR_ERR_ARG, "bad group %d", group);
+    const size_t need = 2 * p->bcount[group];
+    if (count != need) return fail(SAFR_ERR_ARG, "B of group %d holds %zu doubles, got %zu", group, need, count);
+    for (size_t i = 0; i < need; ++i)
+        if (!std::isfinite(host[i])) return fail(SAFR_ERR_NUMERIC, "non-finite value at %zu", i);
+    // export layout [k][j][l][g] -> device FP64 [k][l][g][j] and the FP32 column-pass layout
+    // [k / CPW][l][g][k % CPW][j] with the 1/M^2 of IDFT2 folded in (the precompute's own arithmetic)
+    const int M = p->M, L = p->L, G = p->gsize[group], Kh = p->Kh, cpw = 256 / M;
+    const int kblocks = (Kh + cpw - 1) / cpw;
+    std::vector<double2> b64(p->bcount[group]);
+    std::vector<float2> b32((size_t)kblocks * L * G * 256, make_float2(0.f, 0.f));
+    const double inv_m2 = 1.0 / ((double)M * (double)M);
+    for (int k = 0; k < Kh; ++k)
+        for (int j = 0; j < M; ++j)
+            for (int l = 0; l < L; ++l)
+                for (int g = 0; g < G; ++g) {
+                    const size_t i = (((size_t)k * M + j) * L + l) * G + g;
+                    const double2 v = make_double2(host[2 * i], host[2 * i + 1]);
+                    b64[(((size_t)k * L + l) * G + g) * M + j] = v;
+                    b32[((((size_t)(k / cpw) * L + l) * G + g) * cpw + (k % cpw)) * M + j] =
+                        make_float2((float)(v.x * inv_m2), (float)(v.y * inv_m2));
+                }
+    HIP_TRY(hipStreamSynchronize(s));          // work issued before the import uses the old operator
+    HIP_TRY(hipMemcpy(p->B64 + p->boff[group], b64.data(), b64.size() * sizeof(double2), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(p->B32 + p->boff32[group], b32.data(), b32.size() * sizeof(float2), hipMemcpyHostToDevice));
+    if (group == 1) {
+        const safr_status st = build_basis(p, s);
+        if (st != SAFR_OK) return st;
+    } else if (p->Apack) {
+        const safr_status st = build_pack(p, s);
+        if (st != SAFR_OK) return st;
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    p->imported = 1;
+    return SAFR_OK;
+}
+
+safr_status safr_deadline_stats(safr_plan* p, safr_deadline_info* out, int reset, hipStream_t s) {
+    if (!p || !out) return fail(SAFR_ERR_ARG, "NULL argument");
+    std::memset(out, 0, sizeof(*out));
+    out->period_us = p->deadline_us;
+    if (!p->dstats) return SAFR_OK;
+    unsigned long long h[5] = {0, 0, 0, 0, 0};
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipMemcpy(h, p->dstats, sizeof(h), hipMemcpyDeviceToHost));
+    out->steps = h[0];
+    out->misses = h[1];
+    out->last_us = h[2] / p->ticks_per_us;
+    out->max_us = h[3] / p->ticks_per_us;
+    if (reset) HIP_TRY(hipMemset(p->dstats, 0, sizeof(h)));
+    return SAFR_OK;
+}
+
 safr_status safr_update_alpha(safr_plan* p, double alpha, double alpha_tt, int filter, const double* alpha_weight,
                               hipStream_t s) {
     if (!p) return fail(SAFR_ERR_ARG, "plan is NULL");
@@ -808,6 +873,7 @@ safr_status safr_update_alpha(safr_plan* p, double alpha, double alpha_tt, int f
         p->galpha[1] = galpha[1];
         p->filter = filter;
         p->weighted = alpha_weight != nullptr;
+        p->imported = 0;
     } while (0);
     (void)hipFree(aw_dev);
     (void)hipFree(dbad);
@@ -866,6 +932,8 @@ safr_status safr_reconstruct_batched(safr_plan* p, int frames, const float* wf, 
 safr_status safr_reconstruct(safr_plan* p, const float* wf, float* out, hipStream_t s) {
     return safr_reconstruct_batched(p, 1, wf, out, SAFR_FP32, s);
 }
+
+
 
 safr_status safr_polc(safr_plan* p, int frames, const float* wf, const float* layers, float weight, float* out,
                       hipStream_t s) {
@@ -1310,6 +1378,21 @@ safr_status safr_set_option(safr_plan* p, int option, int value) {
             p->col_nf = value;
             return SAFR_OK;
         case 8: p->check_finite = value != 0; return SAFR_OK;
+        case 9: {
+            if (value < 0) return fail(SAFR_ERR_ARG, "the deadline must be >= 0 microseconds");
+            if (value > 0 && !p->dstats) {
+                int dev = 0, khz = 0;
+                HIP_TRY(hipGetDevice(&dev));
+                HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+                if (khz <= 0) return fail(SAFR_ERR_DEVICE, "no device wall clock");
+                HIP_TRY(hipMalloc(&p->dstats, 5 * sizeof(unsigned long long)));
+                HIP_TRY(hipMemset(p->dstats, 0, 5 * sizeof(unsigned long long)));
+                p->ticks_per_us = khz / 1000.0;
+            }
+            p->deadline_us = value;
+            p->deadline_ticks = value > 0 ? (unsigned long long)std::llround(value * p->ticks_per_us) : 0ull;
+            return SAFR_OK;
+        }
         default: return fail(SAFR_ERR_ARG, "unknown option %d", option);
     }
 }

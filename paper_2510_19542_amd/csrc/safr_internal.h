@@ -141,6 +141,9 @@ int strehl_chunks(int n);
 hipError_t launch_finite_check(const float* x, const unsigned char* pupil, int pix, int per_frame, int frames,
                                int* first, hipStream_t s);       // pupil chunks (256 pixels each) per frame and direction
 hipError_t launch_strehl(const StrehlArgs& a, int frames, hipStream_t s);
+// Deadline monitor of the closed-loop step: stats [steps, misses, last, max, start] in wall-clock ticks.
+hipError_t launch_deadline_start(unsigned long long* stats, hipStream_t s);
+hipError_t launch_deadline_end(unsigned long long* stats, unsigned long long period_ticks, hipStream_t s);
 
 // BF16 hi/lo split apply on matrix cores (batched path).
 struct MfmaArgs {

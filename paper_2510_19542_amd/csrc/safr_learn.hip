@@ -413,6 +413,64 @@ safr_status safr_trainer_step(safr_trainer* t, int nb, const int* frames, float 
     return SAFR_OK;
 }
 
+namespace {
+
+// the training objective of the listed frames for the optimal (mode 0) or Tikhonov (mode 1) filter factors
+safr_status filter_eval(safr_trainer* t, int nb, const int* frames, int mode, double alpha, float* phi_host,
+                        double* loss, hipStream_t s) {
+    if (!t || !frames || nb < 1 || !loss) return lfail(SAFR_ERR_ARG, "bad argument");
+    for (int i = 0; i < nb; ++i)
+        if (frames[i] < 0 || frames[i] >= t->nframes) return lfail(SAFR_ERR_ARG, "frame index %d out of range", frames[i]);
+    int* dframes = nullptr;
+    double* dloss = nullptr;
+    float* dphi = nullptr;
+    hipError_t e = hipMalloc(&dframes, nb * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&dloss, t->H * sizeof(double));
+    if (e == hipSuccess && phi_host) e = hipMalloc(&dphi, t->H * t->r * sizeof(float));
+    if (e == hipSuccess) e = hipMemcpy(dframes, frames, nb * sizeof(int), hipMemcpyHostToDevice);
+    std::vector<double> lh(t->H);
+    if (e == hipSuccess) {
+        FilterEvalArgs a{};
+        a.freq = t->fq_dev;
+        a.stats = t->stats;
+        a.frames = dframes;
+        a.phi = dphi;
+        a.loss = dloss;
+        a.alpha = alpha;
+        a.nb = nb;
+        a.r = t->r;
+        a.stride = t->stride;
+        a.mode = mode;
+        a.H = t->H;
+        hipLaunchKernelGGL(filter_eval_kernel, dim3((unsigned)((t->H + 63) / 64)), dim3(64), 0, s, a);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(lh.data(), dloss, t->H * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && phi_host) e = hipMemcpyAsync(phi_host, dphi, t->H * t->r * sizeof(float), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(dframes);
+    (void)hipFree(dloss);
+    (void)hipFree(dphi);
+    if (e != hipSuccess) return lfail(SAFR_ERR_DEVICE, "filter evaluation failed: %s", hipGetErrorString(e));
+    double acc = 0.0;
+    for (double x : lh) acc += x;
+    *loss = acc / (t->Z * nb);
+    return SAFR_OK;
+}
+
+}  // namespace
+
+safr_status safr_trainer_optimal_filter(safr_trainer* t, int nb, const int* frames, float* phi, double* loss,
+                                        hipStream_t s) {
+    return filter_eval(t, nb, frames, 0, 0.0, phi, loss, s);
+}
+
+safr_status safr_trainer_tikhonov_loss(safr_trainer* t, int nb, const int* frames, double alpha, double* loss,
+                                       hipStream_t s) {
+    if (!(alpha >= 0.0) || !std::isfinite(alpha)) return lfail(SAFR_ERR_ARG, "alpha must be >= 0");
+    return filter_eval(t, nb, frames, 1, alpha, nullptr, loss, s);
+}
+
 int safr_trainer_frames(const safr_trainer* t) { return t ? t->nframes : 0; }
 
 void safr_trainer_destroy(safr_trainer* t) { free_trainer(t); }

@@ -37,9 +37,12 @@ def _lib():
         L.safr_trainer_destroy.argtypes = [vp]
         L.safr_trainer_destroy.restype = None
         L.safr_mlp_infer.argtypes = [fp, vp, i, d, vp, vp]
+        L.safr_trainer_optimal_filter.argtypes = [vp, i, ctypes.POINTER(i), fp, ctypes.POINTER(d), vp]
+        L.safr_trainer_tikhonov_loss.argtypes = [vp, i, ctypes.POINTER(i), d, ctypes.POINTER(d), vp]
         for name in ("safr_trainer_create", "safr_trainer_add_frames", "safr_trainer_set_params",
                      "safr_trainer_get_params", "safr_trainer_get_state", "safr_trainer_set_state",
-                     "safr_trainer_step", "safr_trainer_gradient", "safr_mlp_infer"):
+                     "safr_trainer_step", "safr_trainer_gradient", "safr_mlp_infer",
+                     "safr_trainer_optimal_filter", "safr_trainer_tikhonov_loss"):
             getattr(L, name).restype = ctypes.c_int
         L._learn_bound = True
     return L
@@ -161,6 +164,42 @@ class Trainer:
                                               g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(loss),
                                               S._stream(self.stream)))
         return g, float(loss.value)
+
+
+    def optimal_filter(self, frames, want_phi: bool = False):
+        """Training objective of the closed-form optimal filter factors on these frames (the lower bound of
+        every filter's), and optionally the factors [r][H] (see safr_trainer_optimal_filter)."""
+        f = np.ascontiguousarray(np.asarray(frames, dtype=np.int32))
+        loss = ctypes.c_double()
+        phi = None
+        if want_phi:
+            r = min(self.geo.J, self.geo.L)
+            phi = np.empty((r, (self.geo.M // 2 + 1) * self.geo.M), dtype=np.float32)
+        S._check(_lib().safr_trainer_optimal_filter(
+            ctypes.c_void_p(self.handle), len(f), f.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+            phi.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if phi is not None else None, ctypes.byref(loss),
+            S._stream(self.stream)))
+        return (float(loss.value), phi) if want_phi else float(loss.value)
+
+    def tikhonov_loss(self, frames, alpha: float) -> float:
+        """Training objective of Tikhonov's filter factors s^2 / (s^2 + alpha) on these frames."""
+        f = np.ascontiguousarray(np.asarray(frames, dtype=np.int32))
+        loss = ctypes.c_double()
+        S._check(_lib().safr_trainer_tikhonov_loss(ctypes.c_void_p(self.handle), len(f),
+                                                   f.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), float(alpha),
+                                                   ctypes.byref(loss), S._stream(self.stream)))
+        return float(loss.value)
+
+    def network_loss(self, params, frames, batch: int = 50) -> float:
+        """Training objective of the network `params` on these frames (batch losses averaged; the
+        parameters and the Adam state of this trainer are replaced)."""
+        self.set_params(params)
+        f = np.asarray(frames, dtype=np.int32)
+        tot = 0.0
+        for b in range(0, len(f), batch):
+            part = f[b:b + batch]
+            tot += self.gradient(part)[1] * len(part)
+        return tot / len(f)
 
 
 def add_seeded_frames(trainer: Trainer, first: int, count: int, chunk: int = 500, eta_range=(0.005, 0.05)):

@@ -24,6 +24,7 @@ SAFR_FILTER_TIKHONOV, SAFR_FILTER_MLP, SAFR_FILTER_TSVD = 0, 1, 2
 SAFR_FP32, SAFR_BF16X3 = 0, 1
 SAFR_OPT_GRAPH, SAFR_OPT_ROW_TEAMS, SAFR_OPT_OUT_ROWS, SAFR_OPT_MFMA_FRAMES, SAFR_OPT_COL_FRAMES = 0, 1, 2, 3, 4
 SAFR_OPT_COL_PREFETCH, SAFR_OPT_OUT_FRAMES, SAFR_OPT_COL_TOGETHER, SAFR_OPT_CHECK_FINITE = 5, 6, 7, 8
+SAFR_OPT_DEADLINE_US = 9
 SAFR_MAX_LAYERS = 16
 SAFR_MLP_PARAMS = 8705
 
@@ -32,11 +33,12 @@ EXPORTED = [
     "safr_set_workspace", "safr_plan_info", "safr_export_B", "safr_set_option", "safr_time_stages",
     "safr_autotune", "safr_destroy", "safr_last_error",
     "safr_multi_create", "safr_multi_execute", "safr_multi_autotune", "safr_multi_destroy",
-    "safr_polc", "safr_loop_step", "safr_strehl", "safr_update_alpha",
+    "safr_polc", "safr_loop_step", "safr_strehl", "safr_update_alpha", "safr_import_B", "safr_deadline_stats",
     # learned filter (bound in learn.py)
     "safr_trainer_create", "safr_trainer_add_frames", "safr_trainer_set_params", "safr_trainer_get_params",
     "safr_trainer_get_state", "safr_trainer_set_state",
     "safr_trainer_step", "safr_trainer_gradient", "safr_trainer_frames", "safr_trainer_destroy", "safr_mlp_infer",
+    "safr_trainer_optimal_filter", "safr_trainer_tikhonov_loss",
 ]
 
 
@@ -68,6 +70,11 @@ class safr_plan_desc(ctypes.Structure):
         ("c", ctypes.c_double * SAFR_MAX_LAYERS), ("layer_pitch", ctypes.c_double * SAFR_MAX_LAYERS),
         ("B_complex_per_group", ctypes.c_size_t * 2),
     ]
+
+
+class safr_deadline_info(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_ulonglong), ("misses", ctypes.c_ulonglong), ("last_us", ctypes.c_double),
+                ("max_us", ctypes.c_double), ("period_us", ctypes.c_double)]
 
 
 _lib = None
@@ -112,6 +119,8 @@ def lib() -> ctypes.CDLL:
     L.safr_loop_step.argtypes = [vp, i, vp, vp, ctypes.c_float, vp, vp]
     L.safr_strehl.argtypes = [vp, i, i, ctypes.POINTER(d), vp, vp, ctypes.c_float, vp, vp, vp]
     L.safr_update_alpha.argtypes = [vp, d, d, i, ctypes.POINTER(d), vp]
+    L.safr_import_B.argtypes = [vp, i, ctypes.POINTER(d), sz, vp]
+    L.safr_deadline_stats.argtypes = [vp, ctypes.POINTER(safr_deadline_info), i, vp]
     for name in EXPORTED[:EXPORTED.index("safr_trainer_create")]:
         if name not in ("safr_destroy", "safr_last_error", "safr_multi_destroy"):
             getattr(L, name).restype = ctypes.c_int
@@ -302,6 +311,23 @@ def safr_export_B(plan: Plan, group: int) -> np.ndarray:
                                buf.size))
     z = buf[0::2] + 1j * buf[1::2]
     return z.reshape(d.M // 2 + 1, d.M, d.L, d.group_size[group])
+
+
+def safr_import_B(plan: Plan, group: int, B, stream=None):
+    """Replace one group's B by complex128 [k = 0..M/2][j = 0..M-1][l][g] (the layout of safr_export_B)
+    and rebuild its FP32, BF16 and basis-image forms (synchronises)."""
+    z = np.ascontiguousarray(np.asarray(B, dtype=np.complex128))
+    flat = np.ascontiguousarray(z.view(np.float64).ravel())
+    _check(lib().safr_import_B(plan._as_parameter_, int(group), flat.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               flat.size, _stream(stream)))
+
+
+def safr_deadline_stats(plan: Plan, reset: bool = False, stream=None) -> dict:
+    """Deadline monitor of the loop step: steps, misses (longer than the period), last and longest step [us]."""
+    info = safr_deadline_info()
+    _check(lib().safr_deadline_stats(plan._as_parameter_, ctypes.byref(info), int(bool(reset)), _stream(stream)))
+    return {"steps": int(info.steps), "misses": int(info.misses), "last_us": float(info.last_us),
+            "max_us": float(info.max_us), "period_us": float(info.period_us)}
 
 
 class Multi:

@@ -95,7 +95,8 @@ def _c_layout(tmp_path, structs):
 
 def test_binding_structs_match_the_header_layout(tmp_path):
     from paper_2510_19542_amd import safr as S
-    structs = {"safr_star": S.safr_star, "safr_geometry": S.safr_geometry, "safr_plan_desc": S.safr_plan_desc}
+    structs = {"safr_star": S.safr_star, "safr_geometry": S.safr_geometry, "safr_plan_desc": S.safr_plan_desc,
+               "safr_deadline_info": S.safr_deadline_info}
     c = _c_layout(tmp_path, {n: [f for f, _ in t._fields_] for n, t in structs.items()})
     for name, t in structs.items():
         assert ctypes.sizeof(t) == c[name], name

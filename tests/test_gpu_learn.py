@@ -26,7 +26,7 @@ def _fs(geo):
 
 
 def test_training_gradient_matches_oracle():
-    """GPU FP32 loss and gradient of a minibatch vs the oracle's FP64 analytic ones (rel <= 1e-4 / 2e-3)."""
+    """GPU FP32 loss and gradient of a minibatch vs the oracle's FP64 analytic ones (rel <= 1e-4 each)."""
     torch, S, Lrn = _mods()
     geo = synth.preset("C1")
     amp = synth.vk_amplitude(geo)
@@ -43,7 +43,7 @@ def test_training_gradient_matches_oracle():
     assert abs(loss - lref) <= 1e-4 * abs(lref), (loss, lref)
     err = np.linalg.norm(g - gref) / np.linalg.norm(gref)
     print(f"gradient rel error {err:.2e}, loss {loss:.6e} vs {lref:.6e}")
-    assert err <= 2e-3
+    assert err <= 1e-4
 
 
 def test_bf16_inference_matches_oracle_emulation():
@@ -80,6 +80,70 @@ def test_learned_B_matches_oracle(name, seed, eta):
     err = np.max(np.abs(got - want)) / np.max(np.abs(want))
     print(f"{name}: learned B max rel error {err:.2e}")
     assert err <= 1e-2
+
+
+def test_optimal_filter_and_tikhonov_objective_match_oracle():
+    """The trainer's closed-form optimal filter factors, their objective and Tikhonov's objective on a set of
+    frames vs the oracle's FP64 statistics of the same draws (the GPU statistics are FP32)."""
+    torch, S, Lrn = _mods()
+    geo = synth.preset("C1")
+    amp = synth.vk_amplitude(geo)
+    tr = Lrn.Trainer(geo, amp.reshape(geo.L, -1), 8)
+    Lrn.add_seeded_frames(tr, 300, 8)
+    frames = [0, 2, 3, 7]
+    loss, phi = tr.optimal_filter(frames, want_phi=True)
+    tik = tr.tikhonov_loss(frames, 1e-3)
+    fs = _fs(geo)
+    zl, zn, eta = synth.learn_draws(geo, 300, 8)
+    idx = np.array(frames)
+    Q, c, F2 = LR.statistics(fs, amp, zl[idx], zn[idx], eta[idx].astype(np.float32).astype(np.float64), geo.M)
+    w = LR.multiplicity(geo.M)
+    Z = float(np.sum(w * np.sum(amp ** 2, axis=0)))
+    keep = fs["sigma"] > O.learned_cutoff(fs["sigma"])
+    phi_ref, loss_ref = LR.optimal_filter(Q, c, F2, w, Z, keep)
+    tik_ref = LR.objective(LR.tikhonov_factors(fs["sigma"], 1e-3, keep), Q, c, F2, w, Z)
+    got = np.transpose(phi.reshape(phi.shape[0], geo.M // 2 + 1, geo.M), (1, 2, 0))    # [r][k*M+j] -> (k, j, r)
+    weight = w[..., None] > 0                                                           # Nyquist: no weight
+    e_phi = np.linalg.norm(np.where(weight, got - phi_ref, 0.0)) / np.linalg.norm(np.where(weight, phi_ref, 0.0))
+    print(f"optimal objective {loss:.6e} vs {loss_ref:.6e}; phi rel-L2 {e_phi:.2e}; Tikhonov {tik:.6e} vs {tik_ref:.6e}")
+    assert abs(loss - loss_ref) <= 1e-4 * loss_ref
+    assert abs(tik - tik_ref) <= 1e-4 * tik_ref
+    assert e_phi <= 1e-3
+    assert loss <= tik
+
+
+@pytest.fixture(scope="module")
+def trained_c4():
+    """The learned filter of the benchmark's workload: 8 m geometry with data on the whole grid, trained on
+    20,000 method-generated frames."""
+    torch, S, Lrn = _mods()
+    base = synth.preset("C1")
+    geo = base.replace(n=base.M)
+    params, _ = Lrn.train(geo, frames=20000, epochs=3, batch=16, lr=2e-3, seed=1)
+    assert np.all(np.isfinite(params))
+    return geo, params
+
+
+@pytest.mark.parametrize("eta", [0.005, 0.01, 0.02, 0.05])
+def test_learned_filter_between_optimum_and_best_tikhonov(trained_c4, eta):
+    """On 300 held-out method-generated frames (seeds 20000...) the trained network's training objective
+    lies at or above the closed-form optimum of the filter factors (a bound no filter can pass) and below
+    the best Tikhonov filter over a grid of 25 alphas (1e-6 ... 1): the network gains over the method it
+    replaces, tuned as well as it can be."""
+    torch, S, Lrn = _mods()
+    geo, params = trained_c4
+    tr = Lrn.Trainer(geo, synth.vk_amplitude(geo).reshape(geo.L, -1), 300)
+    Lrn.add_seeded_frames(tr, 20000, 300, eta_range=(eta, eta))
+    idx = np.arange(300)
+    net = tr.network_loss(params, idx)
+    tik = min(tr.tikhonov_loss(idx, a) for a in np.logspace(-6, 0, 25))
+    opt = tr.optimal_filter(idx)
+    tr.close()
+    print(f"eta {eta}: optimum {opt:.6e} <= learned {net:.6e} < best Tikhonov {tik:.6e} "
+          f"(closes {(tik - net) / (tik - opt):.2f} of the gap)")
+    # the network is evaluated in FP32 with its loss summed in FP32: allow rounding below the FP64 optimum
+    assert net >= opt * (1.0 - 1e-5)
+    assert net < tik
 
 
 def test_learned_filter_beats_tikhonov_on_heldout_frames():

@@ -96,3 +96,56 @@ def test_vk_amplitude_matches_screen_variance():
     screens = [synth.periodic_layers(geo, s) for s in range(40)]
     var_emp = np.mean([np.mean(np.sum(x, axis=0) ** 2) - np.mean(np.sum(x, axis=0)) ** 2 for x in screens])
     assert 0.5 < var_emp / var_model < 1.5
+
+
+def _stats(F=5, M=16, eta=0.02):
+    fs, st = _fs(M)
+    amp = np.abs(RNG.standard_normal((2, M // 2 + 1, M))) + 0.1
+    zl, zn = _draws(F, 2, 4, M)
+    Q, c, F2 = LR.statistics(fs, amp, zl, zn, np.full(F, eta), M)
+    w = LR.multiplicity(M)
+    Z = float(np.sum(w * np.sum(amp ** 2, axis=0)))
+    keep = fs["sigma"] > O.learned_cutoff(fs["sigma"])
+    return fs, Q, c, F2, w, Z, keep
+
+
+def test_optimal_filter_is_a_stationary_minimum():
+    """The objective's gradient in phi vanishes at phi* on every kept component, and random perturbations
+    of phi* (kept components) only increase it: the quadratic is convex (Qbar is a Gram matrix)."""
+    fs, Q, c, F2, w, Z, keep = _stats()
+    phi, best = LR.optimal_filter(Q, c, F2, w, Z, keep)
+    grad = 2.0 * (np.einsum("fkjrq,kjq->kjr", Q, phi) - c.sum(axis=0))
+    assert np.max(np.abs(np.where(keep, grad, 0.0))) <= 1e-9 * np.max(np.abs(c.sum(axis=0)))
+    for _ in range(20):
+        d = np.where(keep, RNG.standard_normal(phi.shape) * 1e-2, 0.0)
+        assert LR.objective(phi + d, Q, c, F2, w, Z) > best
+    # below the objective of every Tikhonov filter on the same frames
+    for alpha in (1e-6, 1e-3, 1e-1, 10.0):
+        tik = LR.tikhonov_factors(fs["sigma"], alpha, keep)
+        assert LR.objective(tik, Q, c, F2, w, Z) >= best
+
+
+def test_optimal_filter_one_component_closed_form_and_brute_force():
+    """With one kept component the optimum is sum_f c_f / sum_f Q_f; with two, a direct numerical
+    minimisation of the objective at one frequency (scipy, no use of the normal equations) finds phi*."""
+    from scipy.optimize import minimize
+    fs, Q, c, F2, w, Z, keep = _stats(F=3)
+    k, j = 3, 5
+    assert keep[k, j].all()
+    one = keep.copy()
+    one[k, j, 1] = False
+    phi1, _ = LR.optimal_filter(Q, c, F2, w, Z, one)
+    assert abs(phi1[k, j, 0] - c[:, k, j, 0].sum() / Q[:, k, j, 0, 0].sum()) <= 1e-12 * abs(phi1[k, j, 0])
+    assert phi1[k, j, 1] == 0.0
+    phi, _ = LR.optimal_filter(Q, c, F2, w, Z, keep)
+    f = lambda x: float(np.sum(x @ Q[:, k, j] @ x) - 2.0 * np.sum(c[:, k, j] @ x))
+    res = minimize(f, np.zeros(2), method="Nelder-Mead", options={"xatol": 1e-12, "fatol": 1e-18, "maxiter": 4000})
+    assert np.max(np.abs(res.x - phi[k, j])) <= 1e-6 * np.max(np.abs(phi[k, j]))
+
+
+def test_tikhonov_factors_reproduce_the_tikhonov_filter():
+    """g = phi / sigma with phi = s^2 / (s^2 + alpha) is Tikhonov's g(s) = s / (s^2 + alpha) (Sec. 3.1)."""
+    s = np.array([[[3.0, 0.5, 1e-3]]])
+    keep = np.ones_like(s, dtype=bool)
+    phi = LR.tikhonov_factors(s, 0.25, keep)
+    assert np.allclose(phi / s, s / (s ** 2 + 0.25), rtol=1e-15)
