@@ -176,6 +176,21 @@ safr_status safr_reconstruct(safr_plan* p, const float* wavefronts, float* layer
 safr_status safr_reconstruct_batched(safr_plan* p, int frames, const float* wavefronts,
                                      float* layers, int precision, hipStream_t stream);
 
+/*
+ * For callers that cannot allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): safr_reconstruct_batched with the workspace in a static device array of the library
+ * (safr_static_workspace_bytes(), 64 MiB; each GPU the library runs on holds its own copy until the process
+ * ends) instead of a bound workspace.  Launches the same kernels and gives the same layers; calls no
+ * allocating routine and never captures a graph (SAFR_OPT_GRAPH is ignored).  Frame counts whose workspace
+ * (safr_workspace_size) exceeds the array are rejected with SAFR_ERR_ARG (MORFEO-like plans: up to 20
+ * frames).  Nothing in the path reads the array before writing it, so no call clears it; every call on a
+ * GPU shares that GPU's array, so calls that overlap on one GPU (other streams, other threads) race and must
+ * be ordered by the caller.  The first call on a device looks up the array's device address (no allocation).
+ */
+safr_status safr_reconstruct_batched_static(safr_plan* p, int frames, const float* wavefronts, float* layers,
+                                            int precision, hipStream_t stream);
+size_t safr_static_workspace_bytes(void);
+
 /* Device workspace bytes needed for `frames` frames. */
 safr_status safr_workspace_size(const safr_plan* p, int frames, int precision, size_t* bytes);
 

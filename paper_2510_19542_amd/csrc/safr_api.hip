@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <mutex>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -931,6 +932,59 @@ safr_status safr_reconstruct_batched(safr_plan* p, int frames, const float* wf, 
 
 safr_status safr_reconstruct(safr_plan* p, const float* wf, float* out, hipStream_t s) {
     return safr_reconstruct_batched(p, 1, wf, out, SAFR_FP32, s);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Workspace of safr_reconstruct_batched_static: a file-scope device array (each GPU that loads the library
+// holds its own copy until the process ends).  In host code its name is only a stand-in: the device address
+// is looked up once per device with hipGetSymbolAddress and kept; kernels receive that address.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+void* g_scratch[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+safr_status static_scratch(void** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SAFR_ERR_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(SAFR_ERR_DEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_scratch[dev] = ptr;
+    }
+    *out = g_scratch[dev];
+    return SAFR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t safr_static_workspace_bytes(void) { return kStaticScratchBytes; }
+
+safr_status safr_reconstruct_batched_static(safr_plan* p, int frames, const float* wf, float* out, int precision,
+                                            hipStream_t s) {
+    if (!p || !wf || !out) return fail(SAFR_ERR_ARG, "NULL argument");
+    if (frames < 1) return fail(SAFR_ERR_ARG, "frames must be >= 1");
+    if (precision != SAFR_FP32 && precision != SAFR_BF16X3) return fail(SAFR_ERR_ARG, "bad precision");
+    if (precision == SAFR_BF16X3 && !p->Apack)
+        return fail(SAFR_ERR_UNSUPPORTED, "BF16 path not available for this plan");
+    const size_t need = ws_bytes(p, frames);
+    if (need > kStaticScratchBytes)
+        return fail(SAFR_ERR_ARG, "%d frames of this plan need %zu bytes of workspace; the static workspace holds %zu "
+                                  "(at most %zu frames)", frames, need, kStaticScratchBytes,
+                    (size_t)(kStaticScratchBytes / std::max<size_t>(1, ws_bytes(p, 1))));
+    void* ws = nullptr;
+    const safr_status st = static_scratch(&ws);
+    if (st != SAFR_OK) return st;
+    return launch_all(p, frames, wf, out, precision, ws, s);
 }
 
 

@@ -34,6 +34,7 @@ EXPORTED = [
     "safr_autotune", "safr_destroy", "safr_last_error",
     "safr_multi_create", "safr_multi_execute", "safr_multi_autotune", "safr_multi_destroy",
     "safr_polc", "safr_loop_step", "safr_strehl", "safr_update_alpha", "safr_import_B", "safr_deadline_stats",
+    "safr_reconstruct_batched_static", "safr_static_workspace_bytes",
     # learned filter (bound in learn.py)
     "safr_trainer_create", "safr_trainer_add_frames", "safr_trainer_set_params", "safr_trainer_get_params",
     "safr_trainer_get_state", "safr_trainer_set_state",
@@ -120,9 +121,12 @@ def lib() -> ctypes.CDLL:
     L.safr_strehl.argtypes = [vp, i, i, ctypes.POINTER(d), vp, vp, ctypes.c_float, vp, vp, vp]
     L.safr_update_alpha.argtypes = [vp, d, d, i, ctypes.POINTER(d), vp]
     L.safr_import_B.argtypes = [vp, i, ctypes.POINTER(d), sz, vp]
+    L.safr_reconstruct_batched_static.argtypes = [vp, i, vp, vp, i, vp]
+    L.safr_static_workspace_bytes.argtypes = []
+    L.safr_static_workspace_bytes.restype = sz
     L.safr_deadline_stats.argtypes = [vp, ctypes.POINTER(safr_deadline_info), i, vp]
     for name in EXPORTED[:EXPORTED.index("safr_trainer_create")]:
-        if name not in ("safr_destroy", "safr_last_error", "safr_multi_destroy"):
+        if name not in ("safr_destroy", "safr_last_error", "safr_multi_destroy", "safr_static_workspace_bytes"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -228,6 +232,17 @@ def safr_reconstruct_batched(plan: Plan, frames: int, wavefronts, layers, precis
                              stream=None):
     _check(lib().safr_reconstruct_batched(plan._as_parameter_, int(frames), _ptr(wavefronts), _ptr(layers),
                                           int(precision), _stream(stream)))
+
+
+def safr_reconstruct_batched_static(plan: Plan, frames: int, wavefronts, layers, precision: int = SAFR_FP32,
+                                    stream=None):
+    """safr_reconstruct_batched with the library's static workspace (allocates nothing; see safr.h)."""
+    _check(lib().safr_reconstruct_batched_static(plan._as_parameter_, int(frames), _ptr(wavefronts), _ptr(layers),
+                                                 int(precision), _stream(stream)))
+
+
+def safr_static_workspace_bytes() -> int:
+    return int(lib().safr_static_workspace_bytes())
 
 
 def safr_workspace_size(plan: Plan, frames: int, precision: int = SAFR_FP32) -> int:
