@@ -21,16 +21,26 @@
 
 namespace safr {
 
-template <int M>
+// NN > 0: the pupil size at compile time (the configured workloads); only the inputs that can fall inside
+// the pupil columns are loaded.  All loads are issued unconditionally (addresses clamped into the block's
+// rows, values outside the pupil or past the chunk selected away), so the compiler can wait for them as a
+// group instead of one at a time behind branches.
+template <int M, int NN>
 __global__ __launch_bounds__(256) void rows_kernel(RowArgs a) {
     using S = FftShape<M>;
     constexpr int T = S::T, N1 = S::N1, N2 = S::N2;
     constexpr int Kh = M / 2 + 1;
     constexpr int KC = M / 2;                       // columns written: the Nyquist column is not used
     constexpr int TS = team_lds<M>() + 2;           // team region stride, 4 banks apart
+    constexpr int P0 = NN > 0 ? (M - NN + 1) / 2 : 0;
+    // grid column N2 n1 + t (t < T = N2) meets the pupil columns p0 .. p0 + n - 1 only for n1 in [WLO, WHI]
+    constexpr int WLO = NN > 0 && P0 - N2 + 1 > 0 ? (P0 - N2 + 1 + N2 - 1) / N2 : 0;
+    constexpr int WHI = NN > 0 ? ((P0 + NN - 1) / N2 < N1 - 1 ? (P0 + NN - 1) / N2 : N1 - 1) : N1 - 1;
+    static_assert(T == N2, "one pass-1 sub-transform per team thread");
     extern __shared__ float2 smem[];
 
-    const int n = a.n;
+    const int n = NN > 0 ? NN : a.n;
+    const int p0 = NN > 0 ? P0 : a.p0;
     const int star = blockIdx.y;
     const int f = blockIdx.z;
     const int chunk = blockIdx.x;
@@ -51,31 +61,38 @@ __global__ __launch_bounds__(256) void rows_kernel(RowArgs a) {
     float2* xch = smem + M + team * TS;
     float* red = reinterpret_cast<float*>(smem + M + nteams * TS);
 
-    // the team's two pupil-masked rows straight into the pass-1 registers: x[n1] = (row a, row b) at grid
-    // column N2 n1 + t, i.e. pupil column N2 n1 + t - p0 (all loads issued before any is used)
+    // twiddles first (blocks may have fewer than M threads), then the team's two pupil-masked rows straight
+    // into the pass-1 registers: x[n1] = (row a, row b) at grid column N2 n1 + t, i.e. pupil column
+    // N2 n1 + t - p0 (all loads issued before any is used)
+    constexpr int TWR = (M + 63) / 64;
+    float2 twr[TWR];
+#pragma unroll
+    for (int u = 0; u < TWR; ++u) twr[u] = a.tw[min(tid + u * nthr, M - 1)];
     const int ra = 2 * team;
     const bool active = team < nteams && ra < rows;
     const bool has_b = active && ra + 1 < rows;
-    const float* wa = wf + (size_t)ra * n;
-    const unsigned char* pa = pup + (size_t)ra * n;
+    const int rla = min(ra, rows - 1), rlb = min(ra + 1, rows - 1);      // rows in the chunk (rows >= 1)
+    const float* wa = wf + (size_t)rla * n;
+    const float* wb = wf + (size_t)rlb * n;
+    const unsigned char* pa = pup + (size_t)rla * n;
+    const unsigned char* pb = pup + (size_t)rlb * n;
     float2 x[N1];
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1) {
-        const int qc = N2 * n1 + t - a.p0;
-        const bool in = active && qc >= 0 && qc < n;
-        float va = 0.f, vb = 0.f;
-        unsigned char ma = 0, mb = 0;
-        if (in) {
-            ma = pa[qc];
-            va = wa[qc];
-            if (has_b) {
-                mb = pa[n + qc];
-                vb = wa[n + qc];
-            }
+        if (n1 < WLO || n1 > WHI) {
+            x[n1] = make_float2(0.f, 0.f);
+            continue;
         }
-        x[n1] = make_float2(ma ? va : 0.f, mb ? vb : 0.f);
+        const int qc = N2 * n1 + t - p0;
+        const bool in = active && qc >= 0 && qc < n;
+        const int qs = min(max(qc, 0), n - 1);
+        const unsigned char ma = pa[qs], mb = pb[qs];
+        const float va = wa[qs], vb = wb[qs];
+        x[n1] = make_float2(in && ma ? va : 0.f, in && has_b && mb ? vb : 0.f);
     }
-    for (int i = tid; i < M; i += nthr) tws[i] = a.tw[i];   // blocks may have fewer than M threads
+#pragma unroll
+    for (int u = 0; u < TWR; ++u)
+        if (tid + u * nthr < M) tws[tid + u * nthr] = twr[u];
 
     if (mode != 0) {
         // partial moments (sum v, sum x v, sum y v) of the chunk, coordinates about the pupil centre
@@ -84,7 +101,7 @@ __global__ __launch_bounds__(256) void rows_kernel(RowArgs a) {
         float m0 = 0.f, m1 = 0.f, m2 = 0.f;
 #pragma unroll
         for (int n1 = 0; n1 < N1; ++n1) {
-            const float y = (float)(N2 * n1 + t - a.p0) - half;
+            const float y = (float)(N2 * n1 + t - p0) - half;
             const float s = x[n1].x + x[n1].y;
             m0 += s;
             m1 = fmaf(xa, x[n1].x, fmaf(xb, x[n1].y, m1));
@@ -183,22 +200,26 @@ hipError_t launch_planes(const PlaneKArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int M>
+template <int M, int NN>
 static hipError_t launch_rows_t(const RowArgs& a, int frames, int nchunk, int teams, hipStream_t s) {
     constexpr int T = FftShape<M>::T;
     const size_t lds = rows_lds_bytes(M, a.n, teams);
-    allow_large_lds(reinterpret_cast<const void*>(&rows_kernel<M>));
+    allow_large_lds(reinterpret_cast<const void*>(&rows_kernel<M, NN>));
     const int threads = ((teams * T + 63) / 64) * 64;       // whole wavefronts (the reduction uses all lanes)
-    hipLaunchKernelGGL(rows_kernel<M>, dim3(nchunk, a.J, frames), dim3(threads), lds, s, a);
+    hipLaunchKernelGGL((rows_kernel<M, NN>), dim3(nchunk, a.J, frames), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 
+// pupil sizes of the configured workloads get a compile-time kernel (n = 69 at M = 256, 41 at 128, 33 at 64)
 hipError_t launch_rows(int M, const RowArgs& a, int frames, int nchunk, int teams, hipStream_t s) {
     switch (M) {
-        case 32: return launch_rows_t<32>(a, frames, nchunk, teams, s);
-        case 64: return launch_rows_t<64>(a, frames, nchunk, teams, s);
-        case 128: return launch_rows_t<128>(a, frames, nchunk, teams, s);
-        case 256: return launch_rows_t<256>(a, frames, nchunk, teams, s);
+        case 32: return launch_rows_t<32, 0>(a, frames, nchunk, teams, s);
+        case 64: return a.n == 33 ? launch_rows_t<64, 33>(a, frames, nchunk, teams, s)
+                                  : launch_rows_t<64, 0>(a, frames, nchunk, teams, s);
+        case 128: return a.n == 41 ? launch_rows_t<128, 41>(a, frames, nchunk, teams, s)
+                                   : launch_rows_t<128, 0>(a, frames, nchunk, teams, s);
+        case 256: return a.n == 69 ? launch_rows_t<256, 69>(a, frames, nchunk, teams, s)
+                                   : launch_rows_t<256, 0>(a, frames, nchunk, teams, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -90,7 +90,7 @@ struct safr_plan {
     int weighted = 0;               // B was made with a per-frequency alpha map
     int imported = 0;               // B replaced by safr_import_B (the kept SVDs no longer describe it)
     unsigned char* pupil = nullptr;
-    int* tt_mode = nullptr;
+    int tt_mode[kMaxJ] = {};        // per star: 0 none, 1 remove tip/tilt, 2 plane only
     unsigned plane_mask = 0;     // bit g: star g's tip/tilt plane is used (split tomography)
     float4* polc_tab = nullptr;     // [J][L] line-of-sight sampling of the output grids (closed loop)
     float* strehl_part = nullptr;   // per-chunk moments of the Strehl estimate (grown on demand)
@@ -170,7 +170,6 @@ void free_plan(safr_plan* p) {
     (void)hipFree(p->Yh);
     (void)hipFree(p->P);
     (void)hipFree(p->pupil);
-    (void)hipFree(p->tt_mode);
     (void)hipFree(p->polc_tab);
     (void)hipFree(p->strehl_part);
     for (int gi = 0; gi < 2; ++gi) {
@@ -580,8 +579,7 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
         PC_TRY(hipMemcpy(p->tw, tw.data(), M * sizeof(float2), hipMemcpyHostToDevice));
         PC_TRY(hipMalloc(&p->pupil, pup.size()));
         PC_TRY(hipMemcpy(p->pupil, pup.data(), pup.size(), hipMemcpyHostToDevice));
-        PC_TRY(hipMalloc(&p->tt_mode, J * sizeof(int)));
-        PC_TRY(hipMemcpy(p->tt_mode, mode.data(), J * sizeof(int), hipMemcpyHostToDevice));
+        for (int g = 0; g < J; ++g) p->tt_mode[g] = mode[g];
         for (int g = 0; g < J; ++g)
             if (mode[g] != 0) p->plane_mask |= 1u << g;
         {
@@ -1468,7 +1466,7 @@ safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, in
     ra.R = R;
     ra.mom = mom;
     ra.pupil = p->pupil;
-    ra.tt_mode = p->tt_mode;
+    for (int g = 0; g < p->J; ++g) ra.tt_mode[g] = p->tt_mode[g];
     ra.tw = p->tw;
     ra.n = p->n;
     ra.J = p->J;

@@ -34,10 +34,10 @@ struct RowArgs {
     float2* R;                  // [F][J][Kh][n]
     float* mom;                 // [F][J][nchunk][4] partial moments (sum v, sum x v, sum y v, 0)
     const unsigned char* pupil; // [n][n]
-    const int* tt_mode;         // [J]: 0 none, 1 remove tip/tilt, 2 plane only (moments, no transform)
     const float2* tw;           // (cos, sin)(2 pi e / M), e < M
     int n, J, p0, rows_per_block;
     int slot[kMaxJ];            // group slot of star g
+    int tt_mode[kMaxJ];         // star g: 0 none, 1 remove tip/tilt, 2 plane only (moments, no transform)
 };
 
 // Sum over layers of the commands `lay` ([L][M][M]) sampled by periodic bilinear interpolation at

@@ -1,7 +1,8 @@
 """Mixed-size batches: several plans executed in one graph launch.
 
 * the bundle's results equal each plan's own batched reconstruction bit for bit
-  (same kernels, same launch shapes), on replays with eager work in between;
+  (same kernels, same launch shapes), launched eagerly and replayed from its captured
+  graph on a non-default stream, with eager work in between;
 * the mixed-size workload (64 instances of three sizes, 16 frames each, learned
   filter at eta = 2%) against the FP64 oracle on sampled frames of every size:
   relative L2 <= 1e-4 per frame.
@@ -40,7 +41,10 @@ def _mixed32():
 
 
 @pytest.mark.parametrize("precision", ["FP32", "BF16X3"])
-def test_bundle_equals_single_plans(precision):
+@pytest.mark.parametrize("mode", ["eager", "graph"])
+def test_bundle_equals_single_plans(precision, mode):
+    """eager: the legacy stream (launched directly); graph: a non-default stream, where the first call captures
+    the entries as parallel branches of one graph and later calls replay it."""
     torch, S = _setup()
     prec = getattr(S, "SAFR_" + precision)
     geos = [synth.preset("C5-Mid"), synth.preset("C5-S"), _mixed32(), synth.preset("C5-S")]
@@ -51,11 +55,13 @@ def test_bundle_equals_single_plans(precision):
     want = [S.reconstruct(p, x, precision=prec).cpu().numpy() for p, x in zip(plans, wf)]
     m = S.Multi(plans, frames, precision=prec)
     outs = [torch.full((f, g.L, g.M, g.M), float("nan"), device="cuda") for g, f in zip(geos, frames)]
+    stream = torch.cuda.Stream() if mode == "graph" else torch.cuda.current_stream()
+    assert (stream.cuda_stream != 0) == (mode == "graph")
     for rep in range(3):
         for o in outs:
             o.fill_(float("nan"))
         torch.cuda.synchronize()
-        m.execute(wf, outs, stream=torch.cuda.current_stream())
+        m.execute(wf, outs, stream=stream)
         torch.cuda.synchronize()
         for i, (o, w) in enumerate(zip(outs, want)):
             assert np.array_equal(o.cpu().numpy(), w), (precision, rep, i)
@@ -87,10 +93,18 @@ def test_mixed_size_workload_learned_filter():
     outs = [torch.empty((f, g.L, g.M, g.M), device="cuda") for g, f in zip(geos, frames)]
     m = S.Multi(plans, frames)
     m.autotune(wf, outs, iters=2)
-    for o in outs:
-        o.fill_(float("nan"))
-    m.execute(wf, outs, stream=torch.cuda.current_stream())
-    torch.cuda.synchronize()
+    # a non-default stream: the first call captures the bundle's graph, the second replays it
+    stream = torch.cuda.Stream()
+    for rep in range(2):
+        for o in outs:
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        m.execute(wf, outs, stream=stream)
+        torch.cuda.synchronize()
+        if rep == 0:
+            first = [o.clone() for o in outs]
+    for o, o1 in zip(outs, first):
+        assert torch.equal(o, o1)
     for name, g, f, w, o in zip(names, geos, frames, wf_host, outs):
         ref = O.precompute_geometry(g, mlp_params=params.astype(np.float64), eta=np.float32(eta), mlp_bf16=True)
         got = o.cpu().numpy()
