@@ -251,10 +251,18 @@ safr_status safr_import_B(safr_plan* p, int group, const double* host, size_t co
  *                        kernel has finished, counts the step and whether it took longer than P (two
  *                        one-thread kernels around the step, captured with it in a graph); read and reset
  *                        the counts with safr_deadline_stats.  0 = off (default).  The first call with
- *                        P > 0 allocates the plan's counters and synchronises. */
+ *                        P > 0 allocates the plan's counters and synchronises;
+ *   SAFR_OPT_COL_MFMA    1 = when the FP32 column pass transforms 4 frames together in its
+ *                        compile-time kernel, the per-frequency products B_n d_n of those frames run
+ *                        on the matrix cores as 4 x 4 x 1 FP32 products (the 4 frames times 4 layers,
+ *                        one star per step; FP32 products and sums as on the vector units); the first
+ *                        call with 1 lays out a copy of B for it (device memory of the size of the
+ *                        column group's FP32 B, padded to multiples of 4 layers) and synchronises.
+ *                        0 = on the vector units (default: faster at the configured shapes). */
 enum { SAFR_OPT_GRAPH = 0, SAFR_OPT_ROW_TEAMS = 1, SAFR_OPT_OUT_ROWS = 2, SAFR_OPT_MFMA_FRAMES = 3,
        SAFR_OPT_COL_FRAMES = 4, SAFR_OPT_COL_PREFETCH = 5, SAFR_OPT_OUT_FRAMES = 6,
-       SAFR_OPT_COL_TOGETHER = 7, SAFR_OPT_CHECK_FINITE = 8, SAFR_OPT_DEADLINE_US = 9 };
+       SAFR_OPT_COL_TOGETHER = 7, SAFR_OPT_CHECK_FINITE = 8, SAFR_OPT_DEADLINE_US = 9,
+       SAFR_OPT_COL_MFMA = 10 };
 safr_status safr_set_option(safr_plan* p, int option, int value);
 
 /* Deadline monitor of the closed-loop step (SAFR_OPT_DEADLINE_US): steps counted since the last reset,

@@ -92,8 +92,9 @@ __device__ __forceinline__ bool xcd_work(int nwork, int& w) {
 
 }  // namespace
 
-template <int M, int NF, int GC, int LC, int MODE, int LSPLIT = 1, int NN = 0>
+template <int M, int NF, int GC, int LC, int MODE, int LSPLIT = 1, int NN = 0, bool MF = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 2 : 3))) void cols_kernel(ColArgs a) {
+    static_assert(!MF || (GC > 0 && NF == 4 && LSPLIT == 1), "the matrix-core apply takes 4 frames as its rows");
     using S = FftShape<M>;
     constexpr int T = S::T, N1 = S::N1, NTEAM = 256 / T, TL = team_lds<M>() + 2;   // slot stride, 4 banks apart
     constexpr int CPW = 256 / M, Kh = M / 2 + 1;
@@ -134,6 +135,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
     // forward tasks: (column, frame, star); rounds of NTEAM teams
     const int ftasks = CPW * NF * G;
     constexpr int FR_MAX = FIX ? (CPW * NF * GC + NTEAM - 1) / NTEAM : 1;
+    constexpr int FR_UNROLL = FR_MAX;                          // run-time round counts are not unrolled
     float2 xf[FR_MAX][N1];
     // R of frames f0 .. f0 + NF - 1 through one descriptor (byte offsets stay below 2^31)
     const int fstride = a.J * Kh * a.n;                        // float2 per frame of R
@@ -189,6 +191,73 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
     //
     // forward transforms and apply of the NF frames from f0 (for compile-time shapes their first round's
     // inputs are in xf[0] already)
+    // The apply on the matrix cores (MF: compile-time shapes with NF = 4).  v_mfma_f32_4x4x1f32 computes 16
+    // independent 4 x 4 outer products per wavefront: block = (column, frequency) pair, rows = the 4 frames,
+    // columns = 4 layers, accumulated over the stars.  Lane 4b + m holds row m of block b's A operand and
+    // column m of its B operand; the result for (row m, column n) lands in lane 4b + n, register m.  The
+    // complex product is four real ones: Re b += Re d Re B - Im d Im B, Im b += Im d Re B + Re d Im B.  Each
+    // wavefront takes 4 groups of 16 pairs (its 64 pairs): it reads the d of all frames and stars of a group
+    // into registers, then writes the group's b into the layer slots (in place: only its own pairs).
+    [[maybe_unused]] auto apply_mfma = [&](int f0) {
+        if constexpr (MF) {
+            typedef float f32x4 __attribute__((ext_vector_type(4)));
+            constexpr int LBK = (LC + 3) / 4;                   // layer blocks of 4 (padded with zero B)
+            const int wave = tid >> 6, lane = tid & 63, m4 = lane & 3;
+            const __amdgpu_buffer_rsrc_t bmr =
+                block_rsrc(a.Bm + (size_t)kb * 16 * LBK * GC * 64, (unsigned)(16 * LBK * GC * 64 * 8));
+            (void)f0;
+#pragma unroll 1
+            for (int q = 0; q < 4; ++q) {
+                const int grp = wave * 4 + q;
+                const int pr = grp * 16 + (lane >> 2);          // (column, frequency) pair of the lane's block
+                const int cq = pr / M, jq = pr % M;
+                float ar[GC], ai[GC];
+                float2 xq = make_float2(0.f, 0.f), yq = make_float2(0.f, 0.f);
+                if constexpr (MODE != 0) {
+                    xq = a.Xh[(size_t)(kb * CPW + cq) * M + jq];
+                    yq = a.Yh[(size_t)(kb * CPW + cq) * M + jq];
+                }
+                float2 bb[2][GC];
+#pragma unroll
+                for (int g = 0; g < GC; ++g)
+                    bb[0][g] = load_f2(bmr, (((grp * LBK + 0) * GC + g) * 64 + lane) * 8);
+#pragma unroll
+                for (int g = 0; g < GC; ++g) {
+                    float2 d = slot(cq, m4, g)[jq];             // frame m4 of the lane's pair
+                    if constexpr (MODE != 0) d = remove_plane(d, coef[m4 * GC + g], xq, yq);
+                    ar[g] = d.x;
+                    ai[g] = d.y;
+                }
+                f32x4 accR[LBK], accI[LBK];
+#pragma unroll
+                for (int lb = 0; lb < LBK; ++lb) {
+                    accR[lb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+                    accI[lb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+                    if (lb + 1 < LBK) {
+#pragma unroll
+                        for (int g = 0; g < GC; ++g)
+                            bb[(lb + 1) & 1][g] = load_f2(bmr, (((grp * LBK + lb + 1) * GC + g) * 64 + lane) * 8);
+                    }
+#pragma unroll
+                    for (int g = 0; g < GC; ++g) {
+                        const float2 bv = bb[lb & 1][g];
+                        accR[lb] = __builtin_amdgcn_mfma_f32_4x4x1f32(ar[g], bv.x, accR[lb], 0, 0, 0);
+                        accR[lb] = __builtin_amdgcn_mfma_f32_4x4x1f32(-ai[g], bv.y, accR[lb], 0, 0, 0);
+                        accI[lb] = __builtin_amdgcn_mfma_f32_4x4x1f32(ai[g], bv.x, accI[lb], 0, 0, 0);
+                        accI[lb] = __builtin_amdgcn_mfma_f32_4x4x1f32(ar[g], bv.y, accI[lb], 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int lb = 0; lb < LBK; ++lb) {
+                    const int l = lb * 4 + m4;
+                    if (l < LC) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) slot(cq, r, l)[jq] = make_float2(accR[lb][r], accI[lb][r]);
+                    }
+                }
+            }
+        }
+    };
     constexpr bool PFN = FIX && NN > 0;        // next inputs requested ahead of the stores (pupil size known)
     auto fwd_apply = [&](int f0) {
         if constexpr (FIX && !PFN) load_fwd(f0, 0, xf[0]);
@@ -200,7 +269,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
         __syncthreads();                                        // previous inverse transforms done with the slots
         // 1. forward column transforms into the star slots
         const int frounds = FIX ? FR_MAX : (ftasks + NTEAM - 1) / NTEAM;
-#pragma unroll
+#pragma unroll FR_UNROLL
         for (int r = 0; r < frounds; ++r) {
             const int task = r * NTEAM + team;
             const int cc = task / (NF * G), rem = task - cc * (NF * G);
@@ -227,7 +296,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
         // B of the block's first two layers, requested before the barrier; later layers two ahead of use
         constexpr int BD = 3;                                   // B buffers in flight (prefetch distance 2)
         float2 bq[BD][FIX ? GC : 1];
-        if constexpr (FIX) {
+        if constexpr (FIX && !MF) {
 #pragma unroll
             for (int q = 0; q < BD - 1; ++q) {
                 if (q < LB && (LSPLIT == 1 || q < nl)) {
@@ -241,7 +310,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
         __syncthreads();
 
         // 2. apply: b_l(j) = sum_g B[l][g][j] d_g(j) for the NF frames
-        if constexpr (FIX) {
+        if constexpr (MF) {
+            apply_mfma(f0);
+        } else if constexpr (FIX) {
             float2 dv[NF][GC];
 #pragma unroll
             for (int fl = 0; fl < NF; ++fl)
@@ -288,11 +359,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
         // no branches and the waits after them can be counted.
         const int itasks = CPW * NF * nl;
         constexpr int IR_MAX = FIX ? (CPW * NF * LB + NTEAM - 1) / NTEAM : 1;
+        constexpr int IR_UNROLL = IR_MAX;
         const int irounds = FIX ? IR_MAX : (itasks + NTEAM - 1) / NTEAM;
         const int nfr = min(NF, fend - f0);
         const size_t cfr = (size_t)L * Kh * M;                 // float2 per frame of C
         const __amdgpu_buffer_rsrc_t cr = block_rsrc(a.C + c_index(f0, 0, L, M, 0, 0), (unsigned)(nfr * cfr * 8));
-#pragma unroll
+#pragma unroll IR_UNROLL
         for (int r = 0; r < irounds; ++r) {
             const int task = r * NTEAM + team;
             const int cc = task / (NF * nl), rem = task - cc * (NF * nl);
@@ -327,6 +399,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
     }
     __syncthreads();
     inverse(f0);
+}
+
+// B in the matrix-core lane layout (see ColArgs::Bm): one thread per output float2
+__global__ void pack_mfma_b_kernel(int M, int L, int G, const float2* __restrict__ B32, float2* __restrict__ Bm,
+                                   size_t count) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    const int LBK = (L + 3) / 4;
+    const int lane = (int)(e % 64);
+    size_t r = e / 64;
+    const int g = (int)(r % G);
+    r /= G;
+    const int lb = (int)(r % LBK);
+    r /= LBK;
+    const int grp = (int)(r % 16);
+    const size_t kb = r / 16;
+    const int l = lb * 4 + lane % 4, pr = grp * 16 + lane / 4;
+    Bm[e] = l < L ? B32[((kb * L + l) * G + g) * 256 + pr] : make_float2(0.f, 0.f);
+}
+
+size_t mfma_b_count(int M, int L, int G) {
+    const int kblocks = (M / 2) / (256 / M);                  // the columns k < M/2 of the column pass
+    return (size_t)kblocks * 16 * ((L + 3) / 4) * G * 64;
+}
+
+hipError_t launch_pack_mfma_b(int M, int L, int G, const float2* B32, float2* Bm, hipStream_t s) {
+    const size_t count = mfma_b_count(M, L, G);
+    hipLaunchKernelGGL(pack_mfma_b_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, M, L, G, B32, Bm,
+                       count);
+    return hipGetLastError();
 }
 
 size_t cols_lds_bytes(int M, int G, int L, int nf, bool fixed) {
@@ -372,7 +474,9 @@ hipError_t launch_fixed_n(const ColArgs& a, int nf, int frames, hipStream_t s) {
     switch (nf) {
         case 1: return launch_cols_kernel(&cols_kernel<M, 1, G, L, MODE, 1, NN>, M, 1, true, a, frames, s);
         case 2: return launch_cols_kernel(&cols_kernel<M, 2, G, L, MODE, 1, NN>, M, 2, true, a, frames, s);
-        case 4: return launch_cols_kernel(&cols_kernel<M, 4, G, L, MODE, 1, NN>, M, 4, true, a, frames, s);
+        case 4:
+            return a.Bm ? launch_cols_kernel(&cols_kernel<M, 4, G, L, MODE, 1, NN, true>, M, 4, true, a, frames, s)
+                        : launch_cols_kernel(&cols_kernel<M, 4, G, L, MODE, 1, NN>, M, 4, true, a, frames, s);
         default: return hipErrorInvalidValue;
     }
 }

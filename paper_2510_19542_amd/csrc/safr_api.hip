@@ -74,6 +74,7 @@ struct safr_plan {
     double2* B64 = nullptr;
     float2* B32 = nullptr;
     uint16_t* Apack = nullptr;
+    float2* Bm = nullptr;           // group 0's B in the matrix-core lane layout (FP32 column pass, 4 frames)
     size_t apack_off[2] = {0, 0};
     int mf_lt[2] = {0, 0}, mf_ntile[2] = {0, 0}, mf_ppm[2] = {0, 0};
     float2* tw = nullptr;
@@ -101,6 +102,7 @@ struct safr_plan {
     size_t ws_user_bytes = 0;
     // tuning
     int row_teams = 0, out_rows = 0, out_frames = 1, mfma_frames = 16, col_frames = 1, col_nf = 1, col_prefetch = 1;
+    int col_mfma = 0;               // FP32 column pass with 4 frames: the apply on the matrix cores
     int col_frames_auto = 1;        // column frames per block chosen per launch (until set or autotuned)
     int use_graph = 0;
     int deadline_us = 0;            // loop-step deadline (0: off), see SAFR_OPT_DEADLINE_US
@@ -165,6 +167,7 @@ void free_plan(safr_plan* p) {
     (void)hipFree(p->B64);
     (void)hipFree(p->B32);
     (void)hipFree(p->Apack);
+    (void)hipFree(p->Bm);
     (void)hipFree(p->tw);
     (void)hipFree(p->Xh);
     (void)hipFree(p->Yh);
@@ -325,9 +328,22 @@ safr_status build_basis(safr_plan* p, hipStream_t s) {
     return st;
 }
 
-// BF16 hi/lo tiles of the real-split B for the matrix-core apply (M <= 128), column group only
+// BF16 hi/lo tiles of the real-split B for the matrix-core apply (M <= 128), column group only; and (any M)
+// the FP32 B in the lane layout of the four-frame column pass's matrix-core apply
+safr_status build_mfma_b(safr_plan* p, hipStream_t s) {
+    const int M = p->M, L = p->L, G = p->gsize[0];
+    if (!p->col_mfma || !cols_fixed_shape(M, L, G, p->mixed ? 1 : 0)) return SAFR_OK;
+    if (!p->Bm) HIP_TRY(hipMalloc(&p->Bm, mfma_b_count(M, L, G) * sizeof(float2)));
+    HIP_TRY(launch_pack_mfma_b(M, L, G, p->B32 + p->boff32[0], p->Bm, s));
+    return SAFR_OK;
+}
+
 safr_status build_pack(safr_plan* p, hipStream_t s) {
     const int M = p->M, L = p->L, G = p->gsize[0];
+    {
+        const safr_status st = build_mfma_b(p, s);
+        if (st != SAFR_OK) return st;
+    }
     if (M > 128) return SAFR_OK;
     int nf = 0;
     for (int cand : {16, 8, 4})
@@ -790,7 +806,7 @@ safr_status safr_import_B(safr_plan* p, int group, const double* host, size_t co
     if (group == 1) {
         const safr_status st = build_basis(p, s);
         if (st != SAFR_OK) return st;
-    } else if (p->Apack) {
+    } else {
         const safr_status st = build_pack(p, s);
         if (st != SAFR_OK) return st;
     }
@@ -863,10 +879,8 @@ safr_status safr_update_alpha(safr_plan* p, double alpha, double alpha_tt, int f
             st = build_basis(p, s);
             if (st != SAFR_OK) break;
         }
-        if (p->Apack) {
-            st = build_pack(p, s);
-            if (st != SAFR_OK) break;
-        }
+        st = build_pack(p, s);
+        if (st != SAFR_OK) break;
         BT_TRY(hipStreamSynchronize(s));
         p->galpha[0] = galpha[0];
         p->galpha[1] = galpha[1];
@@ -1430,6 +1444,19 @@ safr_status safr_set_option(safr_plan* p, int option, int value) {
             p->col_nf = value;
             return SAFR_OK;
         case 8: p->check_finite = value != 0; return SAFR_OK;
+        case 10: {
+            const int was = p->col_mfma;
+            p->col_mfma = value != 0;
+            if (p->col_mfma && !was) {      // the lane layout of B (kept up to date only while on)
+                const safr_status st = build_mfma_b(p, nullptr);
+                if (st != SAFR_OK) {
+                    p->col_mfma = 0;
+                    return st;
+                }
+                HIP_TRY(hipStreamSynchronize(nullptr));
+            }
+            return SAFR_OK;
+        }
         case 9: {
             if (value < 0) return fail(SAFR_ERR_ARG, "the deadline must be >= 0 microseconds");
             if (value > 0 && !p->dstats) {
@@ -1524,6 +1551,7 @@ safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, in
         }
         ca.frames_per_block = std::max(1, std::min(fpb, frames));
         ca.prefetch = p->col_prefetch;
+        ca.Bm = p->col_mfma ? p->Bm : nullptr;
         HIP_TRY(launch_cols(p->M, ca, nf, frames, s));
     } else {
         MfmaArgs ma{};

@@ -86,7 +86,15 @@ struct ColArgs {
     GroupArgs grp;
     int n, J, L, p0, frames, frames_per_block;
     int prefetch;               // 1 = compile-time shape (d in registers, inputs prefetched), when available
+    const float2* Bm;           // B in the matrix-core lane layout (see pack_mfma_b), or nullptr
 };
+
+// B of the transformed group in the lane layout of the matrix-core apply (v_mfma_f32_4x4x1f32: 16 blocks of
+// 4 x 4, K = 1): per column block kb, group q of 16 (column, frequency) pairs, layer block lb and star g, 64
+// float2 where lane i holds B[l = 4 lb + i % 4][g] of pair 16 q + i / 4 (zero for l >= L), from the FP32
+// column-pass layout.  Complex count: column blocks x 16 x ceil(L / 4) x G x 64.
+size_t mfma_b_count(int M, int L, int G);
+hipError_t launch_pack_mfma_b(int M, int L, int G, const float2* B32, float2* Bm, hipStream_t s);
 
 // Output pass: C2R row transforms, scaling by 1/M^2, and (mixed asterisms) the
 // natural-star layers from the basis images.
