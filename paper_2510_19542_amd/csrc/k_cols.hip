@@ -263,7 +263,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
         if constexpr (FIX && !PFN) load_fwd(f0, 0, xf[0]);
         // tip/tilt plane coefficients of this iteration's frames, requested now and stored after the
         // forward transforms
-        const PlaneArgs pa{a.planes, a.J, G, f0, fend, min(NF, fend - f0) * G, 0};
+        const PlaneArgs pa{a.planes, a.plane_nch, a.J, G, f0, fend, min(NF, fend - f0) * G, 0};
         float2 pl[1];
         if (MODE != 0) plane_fetch<1>(pa, pl);
         __syncthreads();                                        // previous inverse transforms done with the slots

@@ -98,7 +98,7 @@ __global__ __launch_bounds__(256) void cols_mfma_kernel(MfmaArgs a) {
 
     for (int i = tid; i < M; i += 256) tws[i] = a.tw[i];
     if (mode != 0) {
-        const PlaneArgs pa{a.planes, a.J, G, fb, fb + nf, nf * G, 0};   // nf = valid frames of the block
+        const PlaneArgs pa{a.planes, a.plane_nch, a.J, G, fb, fb + nf, nf * G, 0};   // nf = valid frames of the block
         float2 pl[1];
         plane_fetch<1>(pa, pl);
         plane_put<1>(pa, pl, coef);

@@ -136,7 +136,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OUT_WAVES))
     };
     // natural stars' plane coefficients (b_g, c_g) of an iteration's frames, [NF][ng] as float2
     auto planes_of = [&](int f0) {
-        return PlaneArgs{a.planes, a.J, nb / 2, f0, fend, min(NF, fend - f0) * (nb / 2), a.ngs_base};
+        return PlaneArgs{a.planes, a.plane_nch, a.J, nb / 2, f0, fend, min(NF, fend - f0) * (nb / 2), a.ngs_base};
     };
 
     const float2 twv = tid < M ? a.tw[tid] : make_float2(0.f, 0.f);

@@ -10,12 +10,12 @@
 // memory straight into the registers of the first transform pass.
 //
 // Split tomography (Sec. 3.3) needs the least-squares tip/tilt plane of each
-// wavefront over the pupil.  Each block writes the partial moments
-// (sum v, sum x v, sum y v) of its own rows; plane_kernel adds them up once per
-// (frame, star) and forms the plane coefficients, which the column pass uses to
-// remove the plane of the laser stars in the Fourier domain and the output pass
-// to add the natural stars' layers.  Natural stars of a mixed asterism
-// therefore need no row transform.
+// wavefront over the pupil.  Its coefficients are linear in the data, so each
+// block forms those of its own rows from their moments (sum v, sum x v, sum y v)
+// and the passes that use the plane add the chunks' parts as they read them: the
+// column pass to remove the plane of the laser stars in the Fourier domain, the
+// output pass to add the natural stars' layers.  Natural stars of a mixed
+// asterism therefore need no row transform.
 #include "fft_device.h"
 #include "safr_internal.h"
 
@@ -126,11 +126,10 @@ __global__ __launch_bounds__(256) void rows_kernel(RowArgs a) {
                 s1 += red[3 * w + 1];
                 s2 += red[3 * w + 2];
             }
-            float* mo = a.mom + (((size_t)f * a.J + star) * gridDim.x + chunk) * 4;
-            mo[0] = s0;
-            mo[1] = s1;
-            mo[2] = s2;
-            mo[3] = 0.f;
+            // the chunk's share of the plane coefficients (the fit is linear in the data)
+            a.part[((size_t)f * a.J + a.slot[star]) * gridDim.x + chunk] =
+                make_float2(a.tt_b[0] * s0 + a.tt_b[1] * s1 + a.tt_b[2] * s2,
+                            a.tt_c[0] * s0 + a.tt_c[1] * s1 + a.tt_c[2] * s2);
         }
     }
     if (mode == 2) return;          // natural star of a mixed asterism: only its plane is used
@@ -168,30 +167,25 @@ __global__ __launch_bounds__(256) void rows_kernel(RowArgs a) {
     }
 }
 
-// One wavefront per (frame, star): the least-squares plane of Sec. 3.3 from the chunk moments, stored in
-// the star's group slot.  Lane q adds chunks q, q + 64, ... (all loads in flight together), then a fixed
-// shuffle tree sums the lanes, so every call adds in the same order.
+// One wavefront per (frame, slot): the parts of its plane coefficients added.  Lane q adds chunks q,
+// q + 64, ... (all loads in flight together), then a fixed shuffle tree sums the lanes, so every call adds
+// in the same order.
 __global__ __launch_bounds__(256) void plane_kernel(PlaneKArgs a) {
     const int i = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (i >= a.count) return;                       // whole wavefronts leave together
-    const bool used = (a.mask >> (i % a.J)) & 1u;   // (0, 0) for a star whose plane is not used
-    const float4* mo = reinterpret_cast<const float4*>(a.mom) + (size_t)i * a.nchunk;
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f;
-    for (int q = lane; used && q < a.nchunk; q += 64) {
-        const float4 v = mo[q];
-        s0 += v.x;
-        s1 += v.y;
-        s2 += v.z;
+    const float2* pt = a.part + (size_t)i * a.nchunk;
+    float2 s = make_float2(0.f, 0.f);
+    for (int q = lane; q < a.nchunk; q += 64) {
+        const float2 v = pt[q];
+        s.x += v.x;
+        s.y += v.y;
     }
     for (int o = 32; o > 0; o >>= 1) {
-        s0 += __shfl_xor(s0, o, 64);
-        s1 += __shfl_xor(s1, o, 64);
-        s2 += __shfl_xor(s2, o, 64);
+        s.x += __shfl_xor(s.x, o, 64);
+        s.y += __shfl_xor(s.y, o, 64);
     }
-    if (lane == 0)
-        a.planes[(size_t)(i / a.J) * a.J + a.slot[i % a.J]] = make_float2(a.tt_b[0] * s0 + a.tt_b[1] * s1 + a.tt_b[2] * s2,
-                                  a.tt_c[0] * s0 + a.tt_c[1] * s1 + a.tt_c[2] * s2);
+    if (lane == 0) a.planes[i] = s;
 }
 
 hipError_t launch_planes(const PlaneKArgs& a, hipStream_t s) {

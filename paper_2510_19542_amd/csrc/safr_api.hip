@@ -92,7 +92,6 @@ struct safr_plan {
     int imported = 0;               // B replaced by safr_import_B (the kept SVDs no longer describe it)
     unsigned char* pupil = nullptr;
     int tt_mode[kMaxJ] = {};        // per star: 0 none, 1 remove tip/tilt, 2 plane only
-    unsigned plane_mask = 0;     // bit g: star g's tip/tilt plane is used (split tomography)
     float4* polc_tab = nullptr;     // [J][L] line-of-sight sampling of the output grids (closed loop)
     float* strehl_part = nullptr;   // per-chunk moments of the Strehl estimate (grown on demand)
     size_t strehl_part_floats = 0;
@@ -131,14 +130,14 @@ struct safr_plan {
 
 namespace {
 
-// workspace: row spectra R, layer column spectra C, partial moments (sized for the smallest row blocks)
+// workspace: row spectra R, layer column spectra C, plane parts of the row chunks (sized for the smallest row blocks)
 size_t ws_r(const safr_plan* p, int frames) { return align256((size_t)frames * p->J * p->Kh * p->n * sizeof(float2)); }
 size_t ws_c(const safr_plan* p, int frames) {
     return align256((size_t)frames * p->L * p->Kh * p->M * sizeof(float2));
 }
-// (the moments, then the plane coefficients per frame and star)
+// (the plane coefficients of every row chunk, then, for more than kPlaneLanes chunks, their sums)
 size_t ws_mom(const safr_plan* p, int frames) {
-    return align256((size_t)frames * p->J * ((p->n + 1) / 2) * 4 * sizeof(float));
+    return align256((size_t)frames * p->J * ((p->n + 1) / 2) * sizeof(float2));
 }
 size_t ws_m(const safr_plan* p, int frames) {
     return ws_mom(p, frames) + align256((size_t)frames * p->J * sizeof(float2));
@@ -596,8 +595,6 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
         PC_TRY(hipMalloc(&p->pupil, pup.size()));
         PC_TRY(hipMemcpy(p->pupil, pup.data(), pup.size(), hipMemcpyHostToDevice));
         for (int g = 0; g < J; ++g) p->tt_mode[g] = mode[g];
-        for (int g = 0; g < J; ++g)
-            if (mode[g] != 0) p->plane_mask |= 1u << g;
         {
             // closed loop: star g's line of sight through pupil pixel (i, j) crosses output layer l at
             // c^s_l r + theta_g h_l, r = (p0 + i - M/2, p0 + j - M/2) pitch; on the layer grid (spacing
@@ -1486,12 +1483,16 @@ safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, in
     char* base = reinterpret_cast<char*>(ws);
     float2* R = reinterpret_cast<float2*>(base);
     float2* C = reinterpret_cast<float2*>(base + ws_r(p, frames));
-    float* mom = reinterpret_cast<float*>(base + ws_r(p, frames) + ws_c(p, frames));
+    float2* part = reinterpret_cast<float2*>(base + ws_r(p, frames) + ws_c(p, frames));
     float2* planes = reinterpret_cast<float2*>(base + ws_r(p, frames) + ws_c(p, frames) + ws_mom(p, frames));
     RowArgs ra{};
     ra.wf = wf;
     ra.R = R;
-    ra.mom = mom;
+    ra.part = part;
+    for (int i = 0; i < 3; ++i) {
+        ra.tt_b[i] = p->tt_b[i];
+        ra.tt_c[i] = p->tt_c[i];
+    }
     ra.pupil = p->pupil;
     for (int g = 0; g < p->J; ++g) ra.tt_mode[g] = p->tt_mode[g];
     ra.tw = p->tw;
@@ -1503,21 +1504,19 @@ safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, in
         for (int m = 0; m < p->gsize[gi]; ++m) ra.slot[p->gstar[gi][m]] = slot++;
     const int nchunk = (p->n + ra.rows_per_block - 1) / ra.rows_per_block;
     HIP_TRY(launch_rows(p->M, ra, frames, nchunk, p->row_teams, s));
-    if (p->mixed) {                     // split tomography: the planes of every (frame, star), once
+    // split tomography: the passes add the row chunks' plane parts as they read them, or, for more chunks
+    // than their lane groups take, read the sums of one more launch
+    const float2* plane_src = part;
+    int plane_nch = nchunk;
+    if (p->mixed && nchunk > kPlaneLanes) {
         PlaneKArgs pk{};
-        pk.mom = mom;
+        pk.part = part;
         pk.planes = planes;
-        pk.mask = p->plane_mask;
-        for (int i = 0; i < 3; ++i) {
-            pk.tt_b[i] = p->tt_b[i];
-            pk.tt_c[i] = p->tt_c[i];
-        }
-        pk.J = p->J;
         pk.nchunk = nchunk;
         pk.count = frames * p->J;
-        for (int gi = 0, slot = 0; gi < p->ngroups; ++gi)
-            for (int m = 0; m < p->gsize[gi]; ++m) pk.slot[p->gstar[gi][m]] = slot++;
         HIP_TRY(launch_planes(pk, s));
+        plane_src = planes;
+        plane_nch = 1;
     }
     if (ev) HIP_TRY(hipEventRecord(ev[1], s));
 
@@ -1530,7 +1529,8 @@ safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, in
         ca.B = p->B32 + p->boff32[0];
         ca.C = C;
         ca.tw = p->tw;
-        ca.planes = planes;
+        ca.planes = plane_src;
+        ca.plane_nch = plane_nch;
         ca.Xh = p->Xh;
         ca.Yh = p->Yh;
         ca.grp = grp;
@@ -1563,7 +1563,8 @@ safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, in
         ma.lt = p->mf_lt[0];
         ma.ntile = p->mf_ntile[0];
         ma.ppm = p->mf_ppm[0];
-        ma.planes = planes;
+        ma.planes = plane_src;
+        ma.plane_nch = plane_nch;
         ma.Xh = p->Xh;
         ma.Yh = p->Yh;
         ma.n = p->n;
@@ -1580,7 +1581,8 @@ safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, in
     oa.out = out;
     oa.tw = p->tw;
     oa.P = p->P;
-    oa.planes = planes;
+    oa.planes = plane_src;
+    oa.plane_nch = plane_nch;
     oa.nb = p->nb;
     oa.ngs_base = p->gsize[0];
     oa.L = p->L;

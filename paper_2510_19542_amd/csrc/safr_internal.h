@@ -32,7 +32,8 @@ struct GroupArgs {
 struct RowArgs {
     const float* wf;            // [F][J][n][n]
     float2* R;                  // [F][J][Kh][n]
-    float* mom;                 // [F][J][nchunk][4] partial moments (sum v, sum x v, sum y v, 0)
+    float2* part;               // [F][J][nchunk] tip/tilt plane coefficients of each row chunk, group order
+    float tt_b[3], tt_c[3];     // rows 1 and 2 of the inverse normal matrix of the plane fit of [1, x, y]
     const unsigned char* pupil; // [n][n]
     const float2* tw;           // (cos, sin)(2 pi e / M), e < M
     int n, J, p0, rows_per_block;
@@ -81,6 +82,7 @@ struct ColArgs {
     float2* C;                  // see c_index
     const float2* tw;
     const float2* planes;       // tip/tilt plane coefficients per (frame, group slot), see PlaneArgs
+    int plane_nch;              // parts per plane (row chunks, or 1 when already added)
     const float2* Xh;           // DFT2 of x * pupil, [Kh][M]
     const float2* Yh;           // DFT2 of y * pupil, [Kh][M]
     GroupArgs grp;
@@ -104,6 +106,7 @@ struct OutArgs {
     const float2* tw;
     const float* P;             // [L][nb][M][M] natural-star basis images (mixed asterisms)
     const float2* planes;       // tip/tilt plane coefficients per (frame, group slot), see PlaneArgs
+    int plane_nch;              // parts per plane (row chunks, or 1 when already added)
     int ngs_base;               // group slot of the first natural star (the laser group's size)
     int nb;                     // 2 x natural stars (0: no natural-star part)
     int L, J, frames, frames_per_block;
@@ -160,6 +163,7 @@ struct MfmaArgs {
     float2* C;
     const float2* tw;
     const float2* planes;       // tip/tilt plane coefficients per (frame, group slot), see PlaneArgs
+    int plane_nch;              // parts per plane (row chunks, or 1 when already added)
     const float2* Xh;
     const float2* Yh;
     GroupArgs grp;
@@ -182,57 +186,80 @@ struct BasisArgs {
     float* P;                   // [L][2 G][M][M]
 };
 
-// Tip/tilt plane coefficients (b, c) of every (frame, star) of a call, formed once by plane_kernel from the
-// row pass's partial moments and stored in group order: planes[f][slot] (float2), the laser (or only)
-// group's stars in slots 0 .. G0 - 1 and the natural stars of a mixed asterism after them, so a pass reads
-// its group's coefficients without looking up star indices (a dependent load would make it wait for every
-// earlier memory operation).  A pass needing those of `count` pairs, pair i = (frame f0 + i / per, group
-// slot base + i % per), frames at or beyond fend using fend - 1, requests them early with plane_fetch
-// (thread i % blockDim takes pair i, PMAX rounds in registers) and stores them to out[i] (LDS) with
-// plane_put; pairs beyond PMAX rounds are copied there directly.  Every thread of the block calls both
-// with the same arguments.
+// Tip/tilt plane coefficients (b, c) of every (frame, star) of a call (Sec. 3.3: the least-squares plane).
+// The fit is linear in the wavefront, so each block of the row pass writes the coefficients of its own
+// chunk of rows, part[f][slot][chunk] (float2, nch chunks), and a pass needing a plane adds its nch parts.
+// Stars are in group order: the laser (or only) group's stars in slots 0 .. G0 - 1 and the natural stars
+// of a mixed asterism after them, so a pass reads its group's coefficients without looking up star indices
+// (a dependent load would make it wait for every earlier memory operation).  With more than kPlaneLanes
+// chunks, plane_kernel adds them first and the passes read its sums with nch = 1.
+//
+// A pass needing the planes of `count` pairs, pair i = (frame f0 + i / per, group slot base + i % per),
+// frames at or beyond fend using fend - 1, requests them early with plane_fetch (kPlaneLanes consecutive
+// threads per pair, one chunk each, PMAX rounds of blockDim / kPlaneLanes pairs in registers) and adds
+// and stores them to out[i] (LDS) with plane_put (a fixed lane tree: ((p0 + p1) + (p2 + p3)) +
+// ((p4 + p5) + (p6 + p7)), absent parts zero); pairs beyond PMAX rounds are added there directly, in the
+// same order.  Every thread of the block calls both with the same arguments.
+constexpr int kPlaneLanes = 8;
+
 struct PlaneArgs {
-    const float2* planes;
-    int J, per, f0, fend, count, base;
+    const float2* part;
+    int nch, J, per, f0, fend, count, base;
 };
 
-__device__ inline float2 plane_at(const PlaneArgs& p, int i) {
+__device__ inline const float2* plane_src(const PlaneArgs& p, int i) {
     const int f = min(p.f0 + i / p.per, p.fend - 1);
-    return p.planes[(size_t)f * p.J + p.base + i % p.per];
+    return p.part + ((size_t)f * p.J + p.base + i % p.per) * p.nch;
+}
+
+__device__ inline float2 plane_add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+
+__device__ inline float2 plane_at(const PlaneArgs& p, int i) {
+    const float2* src = plane_src(p, i);
+    float2 v[kPlaneLanes];
+#pragma unroll
+    for (int c = 0; c < kPlaneLanes; ++c) v[c] = c < p.nch ? src[c] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int w = 1; w < kPlaneLanes; w *= 2)
+#pragma unroll
+        for (int c = 0; c < kPlaneLanes; c += 2 * w) v[c] = plane_add(v[c], v[c + w]);
+    return v[0];
 }
 
 template <int PMAX>
 __device__ inline void plane_fetch(const PlaneArgs& p, float2 (&v)[PMAX]) {
+    const int c = (int)threadIdx.x % kPlaneLanes, per_round = (int)blockDim.x / kPlaneLanes;
 #pragma unroll
     for (int u = 0; u < PMAX; ++u) {
-        const int i = (int)threadIdx.x + u * (int)blockDim.x;
-        const float2 w = plane_at(p, min(i, p.count - 1));     // always issued (count >= 1): no branch
-        v[u] = i < p.count ? w : make_float2(0.f, 0.f);
+        const int i = (int)threadIdx.x / kPlaneLanes + u * per_round;
+        // always issued (count, nch >= 1): no branch
+        const float2 w = plane_src(p, min(i, p.count - 1))[min(c, p.nch - 1)];
+        v[u] = i < p.count && c < p.nch ? w : make_float2(0.f, 0.f);
     }
 }
 
 template <int PMAX>
 __device__ inline void plane_put(const PlaneArgs& p, const float2 (&v)[PMAX], float2* out) {
+    const int c = (int)threadIdx.x % kPlaneLanes, per_round = (int)blockDim.x / kPlaneLanes;
 #pragma unroll
     for (int u = 0; u < PMAX; ++u) {
-        const int i = (int)threadIdx.x + u * (int)blockDim.x;
-        if (i < p.count) out[i] = v[u];
+        float2 s = v[u];
+#pragma unroll
+        for (int w = 1; w < kPlaneLanes; w *= 2)
+            s = plane_add(s, make_float2(__shfl_xor(s.x, w, 64), __shfl_xor(s.y, w, 64)));
+        const int i = (int)threadIdx.x / kPlaneLanes + u * per_round;
+        if (c == 0 && i < p.count) out[i] = s;
     }
-    for (int i = (int)threadIdx.x + PMAX * (int)blockDim.x; i < p.count; i += blockDim.x) out[i] = plane_at(p, i);
+    for (int i = (int)threadIdx.x + PMAX * per_round; i < p.count; i += blockDim.x) out[i] = plane_at(p, i);
 }
 
-// Plane coefficients of `count` = F x J (frame, star) pairs: the chunk moments summed in chunk order,
-// (b, c) = rows 1 and 2 of the inverse normal matrix of the fit of [1, x, y] times the sums; (0, 0)
-// for stars whose plane is not used.  Star g's coefficients go to group slot slot[g] (see PlaneArgs).
+// More than kPlaneLanes row chunks: the parts of `count` = F x J (frame, slot) pairs added in chunk order
+// into planes[f][slot] (the passes then read them with nch = 1).
 struct PlaneKArgs {
-    const float* mom;           // [F][J][nchunk][4] partial moments (sum v, sum x v, sum y v, 0)
+    const float2* part;         // [F][J][nchunk] in group order
     float2* planes;             // [F][J] in group order
-    unsigned mask;              // bit g: star g's plane is used (J <= 32)
-    float tt_b[3], tt_c[3];
-    int J, nchunk, count;
-    int slot[kMaxJ];            // group slot of star g
+    int nchunk, count;
 };
-static_assert(kMaxJ <= 32, "the plane mask holds one bit per star");
 hipError_t launch_planes(const PlaneKArgs& a, hipStream_t s);
 
 // Lets a kernel use up to the full 160 KiB of LDS of a gfx950 compute unit (once per kernel).

@@ -12,10 +12,12 @@ of IDFT2 is included).  Each is compared with what the oracle's steps give:
   first axis scaled by 1/M^2.
 Tolerance: relative L2 1e-5 per frame and star or layer (FP32 against FP64).
 
-For mixed asterisms the workspace also holds, after the partial moments, the
-tip/tilt plane coefficients (b, c) of every frame and star, planes[f][star]: the
-plane b x + c y they define over the pupil must match the oracle's least-squares
-fit (Sec. 3.3) within 1e-5 of the largest wavefront value.
+For mixed asterisms the workspace also holds, after C, the tip/tilt plane coefficients (b, c) of every
+row chunk of every frame and star, part[f][slot][chunk] (the fit is linear in the data, so each row-pass
+block forms its own rows' share), and, with more than 8 chunks, their sums planes[f][slot] after them: the
+plane b x + c y that the summed parts define over the pupil must match the oracle's least-squares fit
+(Sec. 3.3) within 1e-5 of the largest wavefront value.  The row-pass blocks take 2 x teams rows, so the
+cases cover 1, 5 and 10 chunks at M = 32 and 5 and 9 at M = 256.
 """
 import numpy as np
 import pytest
@@ -52,11 +54,14 @@ def _small_mixed():
 CASES = {"C1": lambda: synth.preset("C1"), "C2": lambda: synth.preset("C2"), "m32-mixed": _small_mixed}
 
 
-@pytest.mark.parametrize("case", list(CASES))
-def test_row_and_column_pass_intermediates(case):
+@pytest.mark.parametrize("case,teams", [("C1", None), ("C2", 8), ("C2", 4), ("m32-mixed", 10), ("m32-mixed", 2),
+                                        ("m32-mixed", 1)])
+def test_row_and_column_pass_intermediates(case, teams):
     torch, S = _mods()
     geo = CASES[case]()
     plan = S.precompute_geometry(geo)
+    if teams is not None:
+        S.safr_set_option(plan, S.SAFR_OPT_ROW_TEAMS, teams)
     ref = O.precompute_geometry(geo)
     F = 2
     wf = synth.frames(geo, F, first=4)
@@ -101,8 +106,14 @@ def test_row_and_column_pass_intermediates(case):
     if not mixed:
         return
     a256 = lambda b: (b + 255) // 256 * 256
-    p_off = a256(r_bytes) + a256(F * L * Kh * M * 8) + a256(F * J * ((n + 1) // 2) * 16)
-    planes = raw[p_off:p_off + F * J * 8].view(np.float32).reshape(F, J, 2)
+    nchunk = -(-n // (2 * teams))
+    m_off = a256(r_bytes) + a256(F * L * Kh * M * 8)
+    part = raw[m_off:m_off + F * J * nchunk * 8].view(np.float32).reshape(F, J, nchunk, 2)
+    planes = part.astype(np.float64).sum(axis=2)
+    if nchunk > 8:                      # summed by one more launch: the passes read those sums
+        p_off = m_off + a256(F * J * ((n + 1) // 2) * 8)
+        sums = raw[p_off:p_off + F * J * 8].view(np.float32).reshape(F, J, 2)
+        assert np.allclose(sums, planes, rtol=1e-5, atol=1e-6 * np.abs(planes).max())
     # stored in group order: the laser stars first, then the natural stars, each in star order
     slot = {g: i for i, g in enumerate([g for grp in ref.groups for g in grp.stars])}
     x = np.arange(n) - (n - 1) / 2.0
@@ -111,7 +122,7 @@ def test_row_and_column_pass_intermediates(case):
         for g in range(J):
             psi = np.where(pupil, wf[f, g].astype(np.float64), 0.0)
             want_p = np.where(pupil, O.tt_plane(psi, pupil), 0.0)
-            b, c = planes[f, slot[g]].astype(np.float64)
+            b, c = planes[f, slot[g]]
             got_p = np.where(pupil, b * X + c * Y, 0.0)
             err = np.max(np.abs(got_p - want_p))
             assert err <= 1e-5 * np.max(np.abs(psi)), (case, f, g, err, np.max(np.abs(psi)))
