@@ -306,7 +306,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
             }
         }
         // tip/tilt plane coefficients of this iteration's frames (used by the apply, after the barrier)
-        if (MODE != 0) plane_put<1>(pa, pl, coef);
+        static_assert(NF * (FIX ? GC : kMaxG) <= 256 / kPlaneLanes, "one round of plane lanes takes every pair");
+        if (MODE != 0) plane_put<1, false>(pa, pl, coef);
         __syncthreads();
 
         // 2. apply: b_l(j) = sum_g B[l][g][j] d_g(j) for the NF frames

@@ -139,10 +139,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OUT_WAVES))
         return PlaneArgs{a.planes, a.plane_nch, a.J, nb / 2, f0, fend, min(NF, fend - f0) * (nb / 2), a.ngs_base};
     };
 
+    // plane lane rounds: every pair in registers unless the basis count is only known at run time
+    constexpr int PR = TAIL || !MIXED ? 1 : (NF * (NB / 2) + 256 / kPlaneLanes - 1) / (256 / kPlaneLanes);
     const float2 twv = tid < M ? a.tw[tid] : make_float2(0.f, 0.f);
     issue(fbeg);
-    float2 pl[1];
-    if constexpr (MIXED) plane_fetch<1>(planes_of(fbeg), pl);
+    float2 pl[PR];
+    if constexpr (MIXED) plane_fetch<PR>(planes_of(fbeg), pl);
     // the block's basis pixels (its rows, every frame): loaded once, before any store
     float4 pv[V4][NBR];
     if constexpr (MIXED) {
@@ -157,7 +159,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OUT_WAVES))
     }
     if (tid < M) tws[tid] = twv;
     stash();
-    if constexpr (MIXED) plane_put<1>(planes_of(fbeg), pl, reinterpret_cast<float2*>(coef));
+    if constexpr (MIXED) plane_put<PR, TAIL>(planes_of(fbeg), pl, reinterpret_cast<float2*>(coef));
     // every load so far (the basis pixels included) complete here, once: the loop body's waits then only
     // count what the body itself issued, and a later iteration's epilogue does not wait for the previous
     // iteration's stores on the basis pixels' account (vmcnt(0); expcnt and lgkmcnt at their maxima)
@@ -208,7 +210,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OUT_WAVES))
         }
         if constexpr (PF) {
             issue(f0 + NF);
-            if constexpr (MIXED) plane_fetch<1>(planes_of(f0 + NF), pl);
+            if constexpr (MIXED) plane_fetch<PR>(planes_of(f0 + NF), pl);
         }
         __syncthreads();                    // rows of every team
 
@@ -264,7 +266,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OUT_WAVES))
         if constexpr (PF) {
             __syncthreads();                // every epilogue done with the regions and the coefficients
             stash();
-            if constexpr (MIXED) plane_put<1>(planes_of(f0 + NF), pl, reinterpret_cast<float2*>(coef));
+            if constexpr (MIXED) plane_put<PR, TAIL>(planes_of(f0 + NF), pl, reinterpret_cast<float2*>(coef));
             __syncthreads();
         }
     };

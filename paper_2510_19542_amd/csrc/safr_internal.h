@@ -232,25 +232,35 @@ __device__ inline void plane_fetch(const PlaneArgs& p, float2 (&v)[PMAX]) {
 #pragma unroll
     for (int u = 0; u < PMAX; ++u) {
         const int i = (int)threadIdx.x / kPlaneLanes + u * per_round;
-        // always issued (count, nch >= 1): no branch
-        const float2 w = plane_src(p, min(i, p.count - 1))[min(c, p.nch - 1)];
-        v[u] = i < p.count && c < p.nch ? w : make_float2(0.f, 0.f);
+        // always issued (count, nch >= 1): no branch; lanes without a part are zeroed in plane_put, so
+        // nothing here waits for the load
+        v[u] = plane_src(p, min(i, p.count - 1))[min(c, p.nch - 1)];
     }
 }
 
-template <int PMAX>
+// the value of another lane of the same row of 16 (data-parallel-primitive lane move, no LDS round trip)
+template <int CTRL>
+__device__ inline float2 plane_dpp(float2 v) {
+    return make_float2(__int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v.x), CTRL, 0xF, 0xF, false)),
+                       __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v.y), CTRL, 0xF, 0xF, false)));
+}
+
+// REM: pairs beyond PMAX rounds may occur (otherwise the caller guarantees count <= PMAX blockDim / 8)
+template <int PMAX, bool REM = true>
 __device__ inline void plane_put(const PlaneArgs& p, const float2 (&v)[PMAX], float2* out) {
+    static_assert(kPlaneLanes == 8, "the lane tree below adds 8 lanes");
     const int c = (int)threadIdx.x % kPlaneLanes, per_round = (int)blockDim.x / kPlaneLanes;
 #pragma unroll
     for (int u = 0; u < PMAX; ++u) {
-        float2 s = v[u];
-#pragma unroll
-        for (int w = 1; w < kPlaneLanes; w *= 2)
-            s = plane_add(s, make_float2(__shfl_xor(s.x, w, 64), __shfl_xor(s.y, w, 64)));
         const int i = (int)threadIdx.x / kPlaneLanes + u * per_round;
+        float2 s = i < p.count && c < p.nch ? v[u] : make_float2(0.f, 0.f);
+        s = plane_add(s, plane_dpp<0xB1>(s));       // lanes 1 0 3 2 of each quad: pairs of parts
+        s = plane_add(s, plane_dpp<0x4E>(s));       // lanes 2 3 0 1: the quad's sum in all its lanes
+        s = plane_add(s, plane_dpp<0x141>(s));      // lane 7 - i of each 8: the other quad's sum
         if (c == 0 && i < p.count) out[i] = s;
     }
-    for (int i = (int)threadIdx.x + PMAX * per_round; i < p.count; i += blockDim.x) out[i] = plane_at(p, i);
+    if constexpr (REM)
+        for (int i = (int)threadIdx.x + PMAX * per_round; i < p.count; i += blockDim.x) out[i] = plane_at(p, i);
 }
 
 // More than kPlaneLanes row chunks: the parts of `count` = F x J (frame, slot) pairs added in chunk order
