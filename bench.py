@@ -193,6 +193,26 @@ def run_c3(S, torch, stream):
     return res
 
 
+def run_col_mfma(S, torch, geo, batches, out, stream, steps):
+    """The batched MORFEO-like launch with the column pass's per-frequency products on the matrix cores
+    (4 x 4 x 1 FP32 products: 4 frames x 4 layers, one star per step) against the vector units, on a plan
+    of its own with the stored launch shapes, each after 200 steps of load (switching synchronises)."""
+    F = int(batches[0].shape[0])
+    plan = S.precompute_geometry(geo)
+    apply_shape(S, plan, TUNED_BATCHED)
+    _attach_workspace(S, torch, plan, F, S.SAFR_FP32)
+    res = {"workload": f"MORFEO-like frames, {F} per call, stored launch shapes"}
+    for name, on in (("matrix_cores", 1), ("vector_units", 0)):
+        S.safr_set_option(plan, S.SAFR_OPT_COL_MFMA, on)
+        for i in range(200):
+            S.safr_reconstruct_batched(plan, F, batches[i % len(batches)], out, S.SAFR_FP32, stream)
+        ms = _timed(lambda: S.safr_reconstruct_batched(plan, F, batches[0], out, S.SAFR_FP32, stream), steps,
+                    stream, torch)
+        st = S.safr_time_stages(plan, F, batches[0], out, S.SAFR_FP32, 20, stream)
+        res[name] = {"us_per_step": round(ms * 1e3, 2), "cols_us": round(st[1] * 1e3, 2)}
+    return res
+
+
 def run_loop(S, torch, plan, geo, pool, calls):
     """One closed loop of the MORFEO-like geometry: POLC, reconstruction and integrator per time step.
 
@@ -562,6 +582,9 @@ def main():
     ap.add_argument("--calibration-copy", action="store_true",
                     help="after timing, copy 256 MiB device to device three times (counter calibration)")
     ap.add_argument("--no-extras", action="store_true", help="skip the 1024-frame, learned-filter and mixed-size runs")
+    ap.add_argument("--col-mfma", action="store_true",
+                    help="the column pass's per-frequency products on the matrix cores (SAFR_OPT_COL_MFMA) in the "
+                         "timed batched step: for counter runs of that variant")
     ap.add_argument("--c4-frames", type=int, default=20000, help="training frames of the learned filter")
     ap.add_argument("--only-c3", action="store_true",
                     help="only the 1024-frame FP32 and BF16x3 (matrix-core) runs, printed as one JSON line")
@@ -608,6 +631,8 @@ def main():
         tuned, tuned1 = TUNED_BATCHED, TUNED_SINGLE
         apply_shape(S, plan, tuned)
         apply_shape(S, plan1, tuned1)
+    if args.col_mfma:
+        S.safr_set_option(plan, S.SAFR_OPT_COL_MFMA, 1)
     # distinct input buffers (the two synthetic batches, then sign-flipped copies in their own memory), so
     # that a step's inputs were last read several steps earlier
     batches = [pool[:F], pool[F:]]
@@ -654,6 +679,9 @@ def main():
             result["c3_batched_1024"] = run_c3(S, torch, gstream)
             print("bench: mixed-size bundle", file=sys.stderr, flush=True)
             result["c5_mixed_sizes"] = run_c5(S, torch, gstream, params)
+        if not args.col_mfma:
+            print("bench: column apply on the matrix cores", file=sys.stderr, flush=True)
+            result["column_apply_on_matrix_cores"] = run_col_mfma(S, torch, geo, batches, out, stream, args.steps)
 
     # headline: each step reconstructs F frames in one batched call
     print(f"bench: batched step, {F} frames per call, {args.warmup} warm-up + {args.steps} timed steps",
@@ -681,7 +709,8 @@ def main():
             t1.record(stream)
             torch.cuda.synchronize()
             reruns.append(round(F * 1000.0 / (t0.elapsed_time(t1) / args.steps), 1))
-    # per-kernel durations of the batched call (HIP events on the launch stream, inside the library)
+    # per-kernel durations of the batched call (HIP events on the launch stream, inside the library, around 20
+    # back-to-back launches of each stage's kernel)
     stage_ms = S.safr_time_stages(plan, F, batches[0], out, S.SAFR_FP32, 20, stream)
     # the launch is deterministic: the first batch again gives the layers the oracle leg checks
     S.safr_reconstruct_batched(plan, F, batches[0], out, S.SAFR_FP32, stream)
@@ -728,7 +757,8 @@ def main():
         roof = {"bound": "alu", "achieved": round(dom_tfl, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(dom_tfl / FP32_PEAK_TFLOPS, 4)}
     roof.update({"traffic": measured_traffic(F, dk), "kernel": KERNEL_NAMES[dk], "kernel_ms": round(stage_ms[dom], 6),
-                 "duration_source": "HIP events around the kernel on its launch stream, mean of 20 launches",
+                 "duration_source": "HIP events on the launch stream around 20 back-to-back launches of the "
+                                    "stage's kernel (after one full call), mean per launch",
                  "alg_bytes_per_launch": ab["per_kernel"][dk], "alg_flops_per_launch": af["per_kernel"][dk],
                  "hbm_frac": round(dom_gbs / HBM_PEAK_GBS, 4), "alu_frac": round(dom_tfl / FP32_PEAK_TFLOPS, 4),
                  "GBs_with_intermediates": round(ab["with_intermediates"][dk] / dsec / 1e9, 1),
@@ -754,8 +784,9 @@ def main():
                    "frames_per_step": F, "input_batches_cycled": len(batches), "J": geo.J, "L": geo.L, "M": geo.M,
                    "n": geo.n,
                    "launch_shapes": {"batched": list(tuned), "single": list(tuned1), "autotuned_now": args.autotune},
-                   "leg_order": "single-frame, closed loop, refresh, Strehl loop, C4, C3, C5, then the headline "
-                                "(warm-up, timed steps, reruns, stage timing), then the CPU oracle"},
+                   "leg_order": "single-frame, closed loop, refresh, Strehl loop, C4, C3, C5, matrix-core apply, "
+                                "then the headline (warm-up, timed steps, reruns, stage timing, determinism "
+                                "check), then the CPU oracle"},
         "roofline": roof,
         "stage_ms": {k: round(v, 6) for k, v in zip(names, stage_ms)},
         "reruns_frames_per_s": {"runs": reruns, "median": float(np.median(reruns)) if reruns else None},

@@ -275,11 +275,13 @@ typedef struct {
 } safr_deadline_info;
 safr_status safr_deadline_stats(safr_plan* p, safr_deadline_info* out, int reset, hipStream_t stream);
 
-/* Measures the three stages of the hard-real-time step (row pass, with the small
- * kernel that forms the tip/tilt planes of a mixed asterism; column pass with the
- * apply; output pass) with HIP events recorded on `stream` around each, over
- * `iters` synchronised repetitions of a batched call; writes the average
- * milliseconds of each to ms[0..2].  Same buffers and workspace rules as
+/* Measures the three stages of the hard-real-time step (row pass; column pass with the
+ * apply; output pass): after one batched call, which leaves every stage's inputs in
+ * the workspace, each stage's kernels are launched `iters` times back to back on
+ * `stream` between two HIP events; writes the average milliseconds per launch of
+ * each to ms[0..2] (a kernel's duration plus the dispatch gap between back-to-back
+ * launches), and synchronises `stream` once at the end.  `layers` holds the
+ * batched call's result afterwards.  Same buffers and workspace rules as
  * safr_reconstruct_batched. */
 safr_status safr_time_stages(safr_plan* p, int frames, const float* wavefronts, float* layers,
                              int precision, int iters, hipStream_t stream, double* ms);

@@ -263,9 +263,11 @@ void tt_transforms(const std::vector<unsigned char>& pup, int n, int M, int p0, 
         }
 }
 
+// stage >= 0: only that stage's launches (0 row pass, 1 column pass, 2 output pass), on the inputs an earlier
+// full sequence left in the workspace
 safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, int precision,
                        void* ws, hipStream_t s, hipEvent_t* ev = nullptr, const float* prev = nullptr,
-                       float gain = 1.f);
+                       float gain = 1.f, int stage = -1);
 
 // per-frequency alpha multipliers: finite, >= 0 and point-symmetric (B must stay Hermitian)
 safr_status check_alpha_weight(int M, const double* w) {
@@ -1108,27 +1110,25 @@ safr_status safr_time_stages(safr_plan* p, int frames, const float* wf, float* o
     if (p->ws_user && p->ws_user_bytes >= need) ws = p->ws_user;
     else if (p->ws_own_bytes >= need) ws = p->ws_own;
     else return fail(SAFR_ERR_STATE, "workspace of %zu bytes needed for %d frames", need, frames);
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // one full sequence leaves every stage's inputs in the workspace; then each stage's launches run `iters`
+    // times back to back between two events (no host synchronisation until the end)
+    hipEvent_t ev[6] = {};
     for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
-    double acc[3] = {0, 0, 0};
-    safr_status st = SAFR_OK;
-    for (int it = 0; it < iters && st == SAFR_OK; ++it) {
-        st = launch_all(p, frames, wf, out, precision, ws, s, ev);
-        if (st != SAFR_OK) break;
-        if (hipEventSynchronize(ev[3]) != hipSuccess) {
-            st = fail(SAFR_ERR_DEVICE, "event synchronisation failed");
-            break;
-        }
-        for (int k = 0; k < 3 && st == SAFR_OK; ++k) {
-            float t = 0.f;
-            if (hipEventElapsedTime(&t, ev[k], ev[k + 1]) != hipSuccess) st = fail(SAFR_ERR_DEVICE, "event timing failed");
-            acc[k] += t;
-        }
+    safr_status st = launch_all(p, frames, wf, out, precision, ws, s);
+    for (int k = 0; k < 3 && st == SAFR_OK; ++k) {
+        if (hipEventRecord(ev[2 * k], s) != hipSuccess) st = fail(SAFR_ERR_DEVICE, "event record failed");
+        for (int it = 0; it < iters && st == SAFR_OK; ++it)
+            st = launch_all(p, frames, wf, out, precision, ws, s, nullptr, nullptr, 1.f, k);
+        if (st == SAFR_OK && hipEventRecord(ev[2 * k + 1], s) != hipSuccess) st = fail(SAFR_ERR_DEVICE, "event record failed");
+    }
+    if (st == SAFR_OK && hipEventSynchronize(ev[5]) != hipSuccess) st = fail(SAFR_ERR_DEVICE, "event synchronisation failed");
+    for (int k = 0; k < 3 && st == SAFR_OK; ++k) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, ev[2 * k], ev[2 * k + 1]) != hipSuccess) st = fail(SAFR_ERR_DEVICE, "event timing failed");
+        ms[k] = (double)t / iters;
     }
     for (auto& e : ev) (void)hipEventDestroy(e);
-    if (st != SAFR_OK) return st;
-    for (int k = 0; k < 3; ++k) ms[k] = acc[k] / iters;
-    return SAFR_OK;
+    return st;
 }
 
 namespace {
@@ -1478,7 +1478,8 @@ safr_status safr_set_option(safr_plan* p, int option, int value) {
 namespace {
 
 safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, int precision, void* ws,
-                       hipStream_t s, hipEvent_t* ev, const float* prev, float gain) {
+                       hipStream_t s, hipEvent_t* ev, const float* prev, float gain, int stage) {
+    const bool do_rows = stage < 0 || stage == 0, do_cols = stage < 0 || stage == 1, do_out = stage < 0 || stage == 2;
     if (ev) HIP_TRY(hipEventRecord(ev[0], s));
     char* base = reinterpret_cast<char*>(ws);
     float2* R = reinterpret_cast<float2*>(base);
@@ -1503,7 +1504,7 @@ safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, in
     for (int gi = 0, slot = 0; gi < p->ngroups; ++gi)
         for (int m = 0; m < p->gsize[gi]; ++m) ra.slot[p->gstar[gi][m]] = slot++;
     const int nchunk = (p->n + ra.rows_per_block - 1) / ra.rows_per_block;
-    HIP_TRY(launch_rows(p->M, ra, frames, nchunk, p->row_teams, s));
+    if (do_rows) HIP_TRY(launch_rows(p->M, ra, frames, nchunk, p->row_teams, s));
     // split tomography: the passes add the row chunks' plane parts as they read them, or, for more chunks
     // than their lane groups take, read the sums of one more launch
     const float2* plane_src = part;
@@ -1514,7 +1515,7 @@ safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, in
         pk.planes = planes;
         pk.nchunk = nchunk;
         pk.count = frames * p->J;
-        HIP_TRY(launch_planes(pk, s));
+        if (do_rows) HIP_TRY(launch_planes(pk, s));
         plane_src = planes;
         plane_nch = 1;
     }
@@ -1552,7 +1553,7 @@ safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, in
         ca.frames_per_block = std::max(1, std::min(fpb, frames));
         ca.prefetch = p->col_prefetch;
         ca.Bm = p->col_mfma ? p->Bm : nullptr;
-        HIP_TRY(launch_cols(p->M, ca, nf, frames, s));
+        if (do_cols) HIP_TRY(launch_cols(p->M, ca, nf, frames, s));
     } else {
         MfmaArgs ma{};
         ma.R = R;
@@ -1572,7 +1573,7 @@ safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, in
         ma.L = p->L;
         ma.p0 = p->p0;
         ma.frames = frames;
-        HIP_TRY(launch_cols_mfma(p->M, ma, frames, p->mfma_frames, s));
+        if (do_cols) HIP_TRY(launch_cols_mfma(p->M, ma, frames, p->mfma_frames, s));
     }
     if (ev) HIP_TRY(hipEventRecord(ev[2], s));
 
@@ -1591,7 +1592,7 @@ safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, in
     oa.frames_per_block = std::max(1, p->out_frames);
     oa.prev = prev;
     oa.gain = gain;
-    HIP_TRY(launch_out(p->M, oa, p->out_rows, frames, s));
+    if (do_out) HIP_TRY(launch_out(p->M, oa, p->out_rows, frames, s));
     if (ev) HIP_TRY(hipEventRecord(ev[3], s));
     return SAFR_OK;
 }

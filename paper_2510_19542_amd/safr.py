@@ -261,7 +261,8 @@ def safr_set_option(plan: Plan, option: int, value: int):
 
 def safr_time_stages(plan: Plan, frames: int, wavefronts, layers, precision: int = SAFR_FP32, iters: int = 20,
                      stream=None):
-    """Average milliseconds of (row pass, column pass + apply, output pass), HIP events on the launch stream."""
+    """Milliseconds per launch of (row pass, column pass + apply, output pass): one batched call, then each
+    stage's kernels `iters` times back to back between HIP events on the launch stream."""
     ms = (ctypes.c_double * 3)()
     _check(lib().safr_time_stages(plan._as_parameter_, int(frames), _ptr(wavefronts), _ptr(layers), int(precision),
                                   int(iters), _stream(stream), ms))

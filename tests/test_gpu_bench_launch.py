@@ -148,3 +148,26 @@ def test_c5_big_tikhonov_32_frames_matches_oracle():
         err = rel_l2(got[f], O.reconstruct(ref, wf[f].astype(np.float64)))
         print(f"C5-Big Tikhonov, 32 frames, frame {f}: rel-L2 {err:.3e}")
         assert err <= 1e-5, (f, err)
+
+
+def test_stage_timing_leaves_the_batched_result(c2_bench_run):
+    """safr_time_stages runs one batched call and then each stage's kernels back to back on the inputs that
+    call left in the workspace: every stage time is positive and the layers are the batched call's, bit
+    for bit."""
+    torch = _torch()
+    S = _lib()
+    geo, _, plan, x, got = c2_bench_run
+    F = int(x.shape[0])
+    need = S.safr_workspace_size(plan, F)
+    ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+    S.safr_set_workspace(plan, (ws.data_ptr() + 255) & ~255, need)
+    out = torch.full((F, geo.L, geo.M, geo.M), float("nan"), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.Stream()
+    try:
+        ms = S.safr_time_stages(plan, F, x, out, S.SAFR_FP32, 5, stream)
+        stream.synchronize()
+        print("stage ms:", ms)
+        assert len(ms) == 3 and all(0.0 < t < 10.0 for t in ms)
+        assert np.array_equal(out.cpu().numpy(), got)
+    finally:
+        S.safr_set_workspace(plan, 0, 0)
