@@ -95,6 +95,10 @@ CASES = {
     "m128-mixed-L4": lambda: _small(128, 45, (1, 1, 1, 0, 0), L=4, seed=10, obstruction=0.1),
     "m64-lgs-beta0": lambda: _small(64, 31, (1, 1, 1), L=3, seed=12, beta=0.0),
     "m32-mixed-beta2.5": lambda: _small(32, 19, (1, 1, 1, 0, 0), L=3, seed=13, beta=2.5),
+    # the largest asterism and layer count the library takes: 16 stars per group, 16 layers (generic kernels;
+    # 32 natural-star basis images, more than the output pass holds in registers)
+    "m32-max-16lgs-16ngs-L16": lambda: _small(32, 17, (1,) * 16 + (0,) * 16, L=16, seed=21),
+    "m64-max-16lgs-L16": lambda: _small(64, 33, (1,) * 16, L=16, seed=22),
 }
 
 
