@@ -163,7 +163,7 @@ safr_status safr_reconstruct(safr_plan* p, const float* wavefronts, float* layer
                              hipStream_t stream);
 
 /*
- * Batched reconstruction of `frames` independent frames (SAFR_BF16X3: plans with
+ * Batched reconstruction of `frames` independent frames (1..65535, else SAFR_ERR_ARG; SAFR_BF16X3: plans with
  * M <= 128 only, otherwise SAFR_ERR_UNSUPPORTED): wavefronts
  * [frames][J][n][n] -> layers [frames][L][M][M].  precision SAFR_FP32 applies B
  * in FP32; SAFR_BF16X3 applies it on BF16 matrix cores with FP32 accumulation
@@ -191,7 +191,7 @@ safr_status safr_reconstruct_batched_static(safr_plan* p, int frames, const floa
                                             int precision, hipStream_t stream);
 size_t safr_static_workspace_bytes(void);
 
-/* Device workspace bytes needed for `frames` frames. */
+/* Device workspace bytes needed for `frames` frames (1..65535). */
 safr_status safr_workspace_size(const safr_plan* p, int frames, int precision, size_t* bytes);
 
 /* Binds caller-owned device memory (>= 256-byte aligned) as the workspace

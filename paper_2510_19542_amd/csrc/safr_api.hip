@@ -130,6 +130,9 @@ struct safr_plan {
 
 namespace {
 
+// frames of one call: the row pass's grid has one z index per frame
+constexpr int kMaxFrames = 65535;
+
 // workspace: row spectra R, layer column spectra C, plane parts of the row chunks (sized for the smallest row blocks)
 size_t ws_r(const safr_plan* p, int frames) { return align256((size_t)frames * p->J * p->Kh * p->n * sizeof(float2)); }
 size_t ws_c(const safr_plan* p, int frames) {
@@ -718,7 +721,7 @@ safr_status safr_precompute(const safr_geometry* geo, int L, const double* heigh
 
 safr_status safr_workspace_size(const safr_plan* p, int frames, int precision, size_t* bytes) {
     if (!p || !bytes) return fail(SAFR_ERR_ARG, "NULL argument");
-    if (frames < 1) return fail(SAFR_ERR_ARG, "frames must be >= 1");
+    if (frames < 1 || frames > kMaxFrames) return fail(SAFR_ERR_ARG, "frames must be in 1..%d", kMaxFrames);
     if (precision != SAFR_FP32 && precision != SAFR_BF16X3) return fail(SAFR_ERR_ARG, "bad precision");
     *bytes = ws_bytes(p, frames);
     return SAFR_OK;
@@ -895,7 +898,7 @@ safr_status safr_update_alpha(safr_plan* p, double alpha, double alpha_tt, int f
 safr_status safr_reconstruct_batched(safr_plan* p, int frames, const float* wf, float* out, int precision,
                                      hipStream_t s) {
     if (!p || !wf || !out) return fail(SAFR_ERR_ARG, "NULL argument");
-    if (frames < 1) return fail(SAFR_ERR_ARG, "frames must be >= 1");
+    if (frames < 1 || frames > kMaxFrames) return fail(SAFR_ERR_ARG, "frames must be in 1..%d", kMaxFrames);
     if (precision != SAFR_FP32 && precision != SAFR_BF16X3) return fail(SAFR_ERR_ARG, "bad precision");
     if (precision == SAFR_BF16X3 && !p->Apack)
         return fail(SAFR_ERR_UNSUPPORTED, "BF16 path not available for this plan");
@@ -983,7 +986,7 @@ size_t safr_static_workspace_bytes(void) { return kStaticScratchBytes; }
 safr_status safr_reconstruct_batched_static(safr_plan* p, int frames, const float* wf, float* out, int precision,
                                             hipStream_t s) {
     if (!p || !wf || !out) return fail(SAFR_ERR_ARG, "NULL argument");
-    if (frames < 1) return fail(SAFR_ERR_ARG, "frames must be >= 1");
+    if (frames < 1 || frames > kMaxFrames) return fail(SAFR_ERR_ARG, "frames must be in 1..%d", kMaxFrames);
     if (precision != SAFR_FP32 && precision != SAFR_BF16X3) return fail(SAFR_ERR_ARG, "bad precision");
     if (precision == SAFR_BF16X3 && !p->Apack)
         return fail(SAFR_ERR_UNSUPPORTED, "BF16 path not available for this plan");
@@ -1003,7 +1006,7 @@ safr_status safr_reconstruct_batched_static(safr_plan* p, int frames, const floa
 safr_status safr_polc(safr_plan* p, int frames, const float* wf, const float* layers, float weight, float* out,
                       hipStream_t s) {
     if (!p || !wf || !layers || !out) return fail(SAFR_ERR_ARG, "NULL argument");
-    if (frames < 1 || frames > 65535) return fail(SAFR_ERR_ARG, "frames must be in 1..65535");
+    if (frames < 1 || frames > kMaxFrames) return fail(SAFR_ERR_ARG, "frames must be in 1..%d", kMaxFrames);
     if (!std::isfinite(weight)) return fail(SAFR_ERR_ARG, "weight must be finite");
     HIP_TRY(launch_polc(polc_args(p, wf, layers, weight, out), frames, s));
     return SAFR_OK;
@@ -1012,7 +1015,7 @@ safr_status safr_polc(safr_plan* p, int frames, const float* wf, const float* la
 safr_status safr_strehl(safr_plan* p, int frames, int D, const double* dirs, const float* open_loop,
                         const float* layers, float scale, float* sr, float* var, hipStream_t s) {
     if (!p || !dirs || !open_loop || !layers || !sr) return fail(SAFR_ERR_ARG, "NULL argument");
-    if (frames < 1 || frames > 65535) return fail(SAFR_ERR_ARG, "frames must be in 1..65535");
+    if (frames < 1 || frames > kMaxFrames) return fail(SAFR_ERR_ARG, "frames must be in 1..%d", kMaxFrames);
     if (D < 1 || D > kMaxDirs) return fail(SAFR_ERR_ARG, "directions must be in 1..%d", kMaxDirs);
     if (!std::isfinite(scale)) return fail(SAFR_ERR_ARG, "scale must be finite");
     StrehlArgs a{};
@@ -1055,7 +1058,7 @@ safr_status safr_strehl(safr_plan* p, int frames, int D, const double* dirs, con
 safr_status safr_loop_step(safr_plan* p, int frames, const float* wf, const float* a_in, float gain, float* a_out,
                            hipStream_t s) {
     if (!p || !wf || !a_in || !a_out) return fail(SAFR_ERR_ARG, "NULL argument");
-    if (frames < 1 || frames > 65535) return fail(SAFR_ERR_ARG, "frames must be in 1..65535");
+    if (frames < 1 || frames > kMaxFrames) return fail(SAFR_ERR_ARG, "frames must be in 1..%d", kMaxFrames);
     if (!std::isfinite(gain)) return fail(SAFR_ERR_ARG, "gain must be finite");
     const size_t need = ws_bytes(p, frames);
     void* ws = nullptr;
@@ -1102,6 +1105,7 @@ safr_status safr_loop_step(safr_plan* p, int frames, const float* wf, const floa
 
 safr_status safr_time_stages(safr_plan* p, int frames, const float* wf, float* out, int precision, int iters,
                              hipStream_t s, double* ms) {
+    if (frames < 1 || frames > kMaxFrames) return fail(SAFR_ERR_ARG, "frames must be in 1..%d", kMaxFrames);
     if (!p || !wf || !out || !ms || iters < 1) return fail(SAFR_ERR_ARG, "bad argument");
     if (precision != SAFR_FP32 && precision != SAFR_BF16X3) return fail(SAFR_ERR_ARG, "bad precision");
     if (precision == SAFR_BF16X3 && !p->Apack) return fail(SAFR_ERR_UNSUPPORTED, "BF16 path not available");
@@ -1154,6 +1158,7 @@ safr_status time_stage(safr_plan* p, int frames, const float* wf, float* out, in
 safr_status safr_autotune(safr_plan* p, int frames, const float* wf, float* out, int precision, int iters,
                           hipStream_t s, int* choice) {
     if (!p || !wf || !out || iters < 1) return fail(SAFR_ERR_ARG, "bad argument");
+    if (frames < 1 || frames > kMaxFrames) return fail(SAFR_ERR_ARG, "frames must be in 1..%d", kMaxFrames);
     if (precision != SAFR_FP32 && precision != SAFR_BF16X3) return fail(SAFR_ERR_ARG, "bad precision");
     if (precision == SAFR_BF16X3 && !p->Apack) return fail(SAFR_ERR_UNSUPPORTED, "BF16 path not available");
     const size_t need = ws_bytes(p, frames);
@@ -1306,7 +1311,8 @@ safr_status safr_multi_create(safr_plan* const* plans, const int* frames, int co
     if (!plans || !frames || count < 1) return fail(SAFR_ERR_ARG, "need at least one plan");
     if (precision != SAFR_FP32 && precision != SAFR_BF16X3) return fail(SAFR_ERR_ARG, "bad precision");
     for (int i = 0; i < count; ++i) {
-        if (!plans[i] || frames[i] < 1) return fail(SAFR_ERR_ARG, "entry %d: bad plan or frame count", i);
+        if (!plans[i] || frames[i] < 1 || frames[i] > kMaxFrames)
+            return fail(SAFR_ERR_ARG, "entry %d: bad plan or frame count", i);
         if (precision == SAFR_BF16X3 && !plans[i]->Apack)
             return fail(SAFR_ERR_UNSUPPORTED, "entry %d: BF16 path not available for its plan", i);
     }

@@ -63,3 +63,32 @@ def test_more_than_one_gpu_is_refused_before_any_device_work():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_metapupil_masks():
+    """The learned filter's pupil-masked metric counts each layer's metapupil: the union over guide stars of
+    the aperture's footprint at the layer's height (Sec. 2: star g sees layer l through c_g r + theta_g h_l)."""
+    import numpy as np
+    import synth
+    geo = synth.preset("C1")
+    masks = bench.metapupil_masks(geo)
+    pupil = geo.pupil().astype(bool)
+    M, n = geo.M, geo.n
+    p0 = (M - n + 1) // 2
+    # ground layer: every footprint is the pupil itself, placed like the zero extension
+    ground = np.zeros((M, M), dtype=bool)
+    ground[p0:p0 + n, p0:p0 + n] = pupil
+    assert np.array_equal(masks[0], ground)
+    # one star on axis: the metapupil is the pupil at every height
+    on_axis = geo.replace(stars=[(0.0, 0.0, 0)])
+    for m in bench.metapupil_masks(on_axis):
+        assert np.array_equal(m, ground)
+    # stars whose lines of sight shift the footprint by whole pixels at 6 km: the union of the shifted pupils
+    t = geo.pitch / geo.heights[1]                          # one pixel at the second layer
+    stars = [(3 * t, 0.0, 0), (0.0, -5 * t, 0), (-2 * t, 4 * t, 0)]
+    masks = bench.metapupil_masks(geo.replace(stars=stars))
+    want = np.zeros((M, M), dtype=bool)
+    for sx, sy, _ in stars:
+        want |= np.roll(np.roll(ground, int(round(sx / t)), axis=0), int(round(sy / t)), axis=1)
+    assert np.array_equal(masks[0], ground)
+    assert np.array_equal(masks[1], want)

@@ -363,6 +363,27 @@ def test_workspace_too_small_is_an_error():
     assert e.value.status == S.SAFR_ERR_STATE
 
 
+@pytest.mark.parametrize("frames", [0, -3, 65536])
+def test_frame_counts_outside_1_to_65535_are_rejected(frames):
+    """An empty or negative batch, or more frames than the row pass's grid takes, is an argument error
+    before anything is launched (the output stays as it was)."""
+    torch = _torch()
+    S = _lib()
+    geo = _geo("C1")
+    plan = S.precompute_geometry(geo)
+    wf = torch.zeros((1, geo.J, geo.n, geo.n), device="cuda")
+    out = torch.full((1, geo.L, geo.M, geo.M), 7.0, device="cuda")
+    for call in (lambda: S.safr_workspace_size(plan, frames),
+                 lambda: S.safr_reconstruct_batched(plan, frames, wf, out),
+                 lambda: S.safr_reconstruct_batched_static(plan, frames, wf, out),
+                 lambda: S.safr_time_stages(plan, frames, wf, out)):
+        with pytest.raises(S.SafrError) as e:
+            call()
+        assert e.value.status == S.SAFR_ERR_ARG, frames
+    torch.cuda.synchronize()
+    assert bool((out == 7.0).all())
+
+
 def test_autotune_picks_valid_shapes_and_keeps_results():
     torch = _torch()
     S = _lib()
