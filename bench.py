@@ -455,7 +455,79 @@ def run_c4(S, torch, stream, frames):
                     lambda: S.safr_reconstruct_batched(p, F, x, out, S.SAFR_FP32, stream), 20, stream, torch), 1)
     res["frames_per_s"] = speed
     res["training_objective"] = c4_objective_bound(torch, geo, params, etas, alphas[1:])
+    res["heldout_metapupil"] = c4_metapupil(S, torch, stream, base, params, etas, alphas[1:])
     return res, params
+
+
+def metapupil_masks(geo):
+    """(L, M, M) bool: the pixels of each output layer's grid that some guide star's line of sight through
+    the aperture crosses (the union over stars of the aperture footprint at that height; layer l's grid has
+    spacing c_l pitch, centred at index M / 2)."""
+    import numpy as np
+    M, p = geo.M, geo.pitch
+    has_lgs = any(int(s[2]) == 1 for s in geo.stars)
+    idx = (np.arange(M) - M / 2.0) * p
+    out = np.zeros((len(geo.heights), M, M), dtype=bool)
+    r_out, r_in = geo.diameter / 2.0, geo.obstruction * geo.diameter / 2.0
+    for l, h in enumerate(geo.heights):
+        c_l = (1.0 - h / geo.h_lgs) if has_lgs else 1.0
+        X, Y = np.meshgrid(c_l * idx, c_l * idx, indexing="ij")
+        for ax, ay, kind in geo.stars:
+            c_g = (1.0 - h / geo.h_lgs) if int(kind) == 1 else 1.0
+            # the pupil point r maps to c_g r + theta h on the layer
+            rx, ry = (X - ax * h) / c_g, (Y - ay * h) / c_g
+            rr = np.hypot(rx, ry)
+            out[l] |= (rr <= r_out) & (rr >= r_in)
+    return out
+
+
+def c4_metapupil(S, torch, stream, geo, params, etas, alphas, count=250):
+    """The learned filter (trained on periodic whole-grid data) and best-tuned Tikhonov on pupil-masked frames of
+    the 8 m geometry: bilinear line-of-sight wavefronts of frozen von Karman screens with white noise, held-out
+    frames 20000.., the relative layer residual over each layer's metapupil after per-layer piston removal
+    (mean over frames)."""
+    import numpy as np
+    import synth
+    masks = torch.from_numpy(metapupil_masks(geo)).cuda()
+    ids = range(20000, 20000 + count)
+    screens = [synth.truth_screens(geo, f) for f in ids]
+    truth = torch.from_numpy(np.stack([synth.truth_layers(geo, sc, f) for sc, f in zip(screens, ids)])
+                             .astype(np.float32)).cuda()
+    F = count
+    out = torch.empty((F, geo.L, geo.M, geo.M), device="cuda")
+    m = masks[None].float()
+    cnt = m.sum(dim=(2, 3), keepdim=True)
+
+    def err():
+        r = (out - truth) * m
+        r = (r - r.sum(dim=(2, 3), keepdim=True) / cnt) * m
+        t = truth * m
+        t = (t - t.sum(dim=(2, 3), keepdim=True) / cnt) * m
+        num = torch.linalg.vector_norm(r.flatten(1), dim=1)
+        den = torch.linalg.vector_norm(t.flatten(1), dim=1)
+        return float((num / den).mean())
+
+    tik = S.precompute_geometry(geo)
+    _attach_workspace(S, torch, tik, F, S.SAFR_FP32)
+    res = {"workload": f"C1 geometry with its pupil (n=33, M=64), {count} held-out frames: bilinear line-of-sight "
+                       "wavefronts of von Karman screens with white noise; layer residual over each layer's "
+                       "metapupil after per-layer piston removal; the network trained on periodic whole-grid data"}
+    for eta in etas:
+        x = torch.from_numpy(np.stack([synth.simulate_wavefronts(geo, sc, f, eta=eta) for sc, f in zip(screens, ids)])
+                             .astype(np.float32)).cuda()
+        lrn = S.precompute_geometry(geo, filter=S.SAFR_FILTER_MLP, mlp=params, noise=eta)
+        _attach_workspace(S, torch, lrn, F, S.SAFR_FP32)
+        S.safr_reconstruct_batched(lrn, F, x, out, S.SAFR_FP32, stream)
+        e_l = err()
+        errs = []
+        for a in alphas:
+            S.safr_update_alpha(tik, a, a)
+            S.safr_reconstruct_batched(tik, F, x, out, S.SAFR_FP32, stream)
+            errs.append(err())
+        b = int(np.argmin(errs))
+        res[str(eta)] = {"learned": round(e_l, 5), "tikhonov_best": round(errs[b], 5), "best_alpha": float(f"{alphas[b]:.3g}"),
+                         "tikhonov_alpha_0.001": round(errs[int(np.argmin(np.abs(np.log(np.asarray(alphas) / 1e-3))))], 5)}
+    return res
 
 
 def c4_objective_bound(torch, geo, params, etas, alphas, count=1000):
