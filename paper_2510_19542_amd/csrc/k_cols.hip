@@ -108,7 +108,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
     extern __shared__ float2 smem[];
     float2* tws = smem;                                        // [M]
     float2* slots = smem + M;                                  // [CPW][NF][SPF][TL]
-    float2* coef = slots + (size_t)CPW * NF * SPF * TL;        // [NF][G]
+    // the matrix-core apply reads and writes one slot of each of the 4 frames per instruction: frames are
+    // padded to 8 float2 past a multiple of 32 apart, so the 4 frames' 8-pair runs of a half wavefront fall
+    // in distinct banks
+    constexpr int FPAD = MF ? (8 - ((GC > LC ? GC : LC) * TL) % 32 + 32) % 32 : 0;
+    const int FSTR = SPF * TL + FPAD;                           // float2 per (column, frame)
+    float2* coef = slots + (size_t)CPW * NF * FSTR;            // [NF][G]
 
     // columns k < M/2 only: B vanishes on the Nyquist column k = M/2, so its layer spectra are zero and
     // the output pass takes them as such without reading C there
@@ -130,7 +135,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
     const int tid = threadIdx.x, team = tid / T, t = tid % T;
     const int c = tid / M, j = tid % M;                        // apply: column in block, frequency
     const int k = kb * CPW + c;                                // < KC: blocks past the work left above
-    auto slot = [&](int cc, int f, int s) { return slots + ((size_t)(cc * NF + f) * SPF + s) * TL; };
+    auto slot = [&](int cc, int f, int s) { return slots + (size_t)(cc * NF + f) * FSTR + (size_t)s * TL; };
 
     // forward tasks: (column, frame, star); rounds of NTEAM teams
     const int ftasks = CPW * NF * G;
@@ -198,63 +203,97 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
     // complex product is four real ones: Re b += Re d Re B - Im d Im B, Im b += Im d Re B + Re d Im B.  Each
     // wavefront takes 4 groups of 16 pairs (its 64 pairs): it reads the d of all frames and stars of a group
     // into registers, then writes the group's b into the layer slots (in place: only its own pairs).
+    // B streamed in steps s = (group q, star g) of MLBK float2 per lane (its layer blocks), MPF steps ahead
+    constexpr int MLBK = MF ? (LC + 3) / 4 : 1;                // layer blocks of 4 (padded with zero B)
+    // (MPF + 1 divides the steps of a group, so the buffer of each step is known at compile time with the
+    // group loop kept rolled)
+    constexpr int MPF = (MF ? GC : 1) % 3 == 0 ? 2 : 1, MSTEPS = 4 * (MF ? GC : 1);
+    [[maybe_unused]] float2 mb[MPF + 1][MLBK];
+    [[maybe_unused]] float2 mxy[2][2];                         // Xh, Yh of the lane's pair for groups q, q + 1
+    [[maybe_unused]] auto mfma_bload = [&](int step, float2 (&dst)[MLBK]) {
+        if constexpr (MF) {
+            const int q = step / GC, g = step % GC;
+            const int wave = tid >> 6, lane = tid & 63;
+            const __amdgpu_buffer_rsrc_t bmr =
+                block_rsrc(a.Bm + (size_t)kb * 16 * MLBK * GC * 64, (unsigned)(16 * MLBK * GC * 64 * 8));
+#pragma unroll
+            for (int lb = 0; lb < MLBK; ++lb)
+                dst[lb] = load_f2(bmr, ((((wave * 4 + q) * GC + g) * MLBK + lb) * 64 + lane) * 8);
+        }
+    };
+    [[maybe_unused]] auto mfma_xyload = [&](int q, float2 (&dst)[2]) {
+        if constexpr (MF && MODE != 0) {
+            const int pr = (((tid >> 6) * 4 + q) * 16 + ((tid & 63) >> 2));
+            dst[0] = a.Xh[(size_t)(kb * CPW + pr / M) * M + pr % M];
+            dst[1] = a.Yh[(size_t)(kb * CPW + pr / M) * M + pr % M];
+        }
+    };
+    // requested before the barrier that precedes the apply: the first MPF steps of B and group 0's Xh, Yh
+    [[maybe_unused]] auto mfma_prefetch = [&]() {
+        if constexpr (MF) {
+#pragma unroll
+            for (int sp = 0; sp < MPF; ++sp) mfma_bload(sp, mb[sp]);
+            mfma_xyload(0, mxy[0]);
+        }
+    };
+    // The apply on the matrix cores (v_mfma_f32_4x4x1_16b_f32: 16 independent 4 x 4 blocks per wavefront,
+    // K = 1).  Block b of a wavefront takes one (column, frequency) pair: rows = 4 layers, columns = the
+    // NF = 4 frames, accumulated over the stars.  Lane 4b + m holds row m of block b's A operand (B of layer
+    // m) and column m of its B operand (d of frame m); the result for (row m, column n) lands in lane 4b + n,
+    // register m, so each lane reads and writes its own frame.  The complex product is four real ones:
+    // Re b += Re B Re d - Im B Im d, Im b += Re B Im d + Im B Re d.  Each
+    // wavefront takes 4 groups of 16 pairs (its 64 pairs): it reads the d of all frames and stars of a group
+    // into registers, then writes the group's b into the layer slots (in place: only its own pairs).  For
+    // each star the 2 MLBK accumulators (real and imaginary part of each layer block) are independent chains.
     [[maybe_unused]] auto apply_mfma = [&](int f0) {
         if constexpr (MF) {
             typedef float f32x4 __attribute__((ext_vector_type(4)));
-            constexpr int LBK = (LC + 3) / 4;                   // layer blocks of 4 (padded with zero B)
             const int wave = tid >> 6, lane = tid & 63, m4 = lane & 3;
-            const __amdgpu_buffer_rsrc_t bmr =
-                block_rsrc(a.Bm + (size_t)kb * 16 * LBK * GC * 64, (unsigned)(16 * LBK * GC * 64 * 8));
             (void)f0;
 #pragma unroll 1
             for (int q = 0; q < 4; ++q) {
-                const int grp = wave * 4 + q;
-                const int pr = grp * 16 + (lane >> 2);          // (column, frequency) pair of the lane's block
+                const int pr = (wave * 4 + q) * 16 + (lane >> 2); // (column, frequency) pair of the lane's block
                 const int cq = pr / M, jq = pr % M;
                 float ar[GC], ai[GC];
-                float2 xq = make_float2(0.f, 0.f), yq = make_float2(0.f, 0.f);
-                if constexpr (MODE != 0) {
-                    xq = a.Xh[(size_t)(kb * CPW + cq) * M + jq];
-                    yq = a.Yh[(size_t)(kb * CPW + cq) * M + jq];
-                }
-                float2 bb[2][GC];
-#pragma unroll
-                for (int g = 0; g < GC; ++g)
-                    bb[0][g] = load_f2(bmr, (((grp * LBK + 0) * GC + g) * 64 + lane) * 8);
 #pragma unroll
                 for (int g = 0; g < GC; ++g) {
                     float2 d = slot(cq, m4, g)[jq];             // frame m4 of the lane's pair
-                    if constexpr (MODE != 0) d = remove_plane(d, coef[m4 * GC + g], xq, yq);
+                    if constexpr (MODE != 0) d = remove_plane(d, coef[m4 * GC + g], mxy[0][0], mxy[0][1]);
                     ar[g] = d.x;
                     ai[g] = d.y;
                 }
-                f32x4 accR[LBK], accI[LBK];
+                mfma_xyload(min(q + 1, 3), mxy[1]);
+                f32x4 accR[MLBK], accI[MLBK];
 #pragma unroll
-                for (int lb = 0; lb < LBK; ++lb) {
+                for (int lb = 0; lb < MLBK; ++lb) {
                     accR[lb] = (f32x4){0.f, 0.f, 0.f, 0.f};
                     accI[lb] = (f32x4){0.f, 0.f, 0.f, 0.f};
-                    if (lb + 1 < LBK) {
-#pragma unroll
-                        for (int g = 0; g < GC; ++g)
-                            bb[(lb + 1) & 1][g] = load_f2(bmr, (((grp * LBK + lb + 1) * GC + g) * 64 + lane) * 8);
-                    }
-#pragma unroll
-                    for (int g = 0; g < GC; ++g) {
-                        const float2 bv = bb[lb & 1][g];
-                        accR[lb] = __builtin_amdgcn_mfma_f32_4x4x1f32(ar[g], bv.x, accR[lb], 0, 0, 0);
-                        accR[lb] = __builtin_amdgcn_mfma_f32_4x4x1f32(-ai[g], bv.y, accR[lb], 0, 0, 0);
-                        accI[lb] = __builtin_amdgcn_mfma_f32_4x4x1f32(ai[g], bv.x, accI[lb], 0, 0, 0);
-                        accI[lb] = __builtin_amdgcn_mfma_f32_4x4x1f32(ar[g], bv.y, accI[lb], 0, 0, 0);
-                    }
                 }
 #pragma unroll
-                for (int lb = 0; lb < LBK; ++lb) {
-                    const int l = lb * 4 + m4;
-                    if (l < LC) {
+                for (int g = 0; g < GC; ++g) {
+                    const int step = q * GC + g;
+                    // clamped on the last group (a repeated load, never used): no branch around it
+                    mfma_bload(min(step + MPF, MSTEPS - 1), mb[(g + MPF) % (MPF + 1)]);
+                    const float2* bv = mb[g % (MPF + 1)];
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) slot(cq, r, l)[jq] = make_float2(accR[lb][r], accI[lb][r]);
+                    for (int lb = 0; lb < MLBK; ++lb) {
+                        accR[lb] = __builtin_amdgcn_mfma_f32_4x4x1f32(bv[lb].x, ar[g], accR[lb], 0, 0, 0);
+                        accI[lb] = __builtin_amdgcn_mfma_f32_4x4x1f32(bv[lb].x, ai[g], accI[lb], 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int lb = 0; lb < MLBK; ++lb) {
+                        accR[lb] = __builtin_amdgcn_mfma_f32_4x4x1f32(bv[lb].y, -ai[g], accR[lb], 0, 0, 0);
+                        accI[lb] = __builtin_amdgcn_mfma_f32_4x4x1f32(bv[lb].y, ar[g], accI[lb], 0, 0, 0);
                     }
                 }
+                // lane 4b + f holds frame f of layers 4 lb .. 4 lb + 3 (register r = layer 4 lb + r)
+#pragma unroll
+                for (int lb = 0; lb < MLBK; ++lb)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (lb * 4 + r < LC) slot(cq, m4, lb * 4 + r)[jq] = make_float2(accR[lb][r], accI[lb][r]);
+                mxy[0][0] = mxy[1][0];
+                mxy[0][1] = mxy[1][1];
             }
         }
     };
@@ -296,6 +335,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
         // B of the block's first two layers, requested before the barrier; later layers two ahead of use
         constexpr int BD = 3;                                   // B buffers in flight (prefetch distance 2)
         float2 bq[BD][FIX ? GC : 1];
+        if constexpr (MF) mfma_prefetch();
         if constexpr (FIX && !MF) {
 #pragma unroll
             for (int q = 0; q < BD - 1; ++q) {
@@ -410,10 +450,10 @@ __global__ void pack_mfma_b_kernel(int M, int L, int G, const float2* __restrict
     const int LBK = (L + 3) / 4;
     const int lane = (int)(e % 64);
     size_t r = e / 64;
-    const int g = (int)(r % G);
-    r /= G;
     const int lb = (int)(r % LBK);
     r /= LBK;
+    const int g = (int)(r % G);
+    r /= G;
     const int grp = (int)(r % 16);
     const size_t kb = r / 16;
     const int l = lb * 4 + lane % 4, pr = grp * 16 + lane / 4;
@@ -432,20 +472,21 @@ hipError_t launch_pack_mfma_b(int M, int L, int G, const float2* B32, float2* Bm
     return hipGetLastError();
 }
 
-size_t cols_lds_bytes(int M, int G, int L, int nf, bool fixed) {
+size_t cols_lds_bytes(int M, int G, int L, int nf, bool fixed, bool mf) {
     const int N1 = M == 32 ? 8 : (M == 64 ? 8 : 16), N2 = M / N1;
     const size_t tl = (size_t)N1 * (N2 + 1) + 2;
     const int spf = fixed ? (G > L ? G : L) : G + L;
-    return ((size_t)M + (size_t)(256 / M) * nf * spf * tl + (size_t)nf * G) * sizeof(float2);
+    const size_t fpad = mf ? (size_t)((8 - (int)((spf * tl) % 32) + 32) % 32) : 0;
+    return ((size_t)M + (size_t)(256 / M) * nf * (spf * tl + fpad) + (size_t)nf * G) * sizeof(float2);
 }
 
 namespace {
 
 template <class K>
 hipError_t launch_cols_kernel(K kernel, int M, int nf, bool fixed, const ColArgs& a, int frames, hipStream_t s,
-                              int lsplit = 1) {
+                              int lsplit = 1, bool mf = false) {
     const int CPW = 256 / M;
-    const size_t lds = cols_lds_bytes(M, a.grp.G, a.L, nf, fixed);
+    const size_t lds = cols_lds_bytes(M, a.grp.G, a.L, nf, fixed, mf);
     const int kblocks = (M / 2) / CPW;                       // the Nyquist column is not transformed
     const int runs = (frames + a.frames_per_block - 1) / a.frames_per_block;
     const int nblk = (kblocks * runs * lsplit + 7) / 8 * 8;
@@ -476,7 +517,8 @@ hipError_t launch_fixed_n(const ColArgs& a, int nf, int frames, hipStream_t s) {
         case 1: return launch_cols_kernel(&cols_kernel<M, 1, G, L, MODE, 1, NN>, M, 1, true, a, frames, s);
         case 2: return launch_cols_kernel(&cols_kernel<M, 2, G, L, MODE, 1, NN>, M, 2, true, a, frames, s);
         case 4:
-            return a.Bm ? launch_cols_kernel(&cols_kernel<M, 4, G, L, MODE, 1, NN, true>, M, 4, true, a, frames, s)
+            return a.Bm ? launch_cols_kernel(&cols_kernel<M, 4, G, L, MODE, 1, NN, true>, M, 4, true, a, frames, s, 1,
+                                             true)
                         : launch_cols_kernel(&cols_kernel<M, 4, G, L, MODE, 1, NN>, M, 4, true, a, frames, s);
         default: return hipErrorInvalidValue;
     }

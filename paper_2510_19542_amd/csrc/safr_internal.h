@@ -92,9 +92,9 @@ struct ColArgs {
 };
 
 // B of the transformed group in the lane layout of the matrix-core apply (v_mfma_f32_4x4x1f32: 16 blocks of
-// 4 x 4, K = 1): per column block kb, group q of 16 (column, frequency) pairs, layer block lb and star g, 64
+// 4 x 4, K = 1): per column block kb, group q of 16 (column, frequency) pairs, star g and layer block lb, 64
 // float2 where lane i holds B[l = 4 lb + i % 4][g] of pair 16 q + i / 4 (zero for l >= L), from the FP32
-// column-pass layout.  Complex count: column blocks x 16 x ceil(L / 4) x G x 64.
+// column-pass layout.  Complex count: column blocks x 16 x G x ceil(L / 4) x 64.
 size_t mfma_b_count(int M, int L, int G);
 hipError_t launch_pack_mfma_b(int M, int L, int G, const float2* B32, float2* Bm, hipStream_t s);
 
@@ -295,7 +295,7 @@ hipError_t launch_cols_mfma(int M, const MfmaArgs& a, int frames, int frames_per
 size_t rows_lds_bytes(int M, int n, int teams);
 size_t out_lds_bytes(int M, int rows_per_block, int nb);
 size_t mfma_lds_bytes(int M, int frames_per_block, int gmax, int L);
-size_t cols_lds_bytes(int M, int G, int L, int frames_together, bool fixed);
+size_t cols_lds_bytes(int M, int G, int L, int frames_together, bool fixed, bool mf = false);
 
 // Precompute (FP64): SVD per half-spectrum frequency and the assembly of B.
 struct PrecompArgs {
