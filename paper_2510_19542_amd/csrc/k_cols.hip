@@ -142,6 +142,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
     constexpr int FR_MAX = FIX ? (CPW * NF * GC + NTEAM - 1) / NTEAM : 1;
     constexpr int FR_UNROLL = FR_MAX;                          // run-time round counts are not unrolled
     float2 xf[FR_MAX][N1];
+    // Deferred inverse tail (compile-time shapes with more layers than stars, one column per block): the
+    // inverse transforms run layers l < G first and l >= G last, and the tasks of the last inverse round
+    // (all with l >= G, slots no forward transform writes) run in the teams the next frame group's last
+    // forward round leaves idle, whole wavefronts of them, so each group takes one round less.
+    constexpr int IT_FIX = CPW * NF * LB, IR_FIX = FIX ? (IT_FIX + NTEAM - 1) / NTEAM : 1;
+    constexpr int F_LAST = CPW * NF * GC - (FR_MAX - 1) * NTEAM;        // forward tasks of the last round
+    constexpr int I_LAST = IT_FIX - (IR_FIX - 1) * NTEAM;               // inverse tasks of the last round
+    constexpr int TPWV = 64 / T;                                        // teams per wavefront
+    constexpr bool DEFER = FIX && LSPLIT == 1 && CPW == 1 && LC > GC && IR_FIX > 1 && I_LAST > 0 &&
+                           I_LAST <= NF * (LC - GC) && F_LAST % TPWV == 0 && F_LAST + I_LAST <= NTEAM;
+    constexpr int IR_UNROLL = IR_FIX;
     // R of frames f0 .. f0 + NF - 1 through one descriptor (byte offsets stay below 2^31)
     const int fstride = a.J * Kh * a.n;                        // float2 per frame of R
     // pupil rows: compile-time when NN > 0.  Team thread t's inputs are the column's rows N2 n1 + t, so only
@@ -297,8 +308,58 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
             }
         }
     };
+    // inverse transforms of the NF frames from f0 (the apply's layer spectra complete in LDS)
+    // 3. inverse column transforms of the layer slots, in place, written to C.  Compile-time shapes run a
+    // fixed number of rounds with every lane storing: a lane without a task (or whose frame lies past the
+    // run) stores to an offset beyond the descriptor's range, which the hardware drops, so the stores need
+    // no branches and the waits after them can be counted.
+    const int itasks = CPW * NF * nl;
+    const size_t cfr = (size_t)L * Kh * M;                     // float2 per frame of C
+    auto c_rsrc = [&](int f0) __attribute__((always_inline)) {
+        return block_rsrc(a.C + c_index(f0, 0, L, M, 0, 0), (unsigned)(min(NF, fend - f0) * cfr * 8));
+    };
+    auto inv_task = [&](int f0, int task, __amdgpu_buffer_rsrc_t cr) __attribute__((always_inline)) {
+        int cc, fl, l;
+        if constexpr (DEFER) {                                  // layers below G first, the others last
+            cc = 0;
+            if (task < NF * GC) {
+                fl = task / GC;
+                l = task - fl * GC;
+            } else {
+                const int t2 = task - NF * GC;
+                fl = t2 / (LC - GC);
+                l = GC + t2 - fl * (LC - GC);
+            }
+        } else {
+            cc = task / (NF * nl);
+            const int rem = task - cc * (NF * nl);
+            fl = rem / nl;
+            l = rem - fl * nl;
+        }
+        const int kk = kb * CPW + cc, f = f0 + fl;
+        const bool active = task < itasks;
+        float2* sl = active ? slot(cc, fl, LS + l) : slots;
+        float2 x[N1];
+        if (active) {
+#pragma unroll
+            for (int n1 = 0; n1 < N1; ++n1) x[n1] = sl[S::N2 * n1 + t];
+        }
+        team_sync();                            // the team's own slot
+        if (active) fft_pass1_regs<M, +1>(t, sl, tws, x);   // idle teams must not write another team's slot
+        team_sync();                            // the team's own slot
+        // idle teams read slot 0 (another team's data, possibly mid-transform) and drop their stores
+        const bool store = active && f < fend;
+        const int base = store ? (int)(c_index(fl, l0 + l, L, M, kk, 0)) : 0;
+        fft_pass2<M, +1>(t, sl, [&](int p, float2 v) {
+            store_f2(cr, store ? (base + (p >> 3) * (Kh * 8) + (p & 7)) * 8 : kDropOffset, v);
+        });
+    };
     constexpr bool PFN = FIX && NN > 0;        // next inputs requested ahead of the stores (pupil size known)
-    auto fwd_apply = [&](int f0) {
+    // fprev: the previous frame group, whose deferred inverse tail runs in the last forward round (with tail;
+    // both calls are inlined with a constant tail)
+    auto fwd_apply = [&](int f0, int fprev, bool tail) __attribute__((always_inline)) {
+        const bool TAIL = DEFER && tail;
+        const __amdgpu_buffer_rsrc_t crp = c_rsrc(tail ? fprev : f0);
         if constexpr (FIX && !PFN) load_fwd(f0, 0, xf[0]);
         // tip/tilt plane coefficients of this iteration's frames, requested now and stored after the
         // forward transforms
@@ -310,6 +371,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
         const int frounds = FIX ? FR_MAX : (ftasks + NTEAM - 1) / NTEAM;
 #pragma unroll FR_UNROLL
         for (int r = 0; r < frounds; ++r) {
+            if (TAIL && r == FR_MAX - 1 && team >= F_LAST) {    // whole wavefronts: a scalar branch
+                if (team < F_LAST + I_LAST) inv_task(fprev, (IR_FIX - 1) * NTEAM + team - F_LAST, crp);
+                continue;
+            }
             const int task = r * NTEAM + team;
             const int cc = task / (NF * G), rem = task - cc * (NF * G);
             const int fl = rem / G, g = rem - fl * G;
@@ -392,54 +457,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
             }
         }
     };
-    // inverse transforms of the NF frames from f0 (the apply's layer spectra complete in LDS)
-    auto inverse = [&](int f0) {
-        // 3. inverse column transforms of the layer slots, in place, written to C.  Compile-time shapes run a
-        // fixed number of rounds with every lane storing: a lane without a task (or whose frame lies past the
-        // run) stores to an offset beyond the descriptor's range, which the hardware drops, so the stores need
-        // no branches and the waits after them can be counted.
-        const int itasks = CPW * NF * nl;
-        constexpr int IR_MAX = FIX ? (CPW * NF * LB + NTEAM - 1) / NTEAM : 1;
-        constexpr int IR_UNROLL = IR_MAX;
-        const int irounds = FIX ? IR_MAX : (itasks + NTEAM - 1) / NTEAM;
-        const int nfr = min(NF, fend - f0);
-        const size_t cfr = (size_t)L * Kh * M;                 // float2 per frame of C
-        const __amdgpu_buffer_rsrc_t cr = block_rsrc(a.C + c_index(f0, 0, L, M, 0, 0), (unsigned)(nfr * cfr * 8));
+    // all rounds, or (the deferred tail) all but the last
+    auto inverse = [&](int f0, bool all) __attribute__((always_inline)) {
+        const int irounds = FIX ? (DEFER && !all ? IR_FIX - 1 : IR_FIX) : (itasks + NTEAM - 1) / NTEAM;
+        const __amdgpu_buffer_rsrc_t cr = c_rsrc(f0);
 #pragma unroll IR_UNROLL
-        for (int r = 0; r < irounds; ++r) {
-            const int task = r * NTEAM + team;
-            const int cc = task / (NF * nl), rem = task - cc * (NF * nl);
-            const int fl = rem / nl, l = rem - fl * nl;
-            const int kk = kb * CPW + cc, f = f0 + fl;
-            const bool active = task < itasks;
-            float2* sl = active ? slot(cc, fl, LS + l) : slots;
-            float2 x[N1];
-            if (active) {
-#pragma unroll
-                for (int n1 = 0; n1 < N1; ++n1) x[n1] = sl[S::N2 * n1 + t];
-            }
-            team_sync();                        // the team's own slot
-            if (active) fft_pass1_regs<M, +1>(t, sl, tws, x);   // idle teams must not write another team's slot
-            team_sync();                        // the team's own slot
-            // idle teams read slot 0 (another team's data, possibly mid-transform) and drop their stores
-            const bool store = active && f < fend;
-            const int base = store ? (int)(c_index(fl, l0 + l, L, M, kk, 0)) : 0;
-            fft_pass2<M, +1>(t, sl, [&](int p, float2 v) {
-                store_f2(cr, store ? (base + (p >> 3) * (Kh * 8) + (p & 7)) * 8 : kDropOffset, v);
-            });
-        }
+        for (int r = 0; r < irounds; ++r) inv_task(f0, r * NTEAM + team, cr);
     };
     if constexpr (PFN) load_fwd(fbeg, 0, xf[0]);
-    fwd_apply(fbeg);
+    fwd_apply(fbeg, 0, false);
     int f0 = fbeg;
     for (; f0 + NF < fend; f0 += NF) {
         __syncthreads();                                        // the apply's layer spectra
         if constexpr (PFN) load_fwd(f0 + NF, 0, xf[0]);         // ahead of this iteration's stores
-        inverse(f0);
-        fwd_apply(f0 + NF);
+        inverse(f0, false);
+        fwd_apply(f0 + NF, f0, true);                           // with this group's deferred inverse tail
     }
     __syncthreads();
-    inverse(f0);
+    inverse(f0, true);
 }
 
 // B in the matrix-core lane layout (see ColArgs::Bm): one thread per output float2
