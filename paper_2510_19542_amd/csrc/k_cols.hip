@@ -397,8 +397,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
             team_sync();                        // the team's own slot
             if (active) fft_pass2_regs<M, -1>(t, z, [&](int jj, float2 v) { sl[jj] = v; });
         }
-        // B of the block's first two layers, requested before the barrier; later layers two ahead of use
-        constexpr int BD = 3;                                   // B buffers in flight (prefetch distance 2)
+        // B of the block's first layers, requested before the barrier; later layers BD - 1 ahead of use: one
+        // when four frames share each B (a deeper prefetch holds more registers and measured slower), two for
+        // fewer frames (one-frame calls wait on B sooner)
+        constexpr int BD = NF >= 4 ? 2 : 3;                     // B buffers in flight
         float2 bq[BD][FIX ? GC : 1];
         if constexpr (MF) mfma_prefetch();
         if constexpr (FIX && !MF) {
@@ -427,7 +429,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
                     const float2 d = slot(c, fl, g)[j];
                     dv[fl][g] = MODE != 0 ? remove_plane(d, coef[fl * GC + g], xh, yh) : d;
                 }
-            // B of layer l + 2 is requested before the products of layer l
+            // B of layer l + BD - 1 is requested before the products of layer l
 #pragma unroll
             for (int l = 0; l < LB; ++l) {
                 if (LSPLIT > 1 && l >= nl) break;
