@@ -254,10 +254,10 @@ safr_status safr_import_B(safr_plan* p, int group, const double* host, size_t co
  *                        P > 0 allocates the plan's counters and synchronises;
  *   SAFR_OPT_COL_MFMA    1 = when the FP32 column pass transforms 4 frames together in its
  *                        compile-time kernel, the per-frequency products B_n d_n of those frames run
- *                        on the matrix cores as 4 x 4 x 1 FP32 products (the 4 frames times 4 layers,
- *                        one star per step; FP32 products and sums as on the vector units); the first
- *                        call with 1 lays out a copy of B for it (device memory of the size of the
- *                        column group's FP32 B, padded to multiples of 4 layers) and synchronises.
+ *                        on the matrix cores as 4 x 4 x 1 FP32 products (4 layers times the 4 frames,
+ *                        one star per step; FP32 products and sums as on the vector units); switching
+ *                        it on synchronises the device and lays out a copy of B for it (device memory
+ *                        of the size of the column group's FP32 B, padded to multiples of 4 layers).
  *                        0 = on the vector units (default: faster at the configured shapes). */
 enum { SAFR_OPT_GRAPH = 0, SAFR_OPT_ROW_TEAMS = 1, SAFR_OPT_OUT_ROWS = 2, SAFR_OPT_MFMA_FRAMES = 3,
        SAFR_OPT_COL_FRAMES = 4, SAFR_OPT_COL_PREFETCH = 5, SAFR_OPT_OUT_FRAMES = 6,

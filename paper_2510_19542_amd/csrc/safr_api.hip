@@ -1451,6 +1451,8 @@ safr_status safr_set_option(safr_plan* p, int option, int value) {
             const int was = p->col_mfma;
             p->col_mfma = value != 0;
             if (p->col_mfma && !was) {      // the lane layout of B (kept up to date only while on)
+                // work still in flight on any stream may read the copy being rewritten
+                HIP_TRY(hipDeviceSynchronize());
                 const safr_status st = build_mfma_b(p, nullptr);
                 if (st != SAFR_OK) {
                     p->col_mfma = 0;
