@@ -567,8 +567,8 @@ def run_c5(S, torch, stream, params):
     geos = [synth.preset(n) for n in names]
     frames = [16 * count[n] for n in names]
     plans = [S.precompute_geometry(g, filter=S.SAFR_FILTER_MLP, mlp=params, noise=0.02) for g in geos]
-    wf = [torch.from_numpy(synth.random_wavefronts(g, f, seed=50 + i)).cuda()
-          for i, (g, f) in enumerate(zip(geos, frames))]
+    wf_host = [synth.random_wavefronts(g, f, seed=50 + i) for i, (g, f) in enumerate(zip(geos, frames))]
+    wf = [torch.from_numpy(w).cuda() for w in wf_host]
     outs = [torch.empty((f, g.L, g.M, g.M), device="cuda") for g, f in zip(geos, frames)]
     m = S.Multi(plans, frames)
     m.autotune(wf, outs, iters=3, stream=stream)
@@ -576,12 +576,15 @@ def run_c5(S, torch, stream, params):
         m.execute(wf, outs, stream=stream)
     ms = _timed(lambda: m.execute(wf, outs, stream=stream), 20, stream, torch)
     total = sum(frames)
+    torch.cuda.synchronize()
+    # one frame of every size (its first and last), for the oracle check of the CPU leg
+    samples = {n: (g, w[[0, -1]], o[[0, -1]].cpu().numpy()) for n, g, w, o in zip(names, geos, wf_host, outs)}
     m.close()
     return {"workload": "64 instances drawn from {8 m/4 NGS/M=64/L=3, 20 m/6 LGS/M=128/L=5, "
                         "39 m MORFEO-like/M=256/L=9}, 16 frames each, learned filter (eta 2%), one graph launch "
                         "per step on a non-default stream (the sizes as parallel branches)",
             "instances": {n: count[n] for n in names}, "frames_per_step": total,
-            "ms_per_step": round(ms, 5), "frames_per_s": round(total * 1000.0 / ms, 1)}
+            "ms_per_step": round(ms, 5), "frames_per_s": round(total * 1000.0 / ms, 1)}, samples
 
 
 def cpu_baseline(geo, budget_s: float, frames_in=None, gpu_out=None):
@@ -637,6 +640,22 @@ def cpu_baseline(geo, budget_s: float, frames_in=None, gpu_out=None):
         res["gpu_vs_oracle_rel_l2"] = {"frames": done, "max": float(f"{max(errs):.3e}"),
                                        "tolerance": 1e-5, "pass": bool(max(errs) <= 1e-5)}
     return res
+
+
+def c5_oracle_check(samples, params, eta=0.02):
+    """Part of the CPU leg: the first and last frame of every size of the mixed-size step against the FP64
+    oracle with the same network (its BF16 evaluation emulated), relative L2 per frame (tolerance 1e-4, the
+    learned filter's inference precision)."""
+    import numpy as np
+    from oracle import safr as O
+    out = {}
+    for name, (g, wf, got) in samples.items():
+        ref = O.precompute_geometry(g, mlp_params=np.asarray(params, np.float64), eta=np.float32(eta), mlp_bf16=True)
+        errs = [float(np.linalg.norm(got[k].astype(np.float64) - want) / np.linalg.norm(want))
+                for k in range(len(wf)) for want in [O.reconstruct(ref, wf[k].astype(np.float64))]]
+        out[name] = float(f"{max(errs):.3e}")
+    return {"frames_per_size": 2, "max_rel_l2": out, "tolerance": 1e-4,
+            "pass": bool(max(out.values()) <= 1e-4) if out else None}
 
 
 def main():
@@ -718,6 +737,7 @@ def main():
     ref_out = out.cpu().numpy()
 
     result = {}
+    c5_samples, params = None, None
     # Order of the legs: the one-frame latency, the closed loop, the refreshes and the other workloads
     # run first and the headline batched step right after the GPU-heavy batched workloads (1024-frame
     # batches, mixed sizes), with no host-side pause in between; the CPU-only oracle leg comes last.
@@ -752,7 +772,7 @@ def main():
             print("bench: 1024-frame batches (C1 geometry)", file=sys.stderr, flush=True)
             result["c3_batched_1024"] = run_c3(S, torch, gstream)
             print("bench: mixed-size bundle", file=sys.stderr, flush=True)
-            result["c5_mixed_sizes"] = run_c5(S, torch, gstream, params)
+            result["c5_mixed_sizes"], c5_samples = run_c5(S, torch, gstream, params)
         if not args.col_mfma:
             print("bench: column apply on the matrix cores", file=sys.stderr, flush=True)
             result["column_apply_on_matrix_cores"] = run_col_mfma(S, torch, geo, batches, out, stream, args.steps)
@@ -874,6 +894,8 @@ def main():
     if not args.only_batched and not args.no_cpu_baseline:
         print("bench: CPU baseline (FP64 oracle) on the timed launch's first batch", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(geo, args.cpu_budget, batches[0].cpu().numpy(), ref_out)
+        if c5_samples:
+            result["c5_mixed_sizes"]["oracle_check"] = c5_oracle_check(c5_samples, params)
     print(json.dumps(result), flush=True)
 
 
