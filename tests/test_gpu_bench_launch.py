@@ -171,3 +171,21 @@ def test_stage_timing_leaves_the_batched_result(c2_bench_run):
         assert np.array_equal(out.cpu().numpy(), got)
     finally:
         S.safr_set_workspace(plan, 0, 0)
+
+
+def test_odd_frame_count_matches_oracle():
+    """65 frames with the stored shapes (a partial last group of the four-frame column kernel and of the
+    output pass's frame runs; Alg. 1 per frame): frames at both ends against the oracle."""
+    torch = _torch()
+    S = _lib()
+    geo = synth.preset("C2")
+    F = 65
+    wf = synth.random_wavefronts(geo, F, seed=17)
+    plan = S.precompute_geometry(geo)
+    bench.apply_shape(S, plan, bench.TUNED_BATCHED)
+    got = _batched(S, torch, plan, torch.from_numpy(wf).cuda(), torch.cuda.Stream())
+    ref = _oracle_plan(geo)
+    for f in (0, 1, 33, 63, 64):
+        err = rel_l2(got[f], O.reconstruct(ref, wf[f].astype(np.float64)))
+        print(f"C2, 65 frames, frame {f}: rel-L2 {err:.3e}")
+        assert err <= 1e-5, (f, err)
