@@ -38,6 +38,9 @@ namespace safr {
 
 namespace {
 
+// cache policy of the layer stores: non-temporal (2) at device scope (16)
+constexpr int kStoreLayers = 2 | 16;
+
 // linear block -> (row block, layer, frame run), XCD-contiguous (blocks are dealt to the 8 XCDs
 // round-robin), so the frame runs of one row block and layer share an L2 and its basis pixels
 __device__ __forceinline__ bool xcd_work(int nwork, int& w) {
@@ -247,8 +250,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OUT_WAVES))
                     }
                 }
                 if (FULL || f < fend) {
-                    const size_t oi = (((size_t)f * L + l) * M + r0 + r) * M + q;
                     if constexpr (INTEG) {          // integrator of the closed loop (Alg. 3)
+                        const size_t oi = (((size_t)f * L + l) * M + r0 + r) * M + q;
                         const float4 pr = *reinterpret_cast<const float4*>(a.prev + oi);
                         const float keep = 1.f - a.gain;
                         o.x = fmaf(a.gain, o.x, keep * pr.x);
@@ -256,10 +259,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OUT_WAVES))
                         o.z = fmaf(a.gain, o.z, keep * pr.z);
                         o.w = fmaf(a.gain, o.w, keep * pr.w);
                     }
-                    // the layers are not read again by the step: streamed past the caches that hold C and the basis
-                    typedef float f32x4 __attribute__((ext_vector_type(4)));
-                    const f32x4 ov = {o.x, o.y, o.z, o.w};
-                    __builtin_nontemporal_store(ov, reinterpret_cast<f32x4*>(a.out + oi));
+                    // the layers are not read again by the step: streamed past the caches that hold C and the
+                    // basis (non-temporal), at device scope (SC1, measured 0.8 us faster per 64 MORFEO-like frames
+                    // than the non-temporal hint alone); one descriptor per (frame, layer) plane of M^2 floats
+                    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+                    const u32x4 ov = {__float_as_uint(o.x), __float_as_uint(o.y), __float_as_uint(o.z),
+                                      __float_as_uint(o.w)};
+                    const __amdgpu_buffer_rsrc_t plane = __builtin_amdgcn_make_buffer_rsrc(
+                        a.out + ((size_t)f * L + l) * M * M, (short)0, M * M * 4, 0x00020000);
+                    __builtin_amdgcn_raw_buffer_store_b128(ov, plane, ((r0 + r) * M + q) * 4, 0, kStoreLayers);
                 }
             }
         }
