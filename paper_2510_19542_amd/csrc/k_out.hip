@@ -18,10 +18,10 @@
 // next iteration's spectra are requested once the current rows are transformed
 // and arrive while the epilogue runs (requested before the transforms, they
 // were slower).  The epilogue is pixel-stationary (thread -> 4-pixel groups of
-// the block's rows): a group's basis pixels are read once per iteration (from
-// L2: the blocks of one row tile are XCD-contiguous) and serve its NF frames.
-// The kernel targets three wavefronts per SIMD; holding the basis pixels in
-// registers for the whole block instead costs a third of the occupancy.
+// the block's rows): a group's basis pixels are loaded into registers once per
+// block (from L2: the blocks of one row tile are XCD-contiguous) and serve every
+// frame of its run.  The kernel runs two wavefronts per SIMD, the occupancy its
+// registers allow with the basis pixels held.
 //
 // C layout (row tiles of 8): C[f][l][p / 8][k][p % 8]; a block's rows of one
 // frame are one contiguous run.
