@@ -29,11 +29,12 @@ METRIC = "SAFR frames/s at MORFEO scale (J=9,L=9,256²) + HBM/MFMA roofline % at
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3          # MI355X FP32 vector peak (published)
 
-# launch shapes of the MORFEO-like plans, chosen by safr_autotune on an MI355X (the one-frame plan's row teams
-# by a sweep: 5 teams cut the 69 pupil rows into 7 chunks, few enough for the passes to add the tip/tilt plane
-# shares themselves) (row teams, output rows, column frames per block, output frames per block, column frames
-# together)
-TUNED_BATCHED = (16, 8, 16, 8, 4)
+# launch shapes of the MORFEO-like plans, chosen by safr_autotune on an MI355X, the row teams by sweeps (one
+# frame: 5 teams cut the 69 pupil rows into 7 chunks, few enough for the passes to add the tip/tilt plane
+# shares themselves; 64 frames, inputs rotating over 8 batches as in the timed steps: 12 teams, chunks of 24,
+# 24 and 21 rows, 1.5 us per step faster than 16 teams' 32, 32 and 5) (row teams, output rows, column frames
+# per block, output frames per block, column frames together)
+TUNED_BATCHED = (12, 8, 16, 8, 4)
 TUNED_SINGLE = (5, 8, 1, 4, 1)
 
 

@@ -1,7 +1,7 @@
 """Parity of the benchmark's own launch with the FP64 oracle.
 
 The throughput benchmark reconstructs 64 MORFEO-like frames per call with the stored
-launch shapes (16 row teams, 8 output rows, 16 column frames per block, 8 output frames
+launch shapes (12 row teams, 8 output rows, 16 column frames per block, 8 output frames
 per block, 4 frames transformed together in the column pass), i.e. the column kernel
 that applies B to four frames at once and walks four runs of 16 frames per column.
 These tests run exactly that launch and hold its output to the FP32 tolerance of the
