@@ -14,34 +14,34 @@
 
 namespace safr {
 
-__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
-__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+#define SAFR_HD __host__ __device__ __forceinline__
+
+SAFR_HD float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+SAFR_HD float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+SAFR_HD float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+SAFR_HD float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 // a * exp(DIR * i pi / 2): DIR = -1 multiplies by -i, DIR = +1 by +i
-template <int DIR> __device__ __forceinline__ float2 rot90(float2 a) {
+template <int DIR> SAFR_HD float2 rot90(float2 a) {
     return DIR < 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
 }
-// twiddle e^(DIR i 2 pi e / M) from the (cos, sin) table
-template <int DIR> __device__ __forceinline__ float2 twiddle(const float2* __restrict__ tw, int e) {
-    float2 w = tw[e];
-    return make_float2(w.x, DIR < 0 ? -w.y : w.y);
+// x * e^(DIR i theta) for a table entry w = (cos, sin)(theta), as one multiply and one FMA per part written
+// out, so that every kernel rounds it the same way whatever the compiler would contract
+template <int DIR> SAFR_HD float2 mul_twiddle(float2 x, float2 w) {
+    return DIR < 0 ? make_float2(fmaf(x.x, w.x, x.y * w.y), fmaf(x.y, w.x, -(x.x * w.y)))
+                   : make_float2(fmaf(x.x, w.x, -(x.y * w.y)), fmaf(x.y, w.x, x.x * w.y));
 }
 
 constexpr float kSqrtHalf = 0.70710678118654752440f;
 constexpr float kCosPi8 = 0.92387953251128675613f;
-constexpr float kSinPi8 = 0.38268343236508977173f;
+constexpr float kTanPi8 = 0.41421356237309504880f;      // sqrt(2) - 1
 
-template <int DIR> __device__ __forceinline__ void dft2(float2& a, float2& b) {
+template <int DIR> SAFR_HD void dft2(float2& a, float2& b) {
     float2 t = a;
     a = cadd(t, b);
     b = csub(t, b);
 }
 
-template <int DIR> __device__ __forceinline__ void dft4(float2* x) {
+template <int DIR> SAFR_HD void dft4(float2* x) {
     float2 t0 = cadd(x[0], x[2]), t1 = csub(x[0], x[2]);
     float2 t2 = cadd(x[1], x[3]), t3 = rot90<DIR>(csub(x[1], x[3]));
     x[0] = cadd(t0, t2);
@@ -50,23 +50,37 @@ template <int DIR> __device__ __forceinline__ void dft4(float2* x) {
     x[3] = csub(t1, t3);
 }
 
-template <int DIR> __device__ __forceinline__ void dft8(float2* x) {
+// Butterflies with a twiddle w = f (a + i b) written as a scale f times a factor with one entry of
+// magnitude one: u = o (a + i b) takes two FMAs (or two adds when |a| = |b| = 1), and e + f u, e - f u four
+// FMAs, six operations instead of the eight of a complex product followed by an add and a subtract.
+SAFR_HD void bfly_scaled(float2& lo, float2& hi, float2 e, float2 u, float f) {
+    lo = make_float2(fmaf(f, u.x, e.x), fmaf(f, u.y, e.y));
+    hi = make_float2(fmaf(-f, u.x, e.x), fmaf(-f, u.y, e.y));
+}
+// o (1 + i d) and o (-1 + i d), d = DIR: the twiddles of angle pi/4 and 3 pi/4 without their sqrt(1/2)
+template <int DIR> SAFR_HD float2 mul_1p(float2 o) {
+    return DIR < 0 ? make_float2(o.x + o.y, o.y - o.x) : make_float2(o.x - o.y, o.y + o.x);
+}
+template <int DIR> SAFR_HD float2 mul_1m(float2 o) {
+    return DIR < 0 ? make_float2(o.y - o.x, -(o.x + o.y)) : make_float2(-(o.x + o.y), o.x - o.y);
+}
+
+template <int DIR> SAFR_HD void dft8(float2* x) {
     float2 e[4] = {x[0], x[2], x[4], x[6]};
     float2 o[4] = {x[1], x[3], x[5], x[7]};
     dft4<DIR>(e);
     dft4<DIR>(o);
-    const float d = (float)DIR;
-    o[1] = cmul(o[1], make_float2(kSqrtHalf, d * kSqrtHalf));
-    o[2] = rot90<DIR>(o[2]);
-    o[3] = cmul(o[3], make_float2(-kSqrtHalf, d * kSqrtHalf));
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        x[k] = cadd(e[k], o[k]);
-        x[k + 4] = csub(e[k], o[k]);
-    }
+    // W8^1 = sqrt(1/2) (1 + i d), W8^2 = i d, W8^3 = sqrt(1/2) (-1 + i d)
+    x[0] = cadd(e[0], o[0]);
+    x[4] = csub(e[0], o[0]);
+    bfly_scaled(x[1], x[5], e[1], mul_1p<DIR>(o[1]), kSqrtHalf);
+    const float2 o2 = rot90<DIR>(o[2]);
+    x[2] = cadd(e[2], o2);
+    x[6] = csub(e[2], o2);
+    bfly_scaled(x[3], x[7], e[3], mul_1m<DIR>(o[3]), kSqrtHalf);
 }
 
-template <int DIR> __device__ __forceinline__ void dft16(float2* x) {
+template <int DIR> SAFR_HD void dft16(float2* x) {
     float2 e[8], o[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -75,22 +89,26 @@ template <int DIR> __device__ __forceinline__ void dft16(float2* x) {
     }
     dft8<DIR>(e);
     dft8<DIR>(o);
-    const float d = (float)DIR;
-    o[1] = cmul(o[1], make_float2(kCosPi8, d * kSinPi8));
-    o[2] = cmul(o[2], make_float2(kSqrtHalf, d * kSqrtHalf));
-    o[3] = cmul(o[3], make_float2(kSinPi8, d * kCosPi8));
-    o[4] = rot90<DIR>(o[4]);
-    o[5] = cmul(o[5], make_float2(-kSinPi8, d * kCosPi8));
-    o[6] = cmul(o[6], make_float2(-kSqrtHalf, d * kSqrtHalf));
-    o[7] = cmul(o[7], make_float2(-kCosPi8, d * kSinPi8));
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        x[k] = cadd(e[k], o[k]);
-        x[k + 8] = csub(e[k], o[k]);
-    }
+    // W16^k = (cos k pi/8, d sin k pi/8), d = DIR, with c = cos pi/8 and t = tan pi/8:
+    // W^1 = c (1 + i d t), W^3 = c (t + i d), W^5 = c (-t + i d), W^7 = c (-1 + i d t),
+    // W^2 = sqrt(1/2) (1 + i d), W^6 = sqrt(1/2) (-1 + i d), W^4 = i d
+    constexpr float d = (float)DIR, dt = d * kTanPi8;
+    x[0] = cadd(e[0], o[0]);
+    x[8] = csub(e[0], o[0]);
+    bfly_scaled(x[1], x[9], e[1], make_float2(fmaf(-dt, o[1].y, o[1].x), fmaf(dt, o[1].x, o[1].y)), kCosPi8);
+    bfly_scaled(x[2], x[10], e[2], mul_1p<DIR>(o[2]), kSqrtHalf);
+    bfly_scaled(x[3], x[11], e[3], make_float2(fmaf(kTanPi8, o[3].x, -d * o[3].y), fmaf(kTanPi8, o[3].y, d * o[3].x)),
+                kCosPi8);
+    const float2 o4 = rot90<DIR>(o[4]);
+    x[4] = cadd(e[4], o4);
+    x[12] = csub(e[4], o4);
+    bfly_scaled(x[5], x[13], e[5], make_float2(fmaf(-kTanPi8, o[5].x, -d * o[5].y), fmaf(-kTanPi8, o[5].y, d * o[5].x)),
+                kCosPi8);
+    bfly_scaled(x[6], x[14], e[6], mul_1m<DIR>(o[6]), kSqrtHalf);
+    bfly_scaled(x[7], x[15], e[7], make_float2(fmaf(-dt, o[7].y, -o[7].x), fmaf(dt, o[7].x, -o[7].y)), kCosPi8);
 }
 
-template <int N, int DIR> __device__ __forceinline__ void dft(float2* x) {
+template <int N, int DIR> SAFR_HD void dft(float2* x) {
     if constexpr (N == 2) dft2<DIR>(x[0], x[1]);
     else if constexpr (N == 4) dft4<DIR>(x);
     else if constexpr (N == 8) dft8<DIR>(x);
@@ -133,7 +151,7 @@ __device__ __forceinline__ void fft_pass1(int t, float2* __restrict__ lds, const
         lds[n2] = x[0];
 #pragma unroll
         for (int k1 = 1; k1 < S::N1; ++k1)
-            lds[k1 * (S::N2 + 1) + n2] = cmul(x[k1], twiddle<DIR>(tw, n2 * k1));
+            lds[k1 * (S::N2 + 1) + n2] = mul_twiddle<DIR>(x[k1], tw[n2 * k1]);
     }
 }
 
@@ -146,7 +164,30 @@ __device__ __forceinline__ void fft_pass1_regs(int t, float2* __restrict__ lds, 
     dft<S::N1, DIR>(x);
     lds[t] = x[0];
 #pragma unroll
-    for (int k1 = 1; k1 < S::N1; ++k1) lds[k1 * (S::N2 + 1) + t] = cmul(x[k1], twiddle<DIR>(tw, t * k1));
+    for (int k1 = 1; k1 < S::N1; ++k1) lds[k1 * (S::N2 + 1) + t] = mul_twiddle<DIR>(x[k1], tw[t * k1]);
+}
+
+// The thread's pass-1 twiddles in registers: twr[k1] = (cos, sin)(2 pi t k1 / M) for team thread t (shapes
+// with N2 == T, where each thread applies the same N1 - 1 twiddles in every transform), read once from the
+// table in global memory instead of from LDS in every transform.
+template <int M>
+__device__ __forceinline__ void load_pass1_twiddles(const float2* __restrict__ tw, int t,
+                                                    float2 (&twr)[FftShape<M>::N1]) {
+#pragma unroll
+    for (int k1 = 0; k1 < FftShape<M>::N1; ++k1) twr[k1] = tw[t * k1];
+}
+
+// Pass 1 from inputs in registers with the twiddles in registers (see load_pass1_twiddles).
+template <int M, int DIR>
+__device__ __forceinline__ void fft_pass1_regs(int t, float2* __restrict__ lds, const float2 (&twr)[FftShape<M>::N1],
+                                               float2 (&x)[FftShape<M>::N1]) {
+    using S = FftShape<M>;
+    static_assert(S::N2 == S::T, "one pass-1 sub-transform per thread");
+    dft<S::N1, DIR>(x);
+    lds[t] = x[0];
+#pragma unroll
+    for (int k1 = 1; k1 < S::N1; ++k1)
+        lds[k1 * (S::N2 + 1) + t] = mul_twiddle<DIR>(x[k1], twr[k1]);
 }
 
 // Pass 2 for team thread t: k1 = t, t + T, ...; store(k, value) receives X[k].

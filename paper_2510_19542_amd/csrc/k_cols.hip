@@ -111,8 +111,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
     const int LS = FIX ? 0 : G;
 
     extern __shared__ float2 smem[];
-    float2* tws = smem;                                        // [M]
-    float2* slots = smem + M;                                  // [CPW][NF][SPF][TL]
+    float2* slots = smem;                                      // [CPW][NF][SPF][TL]
     // the matrix-core apply reads and writes one slot of each of the 4 frames per instruction: frames are
     // padded to 8 float2 past a multiple of 32 apart, so the 4 frames' 8-pair runs of a half wavefront fall
     // in distinct banks
@@ -191,13 +190,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
         }
     };
 
-    const float2 twv = tid < M ? a.tw[tid] : make_float2(0.f, 0.f);
+    float2 twr[N1];                                            // this thread's pass-1 twiddles
+    load_pass1_twiddles<M>(a.tw, t, twr);
     float2 xh = make_float2(0.f, 0.f), yh = make_float2(0.f, 0.f);
     if (MODE != 0) {
         xh = a.Xh[(size_t)k * M + j];
         yh = a.Yh[(size_t)k * M + j];
     }
-    if (tid < M) tws[tid] = twv;
     const __amdgpu_buffer_rsrc_t Brs = block_rsrc(a.B + (size_t)kb * L * G * 256, (unsigned)(L * G * 256 * 8));
 
     // Software pipelined over the block's frames: the loop body runs the inverse transforms of one iteration
@@ -350,7 +349,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
             for (int n1 = 0; n1 < N1; ++n1) x[n1] = sl[S::N2 * n1 + t];
         }
         team_sync();                            // the team's own slot
-        if (active) fft_pass1_regs<M, +1>(t, sl, tws, x);   // idle teams must not write another team's slot
+        if (active) fft_pass1_regs<M, +1>(t, sl, twr, x);   // idle teams must not write another team's slot
         team_sync();                            // the team's own slot
         // idle teams read slot 0 (another team's data, possibly mid-transform) and drop their stores
         const bool store = active && f < fend;
@@ -392,7 +391,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M >= 128 ? 
             } else {
                 load_fwd(f0, r, x);
             }
-            if (active) fft_pass1_regs<M, -1>(t, sl, tws, x);
+            if (active) fft_pass1_regs<M, -1>(t, sl, twr, x);
             if constexpr (FIX) {
                 if (r + 1 < FR_MAX) load_fwd(f0, r + 1, xf[r + 1 < FR_MAX ? r + 1 : r]);
             }
@@ -519,7 +518,7 @@ size_t cols_lds_bytes(int M, int G, int L, int nf, bool fixed, bool mf) {
     const size_t tl = (size_t)N1 * (N2 + 1) + 2;
     const int spf = fixed ? (G > L ? G : L) : G + L;
     const size_t fpad = mf ? (size_t)((8 - (int)((spf * tl) % 32) + 32) % 32) : 0;
-    return ((size_t)M + (size_t)(256 / M) * nf * (spf * tl + fpad) + (size_t)nf * G) * sizeof(float2);
+    return ((size_t)(256 / M) * nf * (spf * tl + fpad) + (size_t)nf * G) * sizeof(float2);
 }
 
 namespace {

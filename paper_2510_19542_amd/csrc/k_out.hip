@@ -103,9 +103,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OUT_WAVES))
     const int L = a.L;
     const int nb = MIXED ? (TAIL ? a.nb : NB) : 0;
 
-    float2* tws = smem;                                             // [M]
-    float2* reg = tws + M + team * RS;                              // this team's region
-    float* coef = reinterpret_cast<float*>(tws + M + O::NTEAM * RS); // [NF][nb]
+    float2* reg = smem + team * RS;                                 // this team's region
+    float* coef = reinterpret_cast<float*>(smem + O::NTEAM * RS);   // [NF][nb]
 
     // spectra of frame f: RT / 8 row tiles of layer l, each Kh * 8 float2 (two float2 per float4); the
     // Nyquist column k = M/2 is neither written by the column pass nor read here
@@ -132,7 +131,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OUT_WAVES))
             // float4 s4 of the tile: column k = s4 / 4, rows 2 (s4 % 4) and 2 (s4 % 4) + 1 of the tile
             const int tile = wave * O::TPW + e / O::TILE4, s4 = e % O::TILE4;
             const int k = s4 >> 2;
-            float2* dst = smem + M + (tile * 4 + (s4 & 3)) * RS;
+            float2* dst = smem + (tile * 4 + (s4 & 3)) * RS;
             dst[k] = make_float2(ld[i].x, ld[i].y);
             dst[Kh + k] = make_float2(ld[i].z, ld[i].w);
         }
@@ -144,7 +143,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OUT_WAVES))
 
     // plane lane rounds: every pair in registers unless the basis count is only known at run time
     constexpr int PR = TAIL || !MIXED ? 1 : (NF * (NB / 2) + 256 / kPlaneLanes - 1) / (256 / kPlaneLanes);
-    const float2 twv = tid < M ? a.tw[tid] : make_float2(0.f, 0.f);
+    float2 twr[S::N1];                                              // this thread's pass-1 twiddles
+    load_pass1_twiddles<M>(a.tw, t, twr);
     issue(fbeg);
     float2 pl[PR];
     if constexpr (MIXED) plane_fetch<PR>(planes_of(fbeg), pl);
@@ -160,14 +160,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OUT_WAVES))
                 pv[v][i] = *reinterpret_cast<const float4*>(a.P + (((size_t)l * nb + i) * M + r0 + r) * M + q);
         }
     }
-    if (tid < M) tws[tid] = twv;
     stash();
     if constexpr (MIXED) plane_put<PR, TAIL>(planes_of(fbeg), pl, reinterpret_cast<float2*>(coef));
     // every load so far (the basis pixels included) complete here, once: the loop body's waits then only
     // count what the body itself issued, and a later iteration's epilogue does not wait for the previous
     // iteration's stores on the basis pixels' account (vmcnt(0); expcnt and lgkmcnt at their maxima)
     __builtin_amdgcn_s_waitcnt(0x0F70);
-    __syncthreads();                                        // twiddles, spectra and plane coefficients
+    __syncthreads();                                        // spectra and plane coefficients
 
     // one iteration: NF frames from f0, whose spectra and plane coefficients are in LDS.  PF: the next
     // iteration's are requested after the transforms and put into LDS at the end (waiting for them then
@@ -199,7 +198,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OUT_WAVES))
             }
         }
         team_sync();                        // the team's own region
-        fft_pass1_regs<M, +1>(t, reg, tws, x);
+        fft_pass1_regs<M, +1>(t, reg, twr, x);
         team_sync();                        // the team's own region
         float2 z[S::N1 / S::T][S::N2];
         fft_pass2_load<M>(t, reg, z);
@@ -225,7 +224,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OUT_WAVES))
 #pragma unroll
             for (int fi = 0; fi < NF; ++fi) {
                 const int f = f0 + fi;
-                const float* src = reinterpret_cast<const float*>(smem + M + (fi * TPF + r / 2) * RS) + (r & 1) * M + q;
+                const float* src = reinterpret_cast<const float*>(smem + (fi * TPF + r / 2) * RS) + (r & 1) * M + q;
                 float4 o = *reinterpret_cast<const float4*>(src);
                 if constexpr (MIXED) {
                     const float* cf = coef + fi * nb;
@@ -302,7 +301,7 @@ size_t out_lds_bytes(int M, int RT, int nb) {
     const int N1 = M == 32 ? 8 : (M == 64 ? 8 : 16), N2 = M / N1;
     const int T = M == 256 ? 16 : (M == 32 ? 4 : 8);
     const int NF = out_frames_per_iter(M, RT);
-    return ((size_t)M + (size_t)(256 / T) * (N1 * (N2 + 1) + 2)) * sizeof(float2) + (size_t)NF * nb * sizeof(float);
+    return (size_t)(256 / T) * (N1 * (N2 + 1) + 2) * sizeof(float2) + (size_t)NF * nb * sizeof(float);
 }
 
 namespace {
