@@ -55,19 +55,17 @@ __global__ __launch_bounds__(256) void rows_kernel(RowArgs a) {
     const float* wf = a.wf + ((size_t)f * a.J + star) * (size_t)n * n + (size_t)r0 * n;
     const unsigned char* pup = a.pupil + (size_t)r0 * n;
 
-    // LDS: twiddles [M], one region per team (the pass-1 -> pass-2 exchange, then the packed spectrum),
-    // 3 floats per wavefront for the moment reduction
-    float2* tws = smem;
-    float2* xch = smem + M + team * TS;
-    float* red = reinterpret_cast<float*>(smem + M + nteams * TS);
+    // LDS: one region per team (the pass-1 -> pass-2 exchange, then the packed spectrum), 3 floats per
+    // wavefront for the moment reduction.  The thread's pass-1 twiddles are held in registers (no LDS table,
+    // so more blocks fit a CU)
+    float2* xch = smem + team * TS;
+    float* red = reinterpret_cast<float*>(smem + nteams * TS);
 
-    // twiddles first (blocks may have fewer than M threads), then the team's two pupil-masked rows straight
-    // into the pass-1 registers: x[n1] = (row a, row b) at grid column N2 n1 + t, i.e. pupil column
-    // N2 n1 + t - p0 (all loads issued before any is used)
-    constexpr int TWR = (M + 63) / 64;
-    float2 twr[TWR];
-#pragma unroll
-    for (int u = 0; u < TWR; ++u) twr[u] = a.tw[min(tid + u * nthr, M - 1)];
+    // the thread's twiddles, then the team's two pupil-masked rows straight into the pass-1 registers:
+    // x[n1] = (row a, row b) at grid column N2 n1 + t, i.e. pupil column N2 n1 + t - p0 (all loads issued
+    // before any is used)
+    float2 twr[N1];
+    load_pass1_twiddles<M>(a.tw, t, twr);
     const int ra = 2 * team;
     const bool active = team < nteams && ra < rows;
     const bool has_b = active && ra + 1 < rows;
@@ -90,10 +88,6 @@ __global__ __launch_bounds__(256) void rows_kernel(RowArgs a) {
         const float va = wa[qs], vb = wb[qs];
         x[n1] = make_float2(in && ma ? va : 0.f, in && has_b && mb ? vb : 0.f);
     }
-#pragma unroll
-    for (int u = 0; u < TWR; ++u)
-        if (tid + u * nthr < M) tws[tid + u * nthr] = twr[u];
-
     if (mode != 0) {
         // partial moments (sum v, sum x v, sum y v) of the chunk, coordinates about the pupil centre
         const float half = 0.5f * (float)(n - 1);
@@ -133,9 +127,9 @@ __global__ __launch_bounds__(256) void rows_kernel(RowArgs a) {
         }
     }
     if (mode == 2) return;          // natural star of a mixed asterism: only its plane is used
-    __syncthreads();                // twiddles visible
 
-    if (active) fft_pass1_regs<M, -1>(t, xch, tws, x);
+    // the team's own region (the moment reduction above uses another part of LDS)
+    if (active) fft_pass1_regs<M, -1>(t, xch, twr, x);
     team_sync();                    // the team's own region
     float2 zr[N1 / T][N2];
     if (active) fft_pass2_load<M>(t, xch, zr);
@@ -154,7 +148,7 @@ __global__ __launch_bounds__(256) void rows_kernel(RowArgs a) {
         const int k = idx >> lg;
         const int pr = idx & ((1 << lg) - 1);
         if (pr < npair) {
-            const float2* z = smem + M + pr * TS;
+            const float2* z = smem + pr * TS;
             const float2 zk = z[k];
             const float2 zm = cconj(z[(M - k) & (M - 1)]);
             float2* dst = Rb + (size_t)k * n + 2 * pr;
@@ -221,7 +215,7 @@ hipError_t launch_rows(int M, const RowArgs& a, int frames, int nchunk, int team
 size_t rows_lds_bytes(int M, int n, int teams) {
     (void)n;
     const int N1 = M == 32 ? 8 : (M == 64 ? 8 : 16), N2 = M / N1;
-    return ((size_t)M + (size_t)teams * (N1 * (N2 + 1) + 2)) * sizeof(float2) + 64 * sizeof(float);
+    return (size_t)teams * (N1 * (N2 + 1) + 2) * sizeof(float2) + 64 * sizeof(float);
 }
 
 }  // namespace safr
