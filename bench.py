@@ -153,14 +153,20 @@ def measured_traffic(frames: int, stage: str = None):
     return sum(parts) if parts else None
 
 
-def _timed(fn, iters, stream, torch):
+def _timed(fn, iters, stream, torch, host=None):
+    """GPU milliseconds per call between two events around `iters` back-to-back calls; with a dict `host`,
+    also the host's microseconds per call spent issuing them (host["us"])."""
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
+    t0 = time.perf_counter()
     for _ in range(iters):
         fn()
+    t1 = time.perf_counter()
     e1.record(stream)
     torch.cuda.synchronize()
+    if host is not None:
+        host["us"] = (t1 - t0) * 1e6 / iters
     return e0.elapsed_time(e1) / iters
 
 
@@ -177,21 +183,24 @@ def run_c3(S, torch, stream):
         plan = S.precompute_geometry(geo)
         _attach_workspace(S, torch, plan, F, prec)
         tuned = S.safr_autotune(plan, F, x, out, prec, 3, stream)
-        timing = {}
+        timing, host = {}, {}
         # eager launches, then the launch sequence captured once in a HIP graph and replayed (the stream is
-        # not the legacy default stream, which cannot be captured)
+        # not the legacy default stream, which cannot be captured); the host time spent issuing each call is
+        # kept beside the GPU time (a call whose issue takes longer than its kernels leaves the GPU waiting)
         for mode in ("eager", "graph"):
             S.safr_set_option(plan, S.SAFR_OPT_GRAPH, 1 if mode == "graph" else 0)
             for _ in range(3):
                 S.safr_reconstruct_batched(plan, F, x, out, prec, stream)
+            host[mode] = {}
             timing[mode] = _timed(lambda: S.safr_reconstruct_batched(plan, F, x, out, prec, stream), 20, stream,
-                                  torch)
+                                  torch, host[mode])
         S.safr_set_option(plan, S.SAFR_OPT_GRAPH, 0)
         st = S.safr_time_stages(plan, F, x, out, prec, 10, stream)
         ms = timing["graph"]
         res[name] = {"ms_per_call": round(ms, 5), "frames_per_s": round(F * 1000.0 / ms, 1),
                      "ms_per_call_eager": round(timing["eager"], 5),
                      "frames_per_s_eager": round(F * 1000.0 / timing["eager"], 1),
+                     "host_us_per_call": {m: round(host[m]["us"], 2) for m in host},
                      "stage_ms": [round(v, 5) for v in st], "autotuned": tuned}
     return res
 
@@ -237,8 +246,10 @@ def run_loop(S, torch, plan, geo, pool, calls):
         torch.cuda.synchronize()
         for _ in range(100):
             S.safr_loop_step(plan, 1, wf, a, gain, a, s)
-        ms = _timed(lambda: S.safr_loop_step(plan, 1, wf, a, gain, a, s), calls, s, torch)
+        h = {}
+        ms = _timed(lambda: S.safr_loop_step(plan, 1, wf, a, gain, a, s), calls, s, torch, h)
         res[f"us_per_step_{name}"] = round(ms * 1000.0, 3)
+        res[f"host_us_per_step_{name}"] = round(h["us"], 3)
     S.safr_set_option(plan, S.SAFR_OPT_GRAPH, 0)
     # per-step latency (events around every eager step): tail against the 1 ms period of a 1 kHz loop
     nstep = 1000
