@@ -258,11 +258,17 @@ safr_status safr_import_B(safr_plan* p, int group, const double* host, size_t co
  *                        one star per step; FP32 products and sums as on the vector units); switching
  *                        it on synchronises the device and lays out a copy of B for it (device memory
  *                        of the size of the column group's FP32 B, padded to multiples of 4 layers).
- *                        0 = on the vector units (default: faster at the configured shapes). */
+ *                        0 = on the vector units (default: faster at the configured shapes);
+ *   SAFR_OPT_SEQ_FRAMES  frames per launch sequence: a call with more frames runs its row, column and
+ *                        output passes for groups of about equal size, one group after the other (the
+ *                        tuning options apply per group; results are the same as in one sequence).
+ *                        0 = automatic (default): groups whose intermediate spectra take at most
+ *                        200 MiB, so that they stay in the GPU's 256 MB Infinity Cache (69 frames at
+ *                        MORFEO scale); 1 .. 65535 = at most that many frames per group. */
 enum { SAFR_OPT_GRAPH = 0, SAFR_OPT_ROW_TEAMS = 1, SAFR_OPT_OUT_ROWS = 2, SAFR_OPT_MFMA_FRAMES = 3,
        SAFR_OPT_COL_FRAMES = 4, SAFR_OPT_COL_PREFETCH = 5, SAFR_OPT_OUT_FRAMES = 6,
        SAFR_OPT_COL_TOGETHER = 7, SAFR_OPT_CHECK_FINITE = 8, SAFR_OPT_DEADLINE_US = 9,
-       SAFR_OPT_COL_MFMA = 10 };
+       SAFR_OPT_COL_MFMA = 10, SAFR_OPT_SEQ_FRAMES = 11 };
 safr_status safr_set_option(safr_plan* p, int option, int value);
 
 /* Deadline monitor of the closed-loop step (SAFR_OPT_DEADLINE_US): steps counted since the last reset,

@@ -103,6 +103,7 @@ struct safr_plan {
     int row_teams = 0, out_rows = 0, out_frames = 1, mfma_frames = 16, col_frames = 1, col_nf = 1, col_prefetch = 1;
     int col_mfma = 0;               // FP32 column pass with 4 frames: the apply on the matrix cores
     int col_frames_auto = 1;        // column frames per block chosen per launch (until set or autotuned)
+    int seq_frames = 0;             // frames per launch sequence (0: from kSequenceBytes), see SAFR_OPT_SEQ_FRAMES
     int use_graph = 0;
     int deadline_us = 0;            // loop-step deadline (0: off), see SAFR_OPT_DEADLINE_US
     unsigned long long deadline_ticks = 0;
@@ -149,6 +150,17 @@ size_t ws_m(const safr_plan* p, int frames) {
 size_t ws_w(const safr_plan* p, int frames) { return align256((size_t)frames * p->J * p->n * p->n * sizeof(float)); }
 size_t ws_bytes(const safr_plan* p, int frames) {
     return ws_r(p, frames) + ws_c(p, frames) + ws_m(p, frames) + ws_w(p, frames);
+}
+
+// A call with more frames runs as several launch sequences (row, column and output pass) of about equal size,
+// each with at most this many bytes of intermediate spectra (R and C), so that they stay in the 256 MB
+// Infinity Cache next to B and the basis images: 69 MORFEO-like frames (3.0 MB each; measured: 128 frames as
+// one sequence 304 us, as two of 64 243 us).
+constexpr size_t kSequenceBytes = size_t(200) << 20;
+int sequence_frames(const safr_plan* p) {
+    if (p->seq_frames > 0) return p->seq_frames;
+    const size_t per = (size_t)p->J * p->Kh * p->n * sizeof(float2) + (size_t)p->L * p->Kh * p->M * sizeof(float2);
+    return (int)std::max<size_t>(1, std::min<size_t>(kSequenceBytes / per, kMaxFrames));
 }
 
 // captured graphs hold launch shapes and pointers: dropped whenever a tuning option changes
@@ -1447,6 +1459,10 @@ safr_status safr_set_option(safr_plan* p, int option, int value) {
             p->col_nf = value;
             return SAFR_OK;
         case 8: p->check_finite = value != 0; return SAFR_OK;
+        case 11:
+            if (value < 0 || value > kMaxFrames) return fail(SAFR_ERR_ARG, "bad frames per launch sequence");
+            p->seq_frames = value;
+            return SAFR_OK;
         case 10: {
             const int was = p->col_mfma;
             p->col_mfma = value != 0;
@@ -1485,7 +1501,8 @@ safr_status safr_set_option(safr_plan* p, int option, int value) {
 
 namespace {
 
-safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, int precision, void* ws,
+// one launch sequence (row, column and output pass) over `frames` frames
+safr_status launch_seq(safr_plan* p, int frames, const float* wf, float* out, int precision, void* ws,
                        hipStream_t s, hipEvent_t* ev, const float* prev, float gain, int stage) {
     const bool do_rows = stage < 0 || stage == 0, do_cols = stage < 0 || stage == 1, do_out = stage < 0 || stage == 2;
     if (ev) HIP_TRY(hipEventRecord(ev[0], s));
@@ -1602,6 +1619,23 @@ safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, in
     oa.gain = gain;
     if (do_out) HIP_TRY(launch_out(p->M, oa, p->out_rows, frames, s));
     if (ev) HIP_TRY(hipEventRecord(ev[3], s));
+    return SAFR_OK;
+}
+
+// the call's frames in launch sequences of at most sequence_frames(p) frames, one after the other on the stream
+// (each uses the start of the workspace; `ev`, when given, brackets the stages of the first sequence)
+safr_status launch_all(safr_plan* p, int frames, const float* wf, float* out, int precision, void* ws,
+                       hipStream_t s, hipEvent_t* ev, const float* prev, float gain, int stage) {
+    const int cap = sequence_frames(p);
+    if (frames <= cap) return launch_seq(p, frames, wf, out, precision, ws, s, ev, prev, gain, stage);
+    const int nseq = (frames + cap - 1) / cap, per = (frames + nseq - 1) / nseq;
+    const size_t wstride = (size_t)p->J * p->n * p->n, ostride = (size_t)p->L * p->M * p->M;
+    for (int f0 = 0; f0 < frames; f0 += per) {
+        const int nf = std::min(per, frames - f0);
+        const safr_status st = launch_seq(p, nf, wf + f0 * wstride, out + f0 * ostride, precision, ws, s,
+                                          f0 == 0 ? ev : nullptr, prev ? prev + f0 * ostride : nullptr, gain, stage);
+        if (st != SAFR_OK) return st;
+    }
     return SAFR_OK;
 }
 
