@@ -191,7 +191,10 @@ safr_status safr_reconstruct_batched_static(safr_plan* p, int frames, const floa
                                             int precision, hipStream_t stream);
 size_t safr_static_workspace_bytes(void);
 
-/* Device workspace bytes needed for `frames` frames (1..65535). */
+/* Device workspace bytes needed for `frames` frames (1..65535): the row and layer spectra of the call's
+ * largest launch sequence (SAFR_OPT_SEQ_FRAMES; about 3 MB per MORFEO-like frame, at most 200 MiB by
+ * default) plus, for safr_loop_step, the pseudo-open-loop wavefronts of all its frames.  Depends on the
+ * plan's SAFR_OPT_SEQ_FRAMES: a workspace bound before that option is raised may become too small. */
 safr_status safr_workspace_size(const safr_plan* p, int frames, int precision, size_t* bytes);
 
 /* Binds caller-owned device memory (>= 256-byte aligned) as the workspace

@@ -148,10 +148,6 @@ size_t ws_m(const safr_plan* p, int frames) {
 }
 // pseudo-open-loop wavefronts of the closed-loop step
 size_t ws_w(const safr_plan* p, int frames) { return align256((size_t)frames * p->J * p->n * p->n * sizeof(float)); }
-size_t ws_bytes(const safr_plan* p, int frames) {
-    return ws_r(p, frames) + ws_c(p, frames) + ws_m(p, frames) + ws_w(p, frames);
-}
-
 // A call with more frames runs as several launch sequences (row, column and output pass) of about equal size,
 // each with at most this many bytes of intermediate spectra (R and C), so that they stay in the 256 MB
 // Infinity Cache next to B and the basis images: 69 MORFEO-like frames (3.0 MB each; measured: 128 frames as
@@ -162,6 +158,15 @@ int sequence_frames(const safr_plan* p) {
     const size_t per = (size_t)p->J * p->Kh * p->n * sizeof(float2) + (size_t)p->L * p->Kh * p->M * sizeof(float2);
     return (int)std::max<size_t>(1, std::min<size_t>(kSequenceBytes / per, kMaxFrames));
 }
+
+// Workspace of a call: R, C and the plane parts of its largest launch sequence (each sequence starts at the
+// beginning of the workspace), then the pseudo-open-loop wavefronts of all its frames (closed-loop step).
+size_t ws_seq(const safr_plan* p, int frames) {
+    const int f = std::min(frames, sequence_frames(p));
+    return ws_r(p, f) + ws_c(p, f) + ws_m(p, f);
+}
+size_t ws_bytes(const safr_plan* p, int frames) { return ws_seq(p, frames) + ws_w(p, frames); }
+
 
 // captured graphs hold launch shapes and pointers: dropped whenever a tuning option changes
 void drop_graphs(safr_plan* p) {
@@ -416,8 +421,7 @@ safr_status check_inputs(safr_plan* p, int frames, const float* wf, const float*
 // the integrator fused into the output pass
 safr_status launch_loop(safr_plan* p, int frames, const float* wf, const float* a_in, float gain, float* a_out,
                         void* ws, hipStream_t s) {
-    float* psi = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + ws_r(p, frames) + ws_c(p, frames) +
-                                          ws_m(p, frames));
+    float* psi = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + ws_seq(p, frames));
     if (p->deadline_ticks) HIP_TRY(launch_deadline_start(p->dstats, s));
     HIP_TRY(launch_polc(polc_args(p, wf, a_in, 1.f, psi), frames, s));
     const safr_status st = launch_all(p, frames, psi, a_out, SAFR_FP32, ws, s, nullptr, a_in, gain);

@@ -121,3 +121,23 @@ def test_sequence_option_rejects_bad_values():
     for bad in (-1, 65536):
         with pytest.raises(S.SafrError):
             S.safr_set_option(plan, S.SAFR_OPT_SEQ_FRAMES, bad)
+
+
+def test_workspace_holds_one_sequence():
+    """The workspace holds the spectra of one launch sequence (each sequence reuses it) plus the closed-loop
+    wavefronts of every frame: it grows with the frame count only by the latter beyond one sequence."""
+    torch, S = _mods()
+    geo = synth.preset("C2")
+    plan = S.precompute_geometry(geo)
+    J, n = len(geo.stars), geo.n
+    one = S.safr_workspace_size(plan, 69)
+    big = S.safr_workspace_size(plan, 2000)
+    polc = lambda F: F * J * n * n * 4
+    assert big - one <= polc(2000) - polc(69) + 256
+    assert big - one >= polc(2000) - polc(69) - 256
+    # 150 frames (three sequences of 50) in exactly that workspace, against one sequence
+    F = 150
+    x = torch.from_numpy(synth.random_wavefronts(geo, F, seed=2)).cuda()
+    got = _run(S, torch, plan, x, 0)[0]
+    ref = _run(S, torch, plan, x, ONE_SEQUENCE)[0]
+    assert np.array_equal(got, ref)
