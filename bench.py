@@ -189,10 +189,11 @@ def run_c3(S, torch, stream):
         # kept beside the GPU time (a call whose issue takes longer than its kernels leaves the GPU waiting)
         for mode in ("eager", "graph"):
             S.safr_set_option(plan, S.SAFR_OPT_GRAPH, 1 if mode == "graph" else 0)
-            for _ in range(3):
+            # the first replays of a new graph cost the host up to 100 us each, later ones about 20 us
+            for _ in range(20):
                 S.safr_reconstruct_batched(plan, F, x, out, prec, stream)
             host[mode] = {}
-            timing[mode] = _timed(lambda: S.safr_reconstruct_batched(plan, F, x, out, prec, stream), 20, stream,
+            timing[mode] = _timed(lambda: S.safr_reconstruct_batched(plan, F, x, out, prec, stream), 200, stream,
                                   torch, host[mode])
         S.safr_set_option(plan, S.SAFR_OPT_GRAPH, 0)
         st = S.safr_time_stages(plan, F, x, out, prec, 10, stream)
