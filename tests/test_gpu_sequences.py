@@ -141,3 +141,28 @@ def test_workspace_holds_one_sequence():
     got = _run(S, torch, plan, x, 0)[0]
     ref = _run(S, torch, plan, x, ONE_SEQUENCE)[0]
     assert np.array_equal(got, ref)
+
+
+def test_stage_timing_and_autotune_over_groups():
+    """safr_time_stages and safr_autotune on a call of several launch sequences: the stage timing covers every
+    group, the autotuner times the first, and the tuned call still equals one sequence bit for bit."""
+    torch, S = _mods()
+    geo = synth.preset("C1")
+    F = 20
+    plan = S.precompute_geometry(geo)
+    d = plan.desc
+    x = torch.from_numpy(synth.random_wavefronts(geo, F, seed=17)).cuda()
+    out = torch.empty((F, d.L, d.M, d.M), dtype=torch.float32, device="cuda")
+    S.safr_set_option(plan, S.SAFR_OPT_SEQ_FRAMES, 7)
+    need = S.safr_workspace_size(plan, F)
+    ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+    S.safr_set_workspace(plan, (ws.data_ptr() + 255) & ~255, need)
+    stream = torch.cuda.current_stream()
+    ms = S.safr_time_stages(plan, F, x, out, S.SAFR_FP32, 5, stream)
+    assert all(v > 0.0 for v in ms), ms
+    choice = S.safr_autotune(plan, F, x, out, S.SAFR_FP32, 3, stream)
+    assert len(choice) == 5 and all(v >= 1 for v in choice), choice
+    S.safr_set_workspace(plan, 0, 0)
+    got = _run(S, torch, plan, x, 7)[0]
+    ref = _run(S, torch, plan, x, ONE_SEQUENCE)[0]
+    assert np.array_equal(got, ref)
