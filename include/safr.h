@@ -267,11 +267,16 @@ safr_status safr_import_B(safr_plan* p, int group, const double* host, size_t co
  *                        tuning options apply per group; results are the same as in one sequence).
  *                        0 = automatic (default): groups whose intermediate spectra take at most
  *                        200 MiB, so that they stay in the GPU's 256 MB Infinity Cache (69 frames at
- *                        MORFEO scale); 1 .. 65535 = at most that many frames per group. */
+ *                        MORFEO scale); 1 .. 65535 = at most that many frames per group;
+ *   SAFR_OPT_FUSED       1 = FP32 calls of the small configured shape (M = 64, n = 33, one group of 4
+ *                        stars, L = 2 or 3) run the whole step of each frame in one block of one kernel,
+ *                        its spectra in LDS (default); 0 = the row, column and output passes.  Same
+ *                        layers either way.  safr_time_stages then reports the whole step as the row
+ *                        stage and zero for the other two; the closed-loop step keeps the three passes. */
 enum { SAFR_OPT_GRAPH = 0, SAFR_OPT_ROW_TEAMS = 1, SAFR_OPT_OUT_ROWS = 2, SAFR_OPT_MFMA_FRAMES = 3,
        SAFR_OPT_COL_FRAMES = 4, SAFR_OPT_COL_PREFETCH = 5, SAFR_OPT_OUT_FRAMES = 6,
        SAFR_OPT_COL_TOGETHER = 7, SAFR_OPT_CHECK_FINITE = 8, SAFR_OPT_DEADLINE_US = 9,
-       SAFR_OPT_COL_MFMA = 10, SAFR_OPT_SEQ_FRAMES = 11 };
+       SAFR_OPT_COL_MFMA = 10, SAFR_OPT_SEQ_FRAMES = 11, SAFR_OPT_FUSED = 12 };
 safr_status safr_set_option(safr_plan* p, int option, int value);
 
 /* Deadline monitor of the closed-loop step (SAFR_OPT_DEADLINE_US): steps counted since the last reset,

@@ -104,6 +104,7 @@ struct safr_plan {
     int col_mfma = 0;               // FP32 column pass with 4 frames: the apply on the matrix cores
     int col_frames_auto = 1;        // column frames per block chosen per launch (until set or autotuned)
     int seq_frames = 0;             // frames per launch sequence (0: from kSequenceBytes), see SAFR_OPT_SEQ_FRAMES
+    int fused = 1;                  // one-kernel step where the shape has one, see SAFR_OPT_FUSED
     int use_graph = 0;
     int deadline_us = 0;            // loop-step deadline (0: off), see SAFR_OPT_DEADLINE_US
     unsigned long long deadline_ticks = 0;
@@ -1467,6 +1468,7 @@ safr_status safr_set_option(safr_plan* p, int option, int value) {
             if (value < 0 || value > kMaxFrames) return fail(SAFR_ERR_ARG, "bad frames per launch sequence");
             p->seq_frames = value;
             return SAFR_OK;
+        case 12: p->fused = value != 0; return SAFR_OK;
         case 10: {
             const int was = p->col_mfma;
             p->col_mfma = value != 0;
@@ -1510,6 +1512,21 @@ safr_status launch_seq(safr_plan* p, int frames, const float* wf, float* out, in
                        hipStream_t s, hipEvent_t* ev, const float* prev, float gain, int stage) {
     const bool do_rows = stage < 0 || stage == 0, do_cols = stage < 0 || stage == 1, do_out = stage < 0 || stage == 2;
     if (ev) HIP_TRY(hipEventRecord(ev[0], s));
+    if (precision == SAFR_FP32 && !prev && p->fused && p->ngroups == 1 &&
+        frame_shape(p->M, p->n, p->gsize[0], p->L, p->mixed ? 1 : 0)) {
+        // the whole step in one kernel (counted as the row stage; the other two stages are empty)
+        FrameArgs fa{};
+        fa.wf = wf;
+        fa.pupil = p->pupil;
+        fa.tw = p->tw;
+        fa.B = p->B32 + p->boff32[0];
+        fa.out = out;
+        fa.frames = frames;
+        if (do_rows) HIP_TRY(launch_frame(fa, p->L, s));
+        if (ev)
+            for (int e = 1; e < 4; ++e) HIP_TRY(hipEventRecord(ev[e], s));
+        return SAFR_OK;
+    }
     char* base = reinterpret_cast<char*>(ws);
     float2* R = reinterpret_cast<float2*>(base);
     float2* C = reinterpret_cast<float2*>(base + ws_r(p, frames));

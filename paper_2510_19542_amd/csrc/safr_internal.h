@@ -283,6 +283,20 @@ inline void allow_large_lds(const void* kernel) {
     if (ndone < 64) done[ndone++] = kernel;
 }
 
+// The whole step of one frame per block for the small configured geometry (see k_frame.hip): wavefronts
+// [F][4][33][33], layers [F][L][64][64], B of the one group in the column pass's layout.
+struct FrameArgs {
+    const float* wf;
+    const unsigned char* pupil; // [n][n]
+    const float2* tw;           // (cos, sin)(2 pi e / M), e < M
+    const float2* B;            // [k / 4][l][g][k % 4][j] (FP32, 1/M^2 included)
+    float* out;
+    int frames;
+};
+bool frame_shape(int M, int n, int G, int L, int mode);
+size_t frame_lds_bytes();
+hipError_t launch_frame(const FrameArgs& a, int L, hipStream_t s);
+
 // Launchers (defined in the .hip files); return hipSuccess or the launch error.
 hipError_t launch_rows(int M, const RowArgs& a, int frames, int nchunk, int teams, hipStream_t s);
 hipError_t launch_cols(int M, const ColArgs& a, int frames_together, int frames, hipStream_t s);

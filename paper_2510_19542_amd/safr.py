@@ -24,7 +24,7 @@ SAFR_FILTER_TIKHONOV, SAFR_FILTER_MLP, SAFR_FILTER_TSVD = 0, 1, 2
 SAFR_FP32, SAFR_BF16X3 = 0, 1
 SAFR_OPT_GRAPH, SAFR_OPT_ROW_TEAMS, SAFR_OPT_OUT_ROWS, SAFR_OPT_MFMA_FRAMES, SAFR_OPT_COL_FRAMES = 0, 1, 2, 3, 4
 SAFR_OPT_COL_PREFETCH, SAFR_OPT_OUT_FRAMES, SAFR_OPT_COL_TOGETHER, SAFR_OPT_CHECK_FINITE = 5, 6, 7, 8
-SAFR_OPT_DEADLINE_US, SAFR_OPT_COL_MFMA, SAFR_OPT_SEQ_FRAMES = 9, 10, 11
+SAFR_OPT_DEADLINE_US, SAFR_OPT_COL_MFMA, SAFR_OPT_SEQ_FRAMES, SAFR_OPT_FUSED = 9, 10, 11, 12
 SAFR_MAX_LAYERS = 16
 SAFR_MLP_PARAMS = 8705
 

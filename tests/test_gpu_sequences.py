@@ -150,6 +150,7 @@ def test_stage_timing_and_autotune_over_groups():
     geo = synth.preset("C1")
     F = 20
     plan = S.precompute_geometry(geo)
+    S.safr_set_option(plan, S.SAFR_OPT_FUSED, 0)     # the three passes (the one-kernel step has one stage)
     d = plan.desc
     x = torch.from_numpy(synth.random_wavefronts(geo, F, seed=17)).cuda()
     out = torch.empty((F, d.L, d.M, d.M), dtype=torch.float32, device="cuda")

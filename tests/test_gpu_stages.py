@@ -60,6 +60,7 @@ def test_row_and_column_pass_intermediates(case, teams):
     torch, S = _mods()
     geo = CASES[case]()
     plan = S.precompute_geometry(geo)
+    S.safr_set_option(plan, S.SAFR_OPT_FUSED, 0)     # the three passes, whose intermediates are inspected
     if teams is not None:
         S.safr_set_option(plan, S.SAFR_OPT_ROW_TEAMS, teams)
     ref = O.precompute_geometry(geo)
