@@ -272,7 +272,7 @@ safr_status safr_import_B(safr_plan* p, int group, const double* host, size_t co
  *                        stars, L = 2 or 3) run the whole step of each frame in one block of one kernel,
  *                        its spectra in LDS (default); 0 = the row, column and output passes.  Same
  *                        layers either way.  safr_time_stages then reports the whole step as the row
- *                        stage and zero for the other two; the closed-loop step keeps the three passes. */
+ *                        stage and zero for the other two.  The closed-loop step uses it too. */
 enum { SAFR_OPT_GRAPH = 0, SAFR_OPT_ROW_TEAMS = 1, SAFR_OPT_OUT_ROWS = 2, SAFR_OPT_MFMA_FRAMES = 3,
        SAFR_OPT_COL_FRAMES = 4, SAFR_OPT_COL_PREFETCH = 5, SAFR_OPT_OUT_FRAMES = 6,
        SAFR_OPT_COL_TOGETHER = 7, SAFR_OPT_CHECK_FINITE = 8, SAFR_OPT_DEADLINE_US = 9,

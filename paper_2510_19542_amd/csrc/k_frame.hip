@@ -16,7 +16,8 @@
 //   3. apply b_l = sum_g B[l][g] d_g per frequency, in place (layer l in star slot l);
 //   4. inverse column transforms of the layer columns, in place: C[l][k][p];
 //   5. C2R row transforms (two rows packed per complex FFT), exchanged and staged in the
-//      slots behind the layers and written out as float4 rows.
+//      slots behind the layers and written out as float4 rows (in the closed loop through
+//      the integrator, prev read at the pixel just before it is written).
 // The arithmetic of each step is that of the three-pass path (the same transform
 // routines, separation, apply and packing formulas, in the same order), so both
 // give the same layers.
@@ -174,7 +175,6 @@ __global__ __launch_bounds__(kFThreads) void frame_kernel(FrameArgs a) {
     // 5. C2R rows: task (l, pair q), rows 2q and 2q + 1 packed as Z = A + i B over their Hermitian extensions;
     // the teams' exchange regions are the slots behind the layers' (as many teams as there are such slots)
     constexpr int T5 = (kFG - L) * kFKC < kFTeams ? (kFG - L) * kFKC : kFTeams;
-    float* out = a.out + (size_t)f * L * kFM * kFM;
     float2* xch5 = U + ((size_t)L * kFKC + team) * kFTL;
     for (int task = team; team < T5 && task < L * (kFM / 2); task += T5) {
         const int l = task / (kFM / 2), q = task % (kFM / 2);
@@ -212,8 +212,17 @@ __global__ __launch_bounds__(kFThreads) void frame_kernel(FrameArgs a) {
 #pragma unroll
         for (int i = 0; i < 2 * kFM / 4 / kFT; ++i) {
             const int e = t + kFT * i, r = e / (kFM / 4), c4 = e % (kFM / 4);
-            const float4 v = reinterpret_cast<const float4*>(rows)[e];
-            reinterpret_cast<float4*>(out + ((size_t)l * kFM + 2 * q + r) * kFM)[c4] = v;
+            float4 v = reinterpret_cast<const float4*>(rows)[e];
+            const size_t o4 = (((size_t)f * L + l) * kFM + 2 * q + r) * (kFM / 4) + c4;
+            if (a.prev) {                             // integrator of the closed loop (Alg. 3), as the output pass
+                const float4 pr = reinterpret_cast<const float4*>(a.prev)[o4];
+                const float keep = 1.f - a.gain;
+                v.x = fmaf(a.gain, v.x, keep * pr.x);
+                v.y = fmaf(a.gain, v.y, keep * pr.y);
+                v.z = fmaf(a.gain, v.z, keep * pr.z);
+                v.w = fmaf(a.gain, v.w, keep * pr.w);
+            }
+            reinterpret_cast<float4*>(a.out)[o4] = v;
         }
         team_sync();                                  // the region is the next task's exchange buffer
     }

@@ -1512,7 +1512,7 @@ safr_status launch_seq(safr_plan* p, int frames, const float* wf, float* out, in
                        hipStream_t s, hipEvent_t* ev, const float* prev, float gain, int stage) {
     const bool do_rows = stage < 0 || stage == 0, do_cols = stage < 0 || stage == 1, do_out = stage < 0 || stage == 2;
     if (ev) HIP_TRY(hipEventRecord(ev[0], s));
-    if (precision == SAFR_FP32 && !prev && p->fused && p->ngroups == 1 &&
+    if (precision == SAFR_FP32 && p->fused && p->ngroups == 1 &&
         frame_shape(p->M, p->n, p->gsize[0], p->L, p->mixed ? 1 : 0)) {
         // the whole step in one kernel (counted as the row stage; the other two stages are empty)
         FrameArgs fa{};
@@ -1521,6 +1521,8 @@ safr_status launch_seq(safr_plan* p, int frames, const float* wf, float* out, in
         fa.tw = p->tw;
         fa.B = p->B32 + p->boff32[0];
         fa.out = out;
+        fa.prev = prev;
+        fa.gain = gain;
         fa.frames = frames;
         if (do_rows) HIP_TRY(launch_frame(fa, p->L, s));
         if (ev)

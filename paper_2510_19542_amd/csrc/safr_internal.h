@@ -291,6 +291,8 @@ struct FrameArgs {
     const float2* tw;           // (cos, sin)(2 pi e / M), e < M
     const float2* B;            // [k / 4][l][g][k % 4][j] (FP32, 1/M^2 included)
     float* out;
+    const float* prev;          // integrator (Alg. 3): out = (1 - gain) prev + gain layers; nullptr = plain
+    float gain;
     int frames;
 };
 bool frame_shape(int M, int n, int G, int L, int mode);

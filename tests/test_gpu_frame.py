@@ -93,3 +93,30 @@ def test_one_kernel_step_stage_timing():
     ms = S.safr_time_stages(plan, F, x, out, S.SAFR_FP32, 5)
     S.safr_set_workspace(plan, 0, 0)
     assert ms[0] > 0.0 and ms[1] < 0.2 * ms[0] and ms[2] < 0.2 * ms[0], ms
+
+
+def test_one_kernel_loop_step_equals_three_passes():
+    """The closed-loop step (POLC, reconstruction, integrator in place) with the one-kernel step gives the
+    commands of the three passes bit for bit, at gain 0.5 and at gain 0 (the commands unchanged)."""
+    torch, S = _mods()
+    geo = synth.preset("C1")
+    F = 6
+    plan = S.precompute_geometry(geo)
+    d = plan.desc
+    wf = torch.from_numpy(synth.random_wavefronts(geo, F, seed=12)).cuda()
+    a0 = torch.from_numpy(np.random.default_rng(9).standard_normal((F, d.L, d.M, d.M)).astype(np.float32)).cuda()
+    need = S.safr_workspace_size(plan, F)
+    ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+    S.safr_set_workspace(plan, (ws.data_ptr() + 255) & ~255, need)
+    for gain in (0.5, 0.0):
+        res = []
+        for fused in (1, 0):
+            S.safr_set_option(plan, S.SAFR_OPT_FUSED, fused)
+            a = a0.clone()
+            S.safr_loop_step(plan, F, wf, a, gain, a)
+            torch.cuda.synchronize()
+            res.append(a.cpu().numpy())
+        assert np.array_equal(res[0], res[1]), gain
+        if gain == 0.0:
+            assert np.array_equal(res[0], a0.cpu().numpy())
+    S.safr_set_workspace(plan, 0, 0)
